@@ -1,0 +1,425 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each checks a closed form,
+an invariant, a symmetry, an independent differentiation route (dual numbers,
+finite differences) or a reduction to a textbook operation (the linear
+trilinear projector of absorption-only tomography, Sec. 5.3).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+AO, EA = oracle.AO, oracle.EA
+
+
+def _cube(n, value):
+    return np.full((n, n, n), value, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# geometry (f_camera, Alg. 1; sphere pose, Sec. 5.1)
+# ---------------------------------------------------------------------------
+def test_camera_frame_is_orthonormal_pinhole():
+    for yaw, pitch, dist, fovy, W, H in [(30, 20, 2.5, 60, 64, 64), (200, -55, 3.1, 45, 80, 48)]:
+        f = oracle.camera_from_sphere(yaw, pitch, dist, fovy, W, H)
+        e, F, R, U = f[0:3], f[3:6], f[6:9], f[9:12]
+        assert np.linalg.norm(e) == pytest.approx(dist, rel=1e-14)
+        assert np.allclose(F, -e / dist, atol=1e-14)           # faces the centre
+        sy = math.tan(math.radians(fovy) / 2)
+        sx = sy * W / H
+        assert np.linalg.norm(R) == pytest.approx(sx, rel=1e-13)
+        assert np.linalg.norm(U) == pytest.approx(sy, rel=1e-13)
+        assert abs(R @ F) < 1e-14 and abs(U @ F) < 1e-14 and abs(R @ U) < 1e-14
+        assert R[1] == 0.0                                      # horizon stays level
+        assert U[1] > 0                                         # up is +y
+        # right-handed: right x up points back toward the eye
+        assert np.cross(R / sx, U / sy) @ F == pytest.approx(-1.0, abs=1e-13)
+
+
+def test_camera_jacobian_matches_finite_differences():
+    args = (40.0, 25.0, 2.7, 55.0, 96, 64)
+    J = oracle.camera_jacobian(*args)
+    for p in range(4):
+        a = list(args)
+        h_deg = 1e-5
+        hp = [math.radians(h_deg), math.radians(h_deg), 1e-6, math.radians(h_deg)][p]
+        step = [h_deg, h_deg, 1e-6, h_deg][p]
+        a[p] += step
+        fp = oracle.camera_from_sphere(*a)
+        a[p] -= 2 * step
+        fm = oracle.camera_from_sphere(*a)
+        fd = (fp - fm) / (2 * hp)
+        assert np.allclose(J[p], fd, rtol=1e-7, atol=1e-8), p
+
+
+def test_axis_ray_length_and_sample_count():
+    # eye on +x looking at the origin; centre pixel of an odd image is the axis ray
+    n = 17
+    cam = oracle.camera_from_sphere(0.0, 0.0, 2.5, 60.0, 5, 5)
+    for step in (0.1, 0.3, 0.07):
+        N, xo, om, t0, ratio = oracle.ray(cam, (n, n, n), 5, 5, 2, 2, step)
+        assert np.allclose(om, [-1, 0, 0], atol=1e-15)
+        assert t0 == pytest.approx(1.5, abs=1e-14)             # enters at x = +1
+        assert np.allclose(xo, [1, 0, 0], atol=1e-14)
+        assert ratio == pytest.approx(2.0 / step, rel=1e-14)   # L = 2 exactly
+        assert N == math.ceil(2.0 / step - 1e-12)
+
+
+def _slab_length(e, om, lo, hi):
+    tn, tf = -np.inf, np.inf
+    for a in range(3):
+        if om[a] == 0:
+            if not (lo[a] <= e[a] <= hi[a]):
+                return 0.0, 0.0
+            continue
+        t1, t2 = (lo[a] - e[a]) / om[a], (hi[a] - e[a]) / om[a]
+        tn, tf = max(tn, min(t1, t2)), min(tf, max(t1, t2))
+    t0 = max(tn, 0.0)
+    return (t0, tf - t0) if tf > t0 else (0.0, 0.0)
+
+
+def test_sample_counts_match_independent_box_clip():
+    shape = (20, 33, 27)  # nz, ny, nx -> longest axis y spans [-1, 1]
+    h = 2.0 / 32
+    half = np.array([(27 - 1) * h / 2, (33 - 1) * h / 2, (20 - 1) * h / 2])
+    W, H = 23, 19
+    cam = oracle.camera_from_sphere(70, -30, 2.2, 60, W, H)
+    step = 0.037
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        px, py = int(rng.integers(W)), int(rng.integers(H))
+        u = 2 * (px + 0.5) / W - 1
+        v = 1 - 2 * (py + 0.5) / H
+        w = cam[3:6] + u * cam[6:9] + v * cam[9:12]
+        om = w / np.linalg.norm(w)
+        t0, L = _slab_length(cam[0:3], om, -half, half)
+        N, xo, om2, t0o, ratio = oracle.ray(cam, shape, W, H, px, py, step)
+        if L == 0:
+            assert N == 0
+            continue
+        assert np.allclose(om, om2, atol=1e-15)
+        assert t0o == pytest.approx(t0, abs=1e-13)
+        assert ratio == pytest.approx(L / step, rel=1e-12)
+        if abs(L / step - round(L / step)) > 1e-9:
+            assert N == math.ceil(L / step)
+
+
+def test_missing_rays_are_exact_zeros_and_carry_no_gradient():
+    n, W, H = 8, 24, 24
+    rng = np.random.default_rng(4)
+    V = rng.uniform(0, 1, (n, n, n))
+    tf = synth.random_tf(6, rng, 5.0)
+    cam = oracle.camera_from_sphere(10, 10, 2.5, 90, W, H)   # wide fov: corners miss
+    out = oracle.render(V, tf, cam, W, H, 0.05, EA)
+    miss = out["nsamp"] == 0
+    assert miss.sum() > 20 and (~miss).sum() > 20
+    assert np.all(out["image"][miss] == 0.0) and np.all(out["trans"][miss] == 1.0)
+    g = np.zeros((W * H, 4))
+    g[miss] = rng.normal(size=(miss.sum(), 4))
+    adj = oracle.adjoint(V, tf, cam, W, H, 0.05, EA, g)
+    assert np.all(adj["dV"] == 0) and np.all(adj["dTF"] == 0)
+    assert np.all(adj["dcam"] == 0) and adj["dstep"] == 0
+
+
+def test_rotating_the_volume_rotates_the_image():
+    n, W = 12, 16
+    rng = np.random.default_rng(5)
+    V = rng.uniform(0, 1, (n, n, n))
+    cam = oracle.camera_from_sphere(0.0, 0.0, 2.5, 50, W, W)   # looks along -x
+    base = oracle.render(V, None, cam, W, W, 0.043, AO)["image"].reshape(W, W)
+    # rotate by 90 degrees about the x (view) axis: (z, y) plane of the array
+    Vr = np.rot90(V, k=1, axes=(0, 1)).copy()
+    rot = oracle.render(Vr, None, cam, W, W, 0.043, AO)["image"].reshape(W, W)
+    errs = [np.abs(rot - np.rot90(base, k)).max() for k in (1, 3)]
+    assert min(errs) < 1e-12 and max(errs) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# trilinear interpolation (f_interpolate, Sec. 3.1)
+# ---------------------------------------------------------------------------
+def test_trilinear_reproduces_affine_fields_and_vertices():
+    nz, ny, nx = 5, 9, 7
+    h = 2.0 / 8
+    zs = (np.arange(nz) - (nz - 1) / 2) * h
+    ys = (np.arange(ny) - (ny - 1) / 2) * h
+    xs = (np.arange(nx) - (nx - 1) / 2) * h
+    a, gx, gy, gz = 0.3, 1.7, -0.4, 2.9
+    V = a + gx * xs[None, None, :] + gy * ys[None, :, None] + gz * zs[:, None, None]
+    rng = np.random.default_rng(6)
+    lo = np.array([xs[0], ys[0], zs[0]])
+    hi = np.array([xs[-1], ys[-1], zs[-1]])
+    for _ in range(50):
+        x = rng.uniform(lo, hi)
+        assert oracle.trilinear(V, x) == pytest.approx(a + gx * x[0] + gy * x[1] + gz * x[2],
+                                                       abs=1e-13)
+    # exact vertex values of a random field, including the upper faces
+    R = rng.uniform(0, 1, (nz, ny, nx))
+    for (k, j, i) in [(0, 0, 0), (4, 8, 6), (2, 3, 1), (4, 0, 6)]:
+        x = np.array([xs[i], ys[j], zs[k]])
+        assert oracle.trilinear(R, x) == pytest.approx(R[k, j, i], abs=1e-14)
+    # partition of unity
+    assert oracle.trilinear(np.full((nz, ny, nx), 0.77), rng.uniform(lo, hi)) == \
+        pytest.approx(0.77, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# transfer function (f_TF: R regularly spaced knots, linear in between)
+# ---------------------------------------------------------------------------
+def test_tf_knots_constant_and_ramp():
+    rng = np.random.default_rng(7)
+    R = 9
+    T = rng.uniform(0, 1, (R, 4))
+    for k in range(R):
+        assert np.allclose(oracle.tf_lookup(T, k / (R - 1)), T[k], atol=1e-14)
+    # midpoint between knots is their average
+    assert np.allclose(oracle.tf_lookup(T, 2.5 / (R - 1)), 0.5 * (T[2] + T[3]), atol=1e-14)
+    # clamping to [0, 1]
+    assert np.allclose(oracle.tf_lookup(T, -0.3), T[0]) and np.allclose(oracle.tf_lookup(T, 1.7), T[-1])
+    const = np.tile([0.2, 0.4, 0.6, 3.0], (R, 1))
+    for d in rng.uniform(-0.5, 1.5, 20):
+        assert np.allclose(oracle.tf_lookup(const, d), const[0], atol=1e-15)
+    ramp = np.tile((np.arange(R) / (R - 1))[:, None], (1, 4))
+    for d in rng.uniform(-0.5, 1.5, 20):
+        assert oracle.tf_lookup(ramp, d)[3] == pytest.approx(min(max(d, 0.0), 1.0), abs=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Beer-Lambert closed forms on homogeneous slabs (Sec. 3.1, eq. integral2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("step", [0.05, 0.11, 0.3])
+def test_absorption_only_constant_density_closed_form(step):
+    n, W = 9, 7
+    d0 = 0.83
+    cam = oracle.camera_from_sphere(23, 17, 2.6, 40, W, W)
+    out = oracle.render(_cube(n, d0), None, cam, W, W, step, AO)
+    hit = out["nsamp"] > 0
+    assert hit.sum() > 10
+    N = out["nsamp"][hit]
+    expect = 1 - np.exp(-N * step * d0)
+    assert np.allclose(out["image"][hit, 0], expect, rtol=0, atol=1e-14)
+    # continuum limit of eq. (integral2): |alpha - (1 - e^{-L d})| <= dt*d*e^{-L d}
+    L = out["ratio"][hit] * step
+    assert np.all(np.abs(out["image"][hit, 0] - (1 - np.exp(-L * d0))) <=
+                  step * d0 * np.exp(-L * d0) + 1e-15)
+
+
+def test_emission_absorption_constant_tf_closed_form():
+    n, W, step = 7, 9, 0.07
+    rgb, tau = np.array([0.3, 0.5, 0.9]), 2.2
+    tf = np.tile(np.r_[rgb, tau], (5, 1))
+    rng = np.random.default_rng(8)
+    V = rng.uniform(-0.2, 1.2, (n, n, n))     # any density: the TF is constant
+    cam = oracle.camera_from_sphere(120, -35, 2.4, 50, W, W)
+    out = oracle.render(V, tf, cam, W, W, step, EA)
+    hit = out["nsamp"] > 0
+    a = 1 - np.exp(-out["nsamp"][hit] * step * tau)
+    assert np.allclose(out["image"][hit, 3], a, atol=1e-14)
+    assert np.allclose(out["image"][hit, :3], a[:, None] * rgb[None, :], atol=1e-14)
+
+
+def test_linear_ramp_density_arithmetic_series():
+    n, W = 33, 5
+    h = 2.0 / (n - 1)
+    xs = (np.arange(n) - (n - 1) / 2) * h
+    a, b = 0.6, 0.25
+    V = np.broadcast_to(a + b * xs[None, None, :], (n, n, n)).copy()
+    cam = oracle.camera_from_sphere(0.0, 0.0, 2.5, 30, W, W)     # axis ray along -x
+    for step in (0.013, 0.1, 0.17):
+        out = oracle.render(V, None, cam, W, W, step, AO, pix=[2 * W + 2])
+        N = int(out["nsamp"][0])
+        # x_i = 1 - i*dt, d_i = a + b*x_i
+        depth = step * (N * (a + b) - b * step * N * (N - 1) / 2)
+        assert out["image"][0, 0] == pytest.approx(1 - math.exp(-depth), abs=1e-14)
+
+
+def test_invariants_alpha_transmittance_colour_bounds():
+    rng = np.random.default_rng(9)
+    n, W = 10, 12
+    V = rng.uniform(0, 1, (n, n, n))
+    tf = synth.random_tf(7, rng, 15.0)
+    cam = oracle.camera_from_sphere(250, 40, 2.5, 60, W, W)
+    out = oracle.render(V, tf, cam, W, W, 0.04, EA)
+    a = out["image"][:, 3]
+    assert np.all(a >= 0) and np.all(a < 1)
+    assert np.allclose(out["trans"], 1 - a, atol=1e-15)
+    assert np.all(out["image"][:, :3] <= a[:, None] * tf[:, :3].max() + 1e-15)
+    for px, py in [(3, 4), (6, 6), (9, 2)]:
+        tr = oracle.trace_ray(V, tf, cam, W, W, px, py, 0.04, EA)
+        assert tr["N"] > 0
+        T = tr["T"]
+        assert T[0] == 1.0 and np.all(np.diff(T) <= 0) and np.all(T > 0)
+        # every sample lies inside the grid box
+        assert np.all(np.abs(tr["x"]) <= 1 + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# adjoint (Alg. 2) against independent routes
+# ---------------------------------------------------------------------------
+def _problem(model, seed=11, n=(6, 7, 5), W=9, H=8, R=5):
+    rng = np.random.default_rng(seed)
+    V = rng.uniform(0, 1, n)
+    tf = synth.random_tf(R, rng, 8.0).astype(np.float64) if model == EA else None
+    cam = oracle.camera_from_sphere(37, 25, 2.3, 50, W, H)
+    C = 4 if model == EA else 1
+    g = rng.normal(size=(W * H, C))
+    return rng, V, tf, cam, W, H, 0.13, g
+
+
+@pytest.mark.parametrize("model", [AO, EA])
+def test_adjoint_variants_agree_with_stored_tape(model):
+    rng, V, tf, cam, W, H, step, g = _problem(model)
+    ref = oracle.adjoint(V, tf, cam, W, H, step, model, g, variant=oracle.TAPE)
+    for var in (oracle.INV_T, oracle.INV_ALPHA, oracle.CHECKPOINT, oracle.RESIDUAL):
+        got = oracle.adjoint(V, tf, cam, W, H, step, model, g, variant=var)
+        for k in ("dV", "dTF", "dcam"):
+            if ref[k] is None:
+                continue
+            scale = np.abs(ref[k]).max()
+            assert np.abs(got[k] - ref[k]).max() <= 1e-12 * scale, (var, k)
+        assert got["dstep"] == pytest.approx(ref["dstep"], rel=1e-12)
+
+
+@pytest.mark.parametrize("model", [AO, EA])
+def test_adjoint_equals_forward_mode_dual_numbers(model):
+    # Sec. 5.1: adjoint and forward differentiation give the same gradients
+    rng, V, tf, cam, W, H, step, g = _problem(model, seed=12)
+    adj = oracle.adjoint(V, tf, cam, W, H, step, model, g)
+    # random joint direction
+    Vd = rng.normal(size=V.shape)
+    tfd = rng.normal(size=tf.shape) if model == EA else None
+    cd = rng.normal(size=12)
+    sd = float(rng.normal())
+    dual = oracle.render_dual(V, tf, cam, W, H, step, model, Vd, tfd, cd, sd)
+    lhs = float((g * dual["image_dot"]).sum())
+    rhs = float((adj["dV"] * Vd).sum() + (adj["dcam"] * cd).sum() + adj["dstep"] * sd)
+    if model == EA:
+        rhs += float((adj["dTF"] * tfd).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+    # each camera component and the step individually
+    for k in range(12):
+        e = np.zeros(12); e[k] = 1
+        dk = oracle.render_dual(V, tf, cam, W, H, step, model, cam_dir=e)
+        assert float((g * dk["image_dot"]).sum()) == pytest.approx(adj["dcam"][k], rel=1e-10, abs=1e-12)
+    ds = oracle.render_dual(V, tf, cam, W, H, step, model, step_dir=1.0)
+    assert float((g * ds["image_dot"]).sum()) == pytest.approx(adj["dstep"], rel=1e-11)
+    if model == EA:
+        for j in range(tf.shape[0]):
+            for c in range(4):
+                e = np.zeros_like(tf); e[j, c] = 1
+                dk = oracle.render_dual(V, tf, cam, W, H, step, model, tf_dir=e)
+                assert float((g * dk["image_dot"]).sum()) == pytest.approx(
+                    adj["dTF"][j, c], rel=1e-10, abs=1e-12)
+
+
+def test_adjoint_equals_dual_numbers_per_voxel_on_tiny_grid():
+    rng = np.random.default_rng(13)
+    V = rng.uniform(0, 1, (4, 4, 4))
+    tf = synth.random_tf(4, rng, 6.0).astype(np.float64)
+    W = H = 6
+    cam = oracle.camera_from_sphere(-50, 33, 2.2, 60, W, H)
+    g = rng.normal(size=(W * H, 4))
+    adj = oracle.adjoint(V, tf, cam, W, H, 0.09, EA, g)
+    for idx in np.ndindex(V.shape):
+        e = np.zeros_like(V); e[idx] = 1
+        dk = oracle.render_dual(V, tf, cam, W, H, 0.09, EA, V_dir=e)
+        assert float((g * dk["image_dot"]).sum()) == pytest.approx(adj["dV"][idx], rel=1e-10, abs=1e-13)
+
+
+@pytest.mark.parametrize("model", [AO, EA])
+def test_adjoint_matches_central_finite_differences(model):
+    rng, V, tf, cam, W, H, step, g = _problem(model, seed=14)
+    adj = oracle.adjoint(V, tf, cam, W, H, step, model, g)
+
+    def loss(Vx, tfx, camx, sx):
+        return float((g * oracle.render(Vx, tfx, camx, W, H, sx, model)["image"]).sum())
+
+    for _ in range(3):
+        Vd = rng.normal(size=V.shape)
+        tfd = rng.normal(size=tf.shape) if model == EA else np.zeros(1)
+        cd = rng.normal(size=12)
+        sd = float(rng.normal())
+        eps = 1e-6
+        tp = tf + eps * tfd if model == EA else None
+        tm = tf - eps * tfd if model == EA else None
+        fd = (loss(V + eps * Vd, tp, cam + eps * cd, step + eps * sd) -
+              loss(V - eps * Vd, tm, cam - eps * cd, step - eps * sd)) / (2 * eps)
+        an = float((adj["dV"] * Vd).sum() + (adj["dcam"] * cd).sum() + adj["dstep"] * sd)
+        if model == EA:
+            an += float((adj["dTF"] * tfd).sum())
+        assert fd == pytest.approx(an, rel=1e-6)
+
+
+def test_slab_closed_form_gradients():
+    # constant density: grad d = 0, so the step derivative is the Beer-Lambert
+    # term alone: d alpha / d dt = N d e^{-N dt d}; voxel gradients sum to
+    # N dt e^{-N dt d} (trilinear weights sum to one).
+    n, W, d0, step = 9, 5, 0.7, 0.09
+    V = _cube(n, d0)
+    cam = oracle.camera_from_sphere(31, 12, 2.5, 30, W, W)
+    pix = [2 * W + 2]
+    out = oracle.render(V, None, cam, W, W, step, AO, pix=pix)
+    N = int(out["nsamp"][0])
+    adj = oracle.adjoint(V, None, cam, W, W, step, AO, np.ones((1, 1)), pix=pix)
+    ex = math.exp(-N * step * d0)
+    assert adj["dstep"] == pytest.approx(N * d0 * ex, rel=1e-12)
+    assert adj["dV"].sum() == pytest.approx(N * step * ex, rel=1e-12)
+    assert np.all(adj["dV"] >= 0)
+    # EA with a density sitting inside one TF segment: only that segment's two
+    # knots receive gradient, split (1-phi, phi)
+    R = 6
+    dseg = 0.5 / (R - 1) + 2.0 / (R - 1)          # phi = 0.5 in segment 2
+    rng = np.random.default_rng(15)
+    tf = synth.random_tf(R, rng, 4.0).astype(np.float64)
+    out = oracle.render(_cube(n, dseg), tf, cam, W, W, step, EA, pix=pix)
+    gch = np.array([[0.3, -0.2, 0.5, 0.7]])
+    adj = oracle.adjoint(_cube(n, dseg), tf, cam, W, W, step, EA, gch, pix=pix)
+    nz = np.nonzero(np.abs(adj["dTF"]).sum(1))[0]
+    assert list(nz) == [2, 3]
+    assert np.allclose(adj["dTF"][2], adj["dTF"][3], rtol=1e-12)
+
+
+def test_absorption_only_is_a_linear_projector_dot_product():
+    # Sec. 5.3: absorption-only rendering is linear tomography.  Optical depth
+    # -log(1 - alpha) = dt * P_w V is linear in V, and the adjoint at V = 0
+    # (T_N = 1) must be the transpose: <P_w V', W> = <V', P_w^T W>.
+    rng = np.random.default_rng(16)
+    n = (7, 6, 8)
+    W_, H_ = 11, 10
+    cam = oracle.camera_from_sphere(144, -21, 2.4, 55, W_, H_)
+    step = 0.061
+    Vp = rng.uniform(0, 1, n)
+    Wt = rng.normal(size=(W_ * H_, 1))
+    depth = -np.log1p(-oracle.render(Vp, None, cam, W_, H_, step, AO)["image"])
+    adj0 = oracle.adjoint(np.zeros(n), None, cam, W_, H_, step, AO, Wt)
+    assert float((depth * Wt).sum()) == pytest.approx(float((Vp * adj0["dV"]).sum()), rel=1e-12)
+    # at any V the gradient is the backprojection of (g * T_N) (footnote form)
+    V = rng.uniform(0, 1, n)
+    out = oracle.render(V, None, cam, W_, H_, step, AO)
+    adjV = oracle.adjoint(V, None, cam, W_, H_, step, AO, Wt)
+    adjB = oracle.adjoint(np.zeros(n), None, cam, W_, H_, step, AO, Wt * out["trans"][:, None])
+    assert np.allclose(adjV["dV"], adjB["dV"], rtol=1e-12, atol=1e-14)
+
+
+def test_alpha_form_inversion_degrades_when_nearly_opaque():
+    # Sec. 4.4: inversion needs alpha < 1.  With a huge optical depth the
+    # paper's alpha-form loses T^(i) to cancellation while the stored tape and
+    # segment checkpointing stay exact.
+    n, W, step = 9, 5, 0.05
+    V = _cube(n, 60.0)                           # optical depth ~ 120 through the grid
+    cam = oracle.camera_from_sphere(0, 0, 2.5, 20, W, W)
+    pix = [2 * W + 2]
+    g = np.ones((1, 1))
+    ref = oracle.adjoint(V, None, cam, W, W, step, AO, g, variant=oracle.TAPE, pix=pix)
+    ck = oracle.adjoint(V, None, cam, W, W, step, AO, g, variant=oracle.CHECKPOINT, pix=pix)
+    al = oracle.adjoint(V, None, cam, W, W, step, AO, g, variant=oracle.INV_ALPHA, pix=pix)
+    assert np.array_equal(ck["dV"], ref["dV"])
+    scale = np.abs(ref["dV"]).max()
+    assert scale > 0
+    assert np.abs(al["dV"] - ref["dV"]).max() > 0.5 * scale
+    # the T-form inversion stays accurate while T_N is representable
+    it = oracle.adjoint(V, None, cam, W, W, step, AO, g, variant=oracle.INV_T, pix=pix)
+    assert np.abs(it["dV"] - ref["dV"]).max() <= 1e-10 * scale
