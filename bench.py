@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable DVR hot path on one MI355X.
+
+Workload (absorption-only tomography, Sec. 5.3 shapes): a 256^3 grid stored as
+bf16 (float32 master), 64 views on a Fibonacci sphere at 512x512, step 0.2
+voxel, loss L2 against target images rendered once from a seeded
+ground-truth grid of ellipsoids.  One step = refresh the bf16 storage copy of
+the master grid + one fused forward -> L2 gradient -> adjoint pass over all 64
+views in a single launch (replayed from a HIP graph).
+
+Printed (one JSON line): fwd+adjoint ray-samples/s, the roofline of the fused
+kernel (algorithmic bytes per launch / its event-timed duration), the FP64
+oracle timed on the host on a bounded pixel sample, and the speedup over the
+plain per-view float32 path (one launch per view, direct global gathers and
+atomics).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_BF16 = 64      # per sample pair: 8 gathers x 2 B (fwd) + 8 x 2 B (adj) + 8 x 4 B scatter
+ALG_BYTES_F32 = 96
+KERNEL_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_kernels.hip",
+                  "paper_2107_12672_amd/csrc/ddvr_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3_fused.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(work, n_views_max, budget_s=12.0):
+    """FP64 oracle (forward + stored-tape adjoint) on every 8th row and column
+    of successive views until the time budget is spent."""
+    import numpy as np
+    import oracle
+    import synth
+    oracle.build(force=False)
+    V = np.zeros(work.volume.shape, np.float64)
+    W = H = work.views[0].width
+    pix = np.array([y * W + x for y in range(0, H, 8) for x in range(0, W, 8)], np.int32)
+    rng = synth.rng_for(3, 7)
+    samples = 0
+    views = 0
+    t0 = time.perf_counter()
+    for v in work.views[:n_views_max]:
+        cam = oracle.camera_from_sphere(v.yaw, v.pitch, v.dist, v.fovy, W, H)
+        out = oracle.render(V, None, cam, W, H, work.step_world, oracle.AO, pix=pix)
+        tgt = rng.uniform(0.0, 1.0, size=out["image"].shape)
+        g = 2.0 * (out["image"] - tgt) / (len(work.views) * W * H)
+        oracle.adjoint(V, None, cam, W, H, work.step_world, oracle.AO, g, pix=pix)
+        samples += int(out["nsamp"].sum())
+        views += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": samples / dt, "unit": "ray-samples/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"fp64 forward + stored-tape adjoint, every 8th row and column "
+                      f"({len(pix)} rays/view) of {views} of the {len(work.views)} views, "
+                      f"{samples} samples in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="grid edge")
+    ap.add_argument("--views", type=int, default=64)
+    ap.add_argument("--image", type=int, default=512)
+    ap.add_argument("--step-vox", type=float, default=0.2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-views", type=int, default=0,
+                    help="views of the plain path to time (0 = all)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(views would shard across GPUs with one all-reduce of the gradients; "
+              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2107_12672_amd import ddvr as d
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    work = synth.make_c3(args.n, args.views, args.image, args.step_vox)
+    W = H = args.image
+    nv = len(work.views)
+    step = work.step_world
+    log(f"workload: {args.n}^3 bf16, {nv} views {W}x{H}, step {args.step_vox} vox")
+
+    # ground truth -> target images (input preparation, untimed)
+    gt32 = torch.from_numpy(work.target_volume).to(dev)
+    gt16 = torch.empty_like(gt32, dtype=torch.bfloat16)
+    d.cast_volume(gt32, gt16)
+    cams = [d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                 math.radians(v.fovy), W, H) for v in work.views]
+    targets = torch.empty((nv, H, W), device=dev)
+    tviews = [d.make_view(0, cams[i], step, targets[i]) for i in range(nv)]
+    tb = d.Batch([gt16], None, tviews, d.ABSORPTION)
+    tb.run(d.PASS_FORWARD)
+    torch.cuda.synchronize()
+    tb.close()
+    del gt16
+
+    # reconstruction state: float32 master (zero-initialised), bf16 storage, gradient
+    master = torch.zeros((args.n,) * 3, device=dev)
+    vol16 = torch.empty_like(master, dtype=torch.bfloat16)
+    dV = torch.zeros_like(master)
+    images = torch.empty((nv, H, W), device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    scale = 1.0 / (nv * W * H)
+    views = [d.make_view(0, cams[i], step, images[i], target=targets[i]) for i in range(nv)]
+    batch = d.Batch([vol16], None, views, d.ABSORPTION, d_volumes=[dV])
+    S = batch.sample_count()
+    log(f"samples per step: {S:.4g}")
+
+    stream = torch.cuda.current_stream()
+
+    def one_step(ev=None):
+        d.cast_volume(master, vol16)
+        if ev is not None:
+            ev[0].record(stream)
+        batch.run(d.PASS_FUSED, scale, loss, graph=True)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        one_step(kev[k])
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_step = ms_total / args.steps
+    k_ms = sum(a.elapsed_time(b) for a, b in kev) / args.steps
+    value = S / (ms_step * 1e-3)
+    log(f"step {ms_step:.3f} ms, fused kernel {k_ms:.3f} ms, {value:.4g} ray-samples/s")
+
+    achieved = S * ALG_BYTES_BF16 / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
+                "kernel_ms": round(k_ms, 4), "alg_bytes_per_launch": S * ALG_BYTES_BF16}
+
+    result = {
+        "metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
+        "value": value, "unit": "ray-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"absorption-only tomography: {args.n}^3 grid stored bf16 "
+                               f"(f32 master), {nv} Fibonacci views at {W}x{H}, step "
+                               f"{args.step_vox} voxel, L2 loss, gradient w.r.t. density",
+                   "storage": "bf16", "samples_per_step": S, "views": nv, "image": W,
+                   "grid": args.n, "step_vox": args.step_vox,
+                   "launch": "one fused launch per step, HIP graph replay"},
+        "roofline": roofline,
+    }
+
+    if not args.no_plain:
+        # the plain per-view float32 path: one launch per view, global atomics
+        pv = nv if args.plain_views <= 0 else min(nv, args.plain_views)
+        dV32 = torch.zeros_like(master)
+        g32 = d.grads_desc(dV32)
+        img1 = torch.empty((H, W), device=dev)
+
+        def plain_step(nviews):
+            for i in range(nviews):
+                d.render_fused_l2(master, None, cams[i], step, d.ABSORPTION, targets[i], scale,
+                                  img1, None, g32, flags=d.LAUNCH_PLAIN, loss_out=loss)
+
+        plain_step(min(2, pv))
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plain_step(pv)
+        b.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = a.elapsed_time(b) * nv / pv
+        result["plain_fp32_per_view"] = {
+            "ms_per_step": plain_ms, "views_timed": pv,
+            "speedup": plain_ms / ms_step,
+            "path": "float32 grid, one launch per view, direct gathers, global atomics"}
+        log(f"plain per-view fp32: {plain_ms:.1f} ms per step -> speedup {plain_ms / ms_step:.2f}x")
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(work, nv)
+        log(f"cpu baseline: {result['cpu_baseline']}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * ddvr.h -- C ABI of the MI355X (gfx950) differentiable direct volume renderer.
+ *
+ * What is computed (Weiss & Westermann, "DiffDVR", arXiv 2107.12672):
+ *   forward  -- Sec. 4.1, Alg. 1 (Direct Volume Rendering Algorithm): one ray
+ *               per pixel, x_i = x_o + i*dt*omega for i = 0..N-1, trilinear
+ *               density (Sec. 3.1 vertex grid), piecewise-linear transfer
+ *               function with R regularly spaced knots (Sec. 3.1), Beer-Lambert
+ *               opacity alpha_i = 1 - exp(-dt*tau) and front-to-back blending
+ *               (Sec. 3.1; eq. blend-forward, Sec. 4.4).
+ *   adjoint  -- Sec. 4.3, Alg. 2 (Adjoint Code of the DVR Algorithm), run with
+ *               the inversion trick of Sec. 4.4 (eq. inv-blend-forward): the
+ *               ray is re-traversed back to front and the blended state is
+ *               recovered analytically instead of being stored, so memory is
+ *               O(pixels), independent of the number of samples.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the comment says (host).  The caller
+ *     owns all memory; the render calls never allocate.
+ *   - Every call returns an int status (ddvr_status): 0 on success, < 0 on
+ *     error.  Arguments are validated on the host before any launch; on a
+ *     validation error nothing is launched and nothing is written.  No C++
+ *     exception crosses this boundary.  ddvr_last_error() describes the last
+ *     failure of the calling thread.
+ *   - Work is enqueued on the given HIP stream (NULL = the null stream) and
+ *     is asynchronous, except where a (host) output is requested.
+ *   - Gradients ACCUMULATE (+=), as the "+=" of Alg. 2; zero them first.
+ *   - NaN / Inf inside device data are not checked; they propagate.
+ *
+ * Geometry (the paper leaves the camera intrinsics open, Sec. 4.1 / 5.1):
+ *   - volume: scalar densities at the vertices of an nx*ny*nz grid, stored
+ *     [nz][ny][nx] (x fastest).  Isotropic spacing h = 2/(max(n)-1); the grid
+ *     is centred at the origin, so its longest axis spans [-1, 1].
+ *   - camera: pinhole.  Pixel (px, py), py = 0 the top row, has
+ *     u = 2(px+1/2)/W - 1, v = 1 - 2(py+1/2)/H and direction
+ *     omega = normalize(fwd + u*right + v*up); right/up are pre-scaled by
+ *     tan(fovy/2)*W/H and tan(fovy/2).  The ray starts at the box entry point
+ *     x_o = eye + t0*omega (t0 = 0 if the eye is inside the box) and takes
+ *     N = ceil(L/dt) samples, L the chord length inside the box.
+ *   - transfer function (emission-absorption model): table [R][4] of
+ *     (r, g, b, tau), knots at k/(R-1); density clamped to [0,1] first.  The
+ *     emission of a segment is premultiplied, c_i = alpha_i * rgb_i.
+ *   - absorption-only model: tau(d) = d per world unit, no TF, no emission.
+ *   - images: [H][W][4] float32 premultiplied (r, g, b, alpha) for the
+ *     emission-absorption model, [H][W] float32 alpha for absorption-only.
+ *     Background is transparent black; rays that miss the grid give exactly 0.
+ *   - transmittance: [H][W] float32, T_N = 1 - alpha, saved by the forward
+ *     pass for the adjoint (1 - alpha loses T_N in float32 once T_N is tiny).
+ */
+#ifndef DDVR_H
+#define DDVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDVR_ABI_VERSION 1
+
+typedef enum {
+  DDVR_OK = 0,
+  DDVR_ERR_NULL = -1,        /* a required pointer is NULL */
+  DDVR_ERR_SHAPE = -2,       /* a size is out of range (grid < 2, R < 2, W/H <= 0, ...) */
+  DDVR_ERR_DTYPE = -3,       /* unknown storage type */
+  DDVR_ERR_VALUE = -4,       /* a scalar is out of range (step <= 0, non-finite, ...) */
+  DDVR_ERR_HIP = -5,         /* the HIP runtime reported an error (also a pending
+                                asynchronous error of an earlier launch) */
+  DDVR_ERR_UNSUPPORTED = -6, /* valid request this build does not handle */
+  DDVR_ERR_WORKSPACE = -7    /* workspace missing or too small */
+} ddvr_status;
+
+typedef enum { DDVR_F32 = 0, DDVR_F16 = 1, DDVR_BF16 = 2 } ddvr_dtype;
+
+typedef enum { DDVR_ABSORPTION = 0, DDVR_EMISSION_ABSORPTION = 1 } ddvr_model;
+
+/* Adjoint mode (low bits of `flags`).
+ *   AUTO       absorption-only: the inversion of Sec. 4.4 carried out in closed
+ *              form (see render_adjoint); emission-absorption: T-form inversion
+ *              T^(i) = T^(i+1)/e_i, and rays whose saved T_N < 2^-100 (where
+ *              float32 inversion breaks down, Sec. 4.4 "alpha < 1") are handed
+ *              to the segment-checkpoint fallback.
+ *   INVERT_T   T-form inversion for every ray, no fallback.
+ *   INVERT_ALPHA  the paper's alpha-form, eq. (inv-blend-forward).  Its
+ *              recovered T^(i) carries a relative error ~ 2^-24 / T_N, so rays
+ *              with T_N < 2^-10 take the checkpoint fallback (needs workspace).
+ *   CHECKPOINT segment checkpointing for every ray (the stored-state
+ *              alternative; needs workspace). */
+#define DDVR_ADJ_AUTO 0
+#define DDVR_ADJ_INVERT_T 1
+#define DDVR_ADJ_INVERT_ALPHA 2
+#define DDVR_ADJ_CHECKPOINT 3
+#define DDVR_ADJ_MODE_MASK 0xF
+/* Launch strategy (bit flags, OR-ed into `flags`).
+ *   PLAIN      one thread per ray with direct global gathers and global atomics
+ *              for the density gradient (no LDS staging).  Same results up to
+ *              float rounding; kept as the straightforward baseline. */
+#define DDVR_LAUNCH_PLAIN 0x10
+
+/* A scalar grid: data -> [nz][ny][nx] values of `dtype` (device). */
+typedef struct {
+  const void* data;
+  int32_t dtype;   /* ddvr_dtype */
+  int32_t nx, ny, nz;
+} ddvr_volume;
+
+/* Transfer function: rgba_tau -> [R][4] float32 (device), R >= 2.
+ * Ignored (may be {NULL, 0}) for the absorption-only model. */
+typedef struct {
+  const float* rgba_tau;
+  int32_t R;
+} ddvr_tf;
+
+/* Camera frame (host struct): eye, unit forward, right*tan(fovy/2)*W/H,
+ * up*tan(fovy/2), image size. */
+typedef struct {
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t width, height;
+} ddvr_camera;
+
+/* Gradient outputs (device pointers, each may be NULL = not requested).
+ *   d_volume  [nz][ny][nx] float32 (the gradient of the float32 master copy,
+ *             also when the grid is stored as f16/bf16)
+ *   d_tf      [R][4] float32
+ *   d_camera  [12] float32 in the order eye, fwd, right, up of ddvr_camera
+ *   d_step    [1] float32 (per world unit) */
+typedef struct {
+  float* d_volume;
+  float* d_tf;
+  float* d_camera;
+  float* d_step;
+} ddvr_grads;
+
+/* Version of this ABI (DDVR_ABI_VERSION). */
+int ddvr_abi_version(void);
+
+/* Description of the last error of the calling thread (static storage, valid
+ * until the next call on this thread).  Never NULL. */
+const char* ddvr_last_error(void);
+
+/* Camera on a sphere around the grid centre, facing it (Sec. 5.1: longitude /
+ * latitude parameterisation), up = +y.  Angles in RADIANS:
+ * eye = dist*(cos(pitch)cos(yaw), sin(pitch), cos(pitch)sin(yaw)).
+ * out (host).  |pitch| must be < pi/2 (the frame is degenerate at the poles). */
+int ddvr_camera_from_sphere(float yaw, float pitch, float dist, float fovy, int32_t width,
+                            int32_t height, ddvr_camera* out);
+
+/* Chain rule from a frame gradient d_frame[12] (host, layout of
+ * ddvr_grads.d_camera) to d_sphere[4] (host) = d/d(yaw, pitch, dist, fovy). */
+int ddvr_camera_grad_to_sphere(float yaw, float pitch, float dist, float fovy, int32_t width,
+                               int32_t height, const float* d_frame, float* d_sphere);
+
+/* Storage copy of a float32 master grid (form of the grid the kernels read):
+ * dst[i] = round_to_nearest_even(src[i]) in `dtype` (f32: plain copy), for
+ * i < n.  src, dst device; may not overlap. */
+int ddvr_cast_volume(const float* src, void* dst, int32_t dtype, int64_t n, void* hip_stream);
+
+/* Forward pass (Alg. 1) of one view.
+ *   step_world  dt > 0 in world units (a step of s voxels is s*h).
+ *   image       [H][W][4] (EA) or [H][W] (AO) float32, written.
+ *   transmittance [H][W] float32, written; may be NULL (the adjoint needs it).
+ *   flags       0 or DDVR_LAUNCH_PLAIN. */
+int ddvr_render_forward(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, float* image, float* transmittance,
+                        int32_t flags, void* hip_stream);
+
+/* Bytes of workspace render_adjoint / render_fused_l2 need for `flags`
+ * (0 unless a checkpoint path can run: emission-absorption AUTO,
+ * INVERT_ALPHA and CHECKPOINT).  The size depends on the pixel count and on
+ * sqrt(samples per ray), not on the samples themselves.  bytes (host). */
+int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, float step_world,
+                                int32_t model, int32_t flags, size_t* bytes);
+
+/* Adjoint pass (Alg. 2 with the inversion trick, Sec. 4.4) of one view.
+ *   image, transmittance  the forward outputs for the same inputs.
+ *   d_image     dLoss/dimage, layout of `image`.
+ *   grads       (host struct) gradients to accumulate into.
+ *   flags       adjoint mode | launch flags.
+ *   workspace   device scratch of >= ddvr_adjoint_workspace_size bytes (may be
+ *               NULL when that size is 0).
+ *   n_fallback_rays (host, may be NULL): if given, the call synchronises the
+ *               stream and returns how many rays took the checkpoint path. */
+int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, const float* image,
+                        const float* transmittance, const float* d_image,
+                        const ddvr_grads* grads, int32_t flags, void* workspace,
+                        size_t workspace_bytes, int32_t* n_fallback_rays, void* hip_stream);
+
+/* Fused forward -> L2 loss gradient -> adjoint of one view, one launch
+ * (pixel-local loss only).  loss = loss_scale * sum((image - target)^2).
+ *   target      layout of `image`.
+ *   image, transmittance  written as by render_forward (transmittance may be
+ *               NULL unless the fallback path is possible).
+ *   loss_out    (device, may be NULL) one double, += loss. */
+int ddvr_render_fused_l2(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                         float step_world, int32_t model, const float* target, float loss_scale,
+                         float* image, float* transmittance, const ddvr_grads* grads,
+                         int32_t flags, void* workspace, size_t workspace_bytes,
+                         int32_t* n_fallback_rays, double* loss_out, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many views of one or several grids in ONE launch.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t volume;          /* index into the batch's volume array */
+  int32_t tf;              /* index into the batch's TF array (-1 for AO) */
+  ddvr_camera cam;
+  float step_world;
+  float* image;            /* [H][W][C] */
+  float* transmittance;    /* [H][W] or NULL */
+  const float* d_image;    /* adjoint input, or NULL */
+  const float* target;     /* fused-L2 target, or NULL */
+  float* d_camera;         /* [12] or NULL */
+  float* d_step;           /* [1] or NULL */
+} ddvr_view;
+
+typedef struct ddvr_batch ddvr_batch;
+
+/* Build a batch (host-side planning + a small device buffer of view
+ * descriptors and a cost-ordered tile queue, owned by the batch).
+ *   d_volumes[nvol], d_tfs[ntf]: per-volume / per-TF gradient outputs (device,
+ *   entries or the arrays themselves may be NULL).
+ *   The pointers inside are captured; rebuild the batch if they change. */
+int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs, int32_t ntf,
+                      const ddvr_view* views, int32_t nview, int32_t model, int32_t flags,
+                      float* const* d_volumes, float* const* d_tfs, void* hip_stream,
+                      ddvr_batch** out);
+void ddvr_batch_destroy(ddvr_batch* b);
+/* pass: 0 = forward, 1 = adjoint (views need d_image), 2 = fused forward+L2+adjoint
+ * (views need target). loss_out as in render_fused_l2.  Workspace as for a
+ * single view, sized by ddvr_batch_workspace_size. */
+int ddvr_batch_workspace_size(const ddvr_batch* b, size_t* bytes);
+int ddvr_batch_run(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
+                   void* workspace, size_t workspace_bytes, void* hip_stream);
+/* Record pass `pass` of the batch into a HIP graph once and replay it on later
+ * calls (the pointers and loss_scale must not change between replays). */
+int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
+                         void* workspace, size_t workspace_bytes, void* hip_stream);
+/* Samples (sum over rays of N) the batch's views take; host output. */
+int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDVR_H */

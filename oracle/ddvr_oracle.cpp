@@ -741,6 +741,44 @@ int oracle_trace_ray(const double* V, int nx, int ny, int nz, const double* tf, 
   return r.N;
 }
 
+// Distance of each ray to the non-differentiable points of Alg. 1 (for the
+// parity harness): face[q] = min over samples and axes of the distance (in
+// voxels) of the sample to an interior cell face (where the trilinear
+// gradient jumps); knot[q] = min over samples of the distance of
+// u = d*(R-1) to a TF knot 0..R-1 (slope change or clamp end), EA only.
+// Rays that miss get 1e30 in both.
+int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int R,
+                 const double* cam, int W, int H, double step, int model,
+                 const int32_t* pix, int64_t npix, double* face, double* knot) {
+  const bool ea = model == 1;
+  if (!V || !cam || !face || !knot || (ea && !tf)) return -1;
+  if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
+  const Grid g = make_grid(nx, ny, nz);
+  const int64_t n = pix ? npix : int64_t(W) * H;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t p = pix ? int64_t(pix[q]) : q;
+    Ray<double> r = make_ray<double>(cam, int(p % W), int(p / W), W, H, g, step);
+    double fmin = 1e30, kmin = 1e30;
+    for (int i = 0; r.hit && i < r.N; ++i) {
+      Sample<double> s = eval_sample(g, V, tf, R, ea, r, step, i);
+      for (int a = 0; a < 3; ++a) {
+        const double qa = (s.x[a] - g.bmin[a]) / g.h;
+        const double k = std::round(qa);
+        if (k >= 1.0 && k <= double(g.n[a] - 2)) fmin = std::min(fmin, std::fabs(qa - k));
+      }
+      if (ea) {
+        const double u = s.d * double(R - 1);
+        const double k = std::round(u);
+        if (k >= 0.0 && k <= double(R - 1)) kmin = std::min(kmin, std::fabs(u - k));
+      }
+    }
+    face[q] = fmin;
+    knot[q] = kmin;
+  }
+  return 0;
+}
+
 int oracle_num_threads(void) { return nthreads_max(); }
 
 }  // extern "C"

@@ -1,0 +1,713 @@
+// Host side of the C ABI declared in include/ddvr.h: argument validation,
+// camera helpers, launch planning (tile grid, slab length, LDS budget),
+// workspace layout of the checkpoint fallback, batches and graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ddvr.h"
+#include "ddvr_internal.h"
+
+using namespace ddvr;
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DDVR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Surface an asynchronous error left by an earlier launch.
+int check_pending() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "pending HIP error");
+  return DDVR_OK;
+}
+
+bool finite3(const float* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+constexpr int kWaves = 4;                 // 16x16 pixel tiles
+constexpr int kTileW = 16, kTileH = 16;
+constexpr int kLdsCap = 4096;             // voxels per LDS brick (x2: values + gradient)
+constexpr int kFallbackSlots = 65536;     // concurrent checkpoint slots
+
+int validate_volume(const ddvr_volume* v) {
+  if (!v) return fail(DDVR_ERR_NULL, "volume descriptor is NULL");
+  if (!v->data) return fail(DDVR_ERR_NULL, "volume data is NULL");
+  if (v->dtype != DDVR_F32 && v->dtype != DDVR_F16 && v->dtype != DDVR_BF16)
+    return fail(DDVR_ERR_DTYPE, "unknown volume dtype %d", v->dtype);
+  if (v->nx < 2 || v->ny < 2 || v->nz < 2)
+    return fail(DDVR_ERR_SHAPE, "grid %dx%dx%d: every size must be >= 2", v->nx, v->ny, v->nz);
+  if ((int64_t)v->nx * v->ny * v->nz > (int64_t)1 << 34)
+    return fail(DDVR_ERR_SHAPE, "grid too large");
+  return DDVR_OK;
+}
+
+int validate_tf(const ddvr_tf* tf, int model) {
+  if (model == DDVR_ABSORPTION) return DDVR_OK;
+  if (!tf) return fail(DDVR_ERR_NULL, "transfer function descriptor is NULL");
+  if (!tf->rgba_tau) return fail(DDVR_ERR_NULL, "transfer function table is NULL");
+  if (tf->R < 2 || tf->R > 4096) return fail(DDVR_ERR_SHAPE, "TF size R=%d not in [2, 4096]", tf->R);
+  return DDVR_OK;
+}
+
+int validate_model(int model) {
+  if (model != DDVR_ABSORPTION && model != DDVR_EMISSION_ABSORPTION)
+    return fail(DDVR_ERR_VALUE, "unknown model %d", model);
+  return DDVR_OK;
+}
+
+int validate_camera(const ddvr_camera* c) {
+  if (!c) return fail(DDVR_ERR_NULL, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(DDVR_ERR_SHAPE, "image %dx%d", c->width, c->height);
+  if ((int64_t)c->width * c->height > ((int64_t)1 << 31) - 1)
+    return fail(DDVR_ERR_SHAPE, "image too large");
+  if (!finite3(c->eye) || !finite3(c->fwd) || !finite3(c->right) || !finite3(c->up))
+    return fail(DDVR_ERR_VALUE, "camera frame is not finite");
+  return DDVR_OK;
+}
+
+float half_diag(const ddvr_volume* v) {
+  const int nmax = std::max(v->nx, std::max(v->ny, v->nz));
+  const double h = 2.0 / (nmax - 1);
+  const double ex = (v->nx - 1) * h, ey = (v->ny - 1) * h, ez = (v->nz - 1) * h;
+  return (float)(0.5 * std::sqrt(ex * ex + ey * ey + ez * ez));
+}
+
+int64_t max_samples(const ddvr_volume* v, float step) {
+  return (int64_t)std::ceil(2.0 * half_diag(v) / step) + 1;
+}
+
+int validate_step(const ddvr_volume* v, float step) {
+  if (!std::isfinite(step) || !(step > 0.0f)) return fail(DDVR_ERR_VALUE, "step %g must be > 0", step);
+  if (max_samples(v, step) > kMaxSamples)
+    return fail(DDVR_ERR_VALUE, "step %g gives more than %d samples per ray", step, kMaxSamples);
+  return DDVR_OK;
+}
+
+// Samples per slab: the longest run whose estimated brick fits the LDS budget.
+int choose_slab_k(const ddvr_volume* v, const ddvr_camera* c, float step, int cap) {
+  if (cap <= 0) return kMaxSamples + 1;
+  const int nmax = std::max(v->nx, std::max(v->ny, v->nz));
+  const double inv_h = 0.5 * (nmax - 1);
+  const double ry = std::sqrt((double)c->up[0] * c->up[0] + (double)c->up[1] * c->up[1] +
+                              (double)c->up[2] * c->up[2]);
+  const double rx = std::sqrt((double)c->right[0] * c->right[0] +
+                              (double)c->right[1] * c->right[1] +
+                              (double)c->right[2] * c->right[2]);
+  const double pitch = std::max(2.0 * ry / c->height, 2.0 * rx / c->width);
+  const double dist = std::sqrt((double)c->eye[0] * c->eye[0] + (double)c->eye[1] * c->eye[1] +
+                                (double)c->eye[2] * c->eye[2]) + half_diag(v);
+  const double wv = std::max(kTileW, kTileH) * pitch * dist * inv_h + 2.0;
+  double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
+  const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (double& x : f) x /= fl;
+  auto box = [&](double l) {
+    double b = 1.0;
+    for (int a = 0; a < 3; ++a)
+      b *= std::fabs(f[a]) * l + wv * std::sqrt(std::max(0.0, 1.0 - f[a] * f[a])) + 2.0;
+    return b;
+  };
+  const double budget = 0.85 * cap;
+  if (box(0.0) > budget) return 8;   // slabs will mostly go the direct route
+  double lo = 0.0, hi = 4096.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (box(mid) <= budget ? lo : hi) = mid;
+  }
+  const double k = lo / (step * inv_h);
+  return (int)std::min(4096.0, std::max(4.0, std::floor(k)));
+}
+
+void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_camera* c,
+               float step, int model, int cap) {
+  std::memset(&d, 0, sizeof(d));
+  for (int a = 0; a < 3; ++a) {
+    d.eye[a] = c->eye[a]; d.fwd[a] = c->fwd[a]; d.right[a] = c->right[a]; d.up[a] = c->up[a];
+  }
+  d.W = c->width;
+  d.H = c->height;
+  d.step = step;
+  d.vol = v->data;
+  d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
+  const int nmax = std::max(v->nx, std::max(v->ny, v->nz));
+  const double h = 2.0 / (nmax - 1);
+  d.h = (float)h;
+  d.inv_h = (float)(0.5 * (nmax - 1));
+  const int n[3] = {v->nx, v->ny, v->nz};
+  for (int a = 0; a < 3; ++a) {
+    d.bmin[a] = (float)(-0.5 * (n[a] - 1) * h);
+    d.bmax[a] = (float)(0.5 * (n[a] - 1) * h);
+  }
+  if (model == DDVR_EMISSION_ABSORPTION) { d.tf = tf->rgba_tau; d.R = tf->R; }
+  d.tiles_x = (c->width + kTileW - 1) / kTileW;
+  d.tiles_y = (c->height + kTileH - 1) / kTileH;
+  d.slab_k = choose_slab_k(v, c, step, cap);
+}
+
+size_t lds_bytes(int cap, int model, int R) {
+  const size_t tf = model == DDVR_EMISSION_ABSORPTION ? (size_t)R * 8 : 0;
+  return ((size_t)2 * cap + tf) * sizeof(float) + 64 * sizeof(int);
+}
+
+int grad_mask_of(const ddvr_grads* g) {
+  if (!g) return 0;
+  return (g->d_volume ? GRAD_V : 0) | (g->d_tf ? GRAD_TF : 0) | (g->d_camera ? GRAD_CAM : 0) |
+         (g->d_step ? GRAD_STEP : 0);
+}
+
+// Workspace of the checkpoint fallback:
+//   [0, 256)                 queue length (int32)
+//   [256, 256 + 8*cap)       queue of (view << 32 | pixel)
+//   then slots*slot_floats   per-slot checkpoint storage
+struct FbLayout {
+  int64_t cap = 0;
+  int slots = 0, slot_floats = 0;
+  size_t bytes = 0;
+};
+
+FbLayout fallback_layout(int64_t rays, int64_t nmax_samples) {
+  FbLayout L;
+  L.cap = rays;
+  int K = (int)std::ceil(std::sqrt((double)nmax_samples));
+  while ((int64_t)K * K < nmax_samples) ++K;
+  // a ray of N <= nmax_samples samples uses ceil(N/K) + K + 1 <= 2K + 1 floats
+  L.slot_floats = ((2 * K + 4 + 63) / 64) * 64;
+  L.slots = (int)std::min<int64_t>(kFallbackSlots, std::max<int64_t>(rays, 1));
+  L.bytes = 256 + (size_t)8 * rays;
+  L.bytes = (L.bytes + 255) / 256 * 256;
+  L.bytes += (size_t)L.slots * L.slot_floats * sizeof(float);
+  return L;
+}
+
+bool needs_fallback(int model, int flags) {
+  const int mode = flags & DDVR_ADJ_MODE_MASK;
+  return mode == DDVR_ADJ_CHECKPOINT || mode == DDVR_ADJ_INVERT_ALPHA ||
+         (model == DDVR_EMISSION_ABSORPTION && mode == DDVR_ADJ_AUTO);
+}
+
+int validate_flags(int flags) {
+  const int mode = flags & DDVR_ADJ_MODE_MASK;
+  if (mode > DDVR_ADJ_CHECKPOINT) return fail(DDVR_ERR_VALUE, "unknown adjoint mode %d", mode);
+  if (flags & ~(DDVR_ADJ_MODE_MASK | DDVR_LAUNCH_PLAIN))
+    return fail(DDVR_ERR_VALUE, "unknown flag bits 0x%x", flags);
+  return DDVR_OK;
+}
+
+void attach_fallback(LaunchParams& p, const FbLayout& L, void* ws, int flags) {
+  char* b = static_cast<char*>(ws);
+  p.fb_count = reinterpret_cast<int32_t*>(b);
+  p.fb_list = reinterpret_cast<int64_t*>(b + 256);
+  p.fb_cap = L.cap;
+  p.fb_tmin = (flags & DDVR_ADJ_MODE_MASK) == DDVR_ADJ_INVERT_ALPHA ? kFallbackTminAlpha
+                                                                     : kFallbackTmin;
+  p.fb_all = (flags & DDVR_ADJ_MODE_MASK) == DDVR_ADJ_CHECKPOINT ? 1 : 0;
+  const size_t off = ((256 + (size_t)8 * L.cap) + 255) / 256 * 256;
+  p.fb_scratch = reinterpret_cast<float*>(b + off);
+  p.fb_slots = L.slots;
+  p.fb_slot_floats = L.slot_floats;
+}
+
+int read_fallback_count(const LaunchParams& p, hipStream_t s, int32_t* out) {
+  if (!out) return DDVR_OK;
+  if (!p.fb_count) { *out = 0; return DDVR_OK; }
+  int32_t n = 0;
+  hipError_t e = hipMemcpyAsync(&n, p.fb_count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading the fallback count");
+  *out = n;
+  return DDVR_OK;
+}
+
+// One view: forward / adjoint / fused.
+int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+               float step, int model, float* image, float* trans, const float* d_image,
+               const float* target, float loss_scale, const ddvr_grads* grads, int flags,
+               void* ws, size_t ws_bytes, int32_t* n_fb, double* loss_out, void* stream) {
+  int rc;
+  if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
+      (rc = validate_camera(cam)) || (rc = validate_step(vol, step)) || (rc = validate_flags(flags)))
+    return rc;
+  if (!image) return fail(DDVR_ERR_NULL, "image is NULL");
+  if (pass == PASS_ADJ) {
+    if (!trans) return fail(DDVR_ERR_NULL, "transmittance is NULL (the adjoint needs T_N)");
+    if (!d_image) return fail(DDVR_ERR_NULL, "d_image is NULL");
+  }
+  if (pass == PASS_FUSED && !target) return fail(DDVR_ERR_NULL, "target is NULL");
+  if (!std::isfinite(loss_scale)) return fail(DDVR_ERR_VALUE, "loss_scale is not finite");
+  const bool fb = pass != PASS_FWD && needs_fallback(model, flags);
+  FbLayout L;
+  if (fb) {
+    if (pass == PASS_FUSED && !trans && (flags & DDVR_ADJ_MODE_MASK) == DDVR_ADJ_AUTO &&
+        model == DDVR_EMISSION_ABSORPTION) {
+      // the fallback kernel recomputes the loss gradient from the written image
+    }
+    L = fallback_layout((int64_t)cam->width * cam->height, max_samples(vol, step));
+    if (!ws || ws_bytes < L.bytes)
+      return fail(DDVR_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.bytes,
+                  ws ? ws_bytes : (size_t)0);
+  }
+  if ((rc = check_pending())) return rc;
+
+  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  LaunchParams p;
+  std::memset(&p, 0, sizeof(p));
+  fill_view(p.one, vol, tf, cam, step, model, cap);
+  p.one.image = image;
+  p.one.trans = trans;
+  p.one.d_image = d_image;
+  p.one.target = target;
+  if (grads) {
+    p.one.dV = grads->d_volume;
+    p.one.dTF = model == DDVR_EMISSION_ABSORPTION ? grads->d_tf : nullptr;
+    p.one.dcam = grads->d_camera;
+    p.one.dstep = grads->d_step;
+  }
+  p.views = nullptr;
+  p.work = nullptr;
+  p.n_items = p.one.tiles_x * p.one.tiles_y;
+  p.flags = flags;
+  p.grad_mask = grad_mask_of(grads);
+  if (model != DDVR_EMISSION_ABSORPTION) p.grad_mask &= ~GRAD_TF;
+  p.lds_cap = cap;
+  p.loss_scale = loss_scale;
+  p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
+  if (fb) attach_fallback(p, L, ws, flags);
+
+  hipError_t e;
+  if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, stream)) != hipSuccess)
+    return hip_fail(e, "zeroing the fallback queue");
+  e = (hipError_t)launch_render(p, pass, model, vol->dtype, kWaves, p.n_items,
+                                lds_bytes(cap, model, p.one.R), stream);
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  if (fb) {
+    e = (hipError_t)launch_fallback(p, model, vol->dtype, pass == PASS_FUSED ? 1 : 0, stream);
+    if (e != hipSuccess) return hip_fail(e, "fallback launch");
+  }
+  if (n_fb) {
+    if (!fb) *n_fb = 0;
+    else if ((rc = read_fallback_count(p, static_cast<hipStream_t>(stream), n_fb))) return rc;
+  }
+  return DDVR_OK;
+}
+
+// ---- tiny forward-mode number for the camera chain rule -------------------
+struct D4 {
+  double v, d[4];
+};
+D4 cst(double v) { D4 r{v, {0, 0, 0, 0}}; return r; }
+D4 var(double v, int k) { D4 r = cst(v); r.d[k] = 1.0; return r; }
+D4 add(D4 a, D4 b) { D4 r{a.v + b.v, {}}; for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+D4 sub(D4 a, D4 b) { D4 r{a.v - b.v, {}}; for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+D4 mul(D4 a, D4 b) {
+  D4 r{a.v * b.v, {}};
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+D4 dvd(D4 a, D4 b) {
+  D4 r{a.v / b.v, {}};
+  for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+D4 fn(double v, double dv, D4 a) { D4 r{v, {}}; for (int k = 0; k < 4; ++k) r.d[k] = dv * a.d[k]; return r; }
+D4 dsin(D4 a) { return fn(std::sin(a.v), std::cos(a.v), a); }
+D4 dcos(D4 a) { return fn(std::cos(a.v), -std::sin(a.v), a); }
+D4 dtan(D4 a) { const double t = std::tan(a.v); return fn(t, 1.0 + t * t, a); }
+D4 dsqrt(D4 a) { const double s = std::sqrt(a.v); return fn(s, 0.5 / s, a); }
+
+// frame[12] = eye, fwd, right*sx, up*sy as functions of (yaw, pitch, dist, fovy)
+void sphere_frame(double yaw, double pitch, double dist, double fovy, int W, int H, D4* f) {
+  const D4 y = var(yaw, 0), p = var(pitch, 1), r = var(dist, 2), fo = var(fovy, 3);
+  const D4 e0 = mul(mul(r, dcos(p)), dcos(y));
+  const D4 e1 = mul(r, dsin(p));
+  const D4 e2 = mul(mul(r, dcos(p)), dsin(y));
+  const D4 len = dsqrt(add(add(mul(e0, e0), mul(e1, e1)), mul(e2, e2)));
+  const D4 F0 = dvd(sub(cst(0), e0), len), F1 = dvd(sub(cst(0), e1), len),
+           F2 = dvd(sub(cst(0), e2), len);
+  const D4 rl = dsqrt(add(mul(F2, F2), mul(F0, F0)));
+  const D4 R0 = dvd(sub(cst(0), F2), rl), R1 = cst(0.0), R2 = dvd(F0, rl);
+  const D4 U0 = sub(mul(R1, F2), mul(R2, F1));
+  const D4 U1 = sub(mul(R2, F0), mul(R0, F2));
+  const D4 U2 = sub(mul(R0, F1), mul(R1, F0));
+  const D4 sy = dtan(mul(fo, cst(0.5)));
+  const D4 sx = mul(sy, cst((double)W / H));
+  f[0] = e0; f[1] = e1; f[2] = e2;
+  f[3] = F0; f[4] = F1; f[5] = F2;
+  f[6] = mul(R0, sx); f[7] = mul(R1, sx); f[8] = mul(R2, sx);
+  f[9] = mul(U0, sy); f[10] = mul(U1, sy); f[11] = mul(U2, sy);
+}
+
+int validate_sphere(float yaw, float pitch, float dist, float fovy, int W, int H) {
+  if (!std::isfinite(yaw) || !std::isfinite(pitch) || !std::isfinite(dist) || !std::isfinite(fovy))
+    return fail(DDVR_ERR_VALUE, "camera pose is not finite");
+  if (!(std::fabs(pitch) < 1.5707963267948966 - 1e-6))
+    return fail(DDVR_ERR_VALUE, "|pitch| must be < pi/2");
+  if (!(dist > 0.0f)) return fail(DDVR_ERR_VALUE, "camera distance must be > 0");
+  if (!(fovy > 0.0f) || !(fovy < 3.14159265f)) return fail(DDVR_ERR_VALUE, "fovy must be in (0, pi)");
+  if (W <= 0 || H <= 0) return fail(DDVR_ERR_SHAPE, "image %dx%d", W, H);
+  return DDVR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+struct ddvr_batch {
+  int model = 0, flags = 0;
+  std::vector<ViewDesc> views;
+  std::vector<int> view_dtype;
+  // launch groups: one per storage dtype, each a contiguous range of `work`
+  struct Group { int dtype, first, count, maxR; };
+  std::vector<Group> groups;
+  ViewDesc* d_views = nullptr;
+  int32_t* d_work = nullptr;
+  int64_t total_rays = 0, max_n = 1;
+  int64_t samples = -1;
+  int grad_mask = 0;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int g_pass = -1;
+  float g_scale = 0.0f;
+  double* g_loss = nullptr;
+  void* g_ws = nullptr;
+};
+
+extern "C" {
+
+int ddvr_abi_version(void) { return DDVR_ABI_VERSION; }
+
+const char* ddvr_last_error(void) { return g_err; }
+
+int ddvr_camera_from_sphere(float yaw, float pitch, float dist, float fovy, int32_t width,
+                            int32_t height, ddvr_camera* out) {
+  if (!out) return fail(DDVR_ERR_NULL, "output camera is NULL");
+  int rc = validate_sphere(yaw, pitch, dist, fovy, width, height);
+  if (rc) return rc;
+  D4 f[12];
+  sphere_frame(yaw, pitch, dist, fovy, width, height, f);
+  for (int a = 0; a < 3; ++a) {
+    out->eye[a] = (float)f[a].v;
+    out->fwd[a] = (float)f[3 + a].v;
+    out->right[a] = (float)f[6 + a].v;
+    out->up[a] = (float)f[9 + a].v;
+  }
+  out->width = width;
+  out->height = height;
+  return DDVR_OK;
+}
+
+int ddvr_camera_grad_to_sphere(float yaw, float pitch, float dist, float fovy, int32_t width,
+                               int32_t height, const float* d_frame, float* d_sphere) {
+  if (!d_frame || !d_sphere) return fail(DDVR_ERR_NULL, "gradient pointer is NULL");
+  int rc = validate_sphere(yaw, pitch, dist, fovy, width, height);
+  if (rc) return rc;
+  D4 f[12];
+  sphere_frame(yaw, pitch, dist, fovy, width, height, f);
+  for (int k = 0; k < 4; ++k) {
+    double acc = 0.0;
+    for (int j = 0; j < 12; ++j) acc += f[j].d[k] * (double)d_frame[j];
+    d_sphere[k] = (float)acc;
+  }
+  return DDVR_OK;
+}
+
+int ddvr_cast_volume(const float* src, void* dst, int32_t dtype, int64_t n, void* hip_stream) {
+  if (!src || !dst) return fail(DDVR_ERR_NULL, "source or destination is NULL");
+  if (dtype != DDVR_F32 && dtype != DDVR_F16 && dtype != DDVR_BF16)
+    return fail(DDVR_ERR_DTYPE, "unknown dtype %d", dtype);
+  if (n < 0) return fail(DDVR_ERR_SHAPE, "negative element count");
+  int rc = check_pending();
+  if (rc) return rc;
+  const hipError_t e = (hipError_t)launch_cast(src, dst, dtype, n, hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "cast launch");
+  return DDVR_OK;
+}
+
+int ddvr_render_forward(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, float* image, float* transmittance,
+                        int32_t flags, void* hip_stream) {
+  if (flags & DDVR_ADJ_MODE_MASK)
+    return fail(DDVR_ERR_VALUE, "forward flags must be 0 or DDVR_LAUNCH_PLAIN");
+  return run_single(PASS_FWD, vol, tf, cam, step_world, model, image, transmittance, nullptr,
+                    nullptr, 0.0f, nullptr, flags, nullptr, 0, nullptr, nullptr, hip_stream);
+}
+
+int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, float step_world,
+                                int32_t model, int32_t flags, size_t* bytes) {
+  int rc;
+  if (!bytes) return fail(DDVR_ERR_NULL, "bytes is NULL");
+  if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_camera(cam)) ||
+      (rc = validate_step(vol, step_world)) || (rc = validate_flags(flags)))
+    return rc;
+  *bytes = needs_fallback(model, flags)
+               ? fallback_layout((int64_t)cam->width * cam->height, max_samples(vol, step_world)).bytes
+               : 0;
+  return DDVR_OK;
+}
+
+int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, const float* image,
+                        const float* transmittance, const float* d_image,
+                        const ddvr_grads* grads, int32_t flags, void* workspace,
+                        size_t workspace_bytes, int32_t* n_fallback_rays, void* hip_stream) {
+  if (!grads) return fail(DDVR_ERR_NULL, "grads is NULL");
+  return run_single(PASS_ADJ, vol, tf, cam, step_world, model, const_cast<float*>(image),
+                    const_cast<float*>(transmittance), d_image, nullptr, 0.0f, grads, flags,
+                    workspace, workspace_bytes, n_fallback_rays, nullptr, hip_stream);
+}
+
+int ddvr_render_fused_l2(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                         float step_world, int32_t model, const float* target, float loss_scale,
+                         float* image, float* transmittance, const ddvr_grads* grads,
+                         int32_t flags, void* workspace, size_t workspace_bytes,
+                         int32_t* n_fallback_rays, double* loss_out, void* hip_stream) {
+  return run_single(PASS_FUSED, vol, tf, cam, step_world, model, image, transmittance, nullptr,
+                    target, loss_scale, grads, flags, workspace, workspace_bytes,
+                    n_fallback_rays, loss_out, hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs, int32_t ntf,
+                      const ddvr_view* views, int32_t nview, int32_t model, int32_t flags,
+                      float* const* d_volumes, float* const* d_tfs, void* hip_stream,
+                      ddvr_batch** out) {
+  int rc;
+  if (!out) return fail(DDVR_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (!vols || !views) return fail(DDVR_ERR_NULL, "volumes or views is NULL");
+  if (nvol <= 0 || nview <= 0 || nview >= 2048)
+    return fail(DDVR_ERR_SHAPE, "need 1..2047 views and >= 1 volume");
+  if ((rc = validate_model(model)) || (rc = validate_flags(flags))) return rc;
+  if (model == DDVR_EMISSION_ABSORPTION && (!tfs || ntf <= 0))
+    return fail(DDVR_ERR_NULL, "emission-absorption batch without transfer functions");
+  for (int i = 0; i < nvol; ++i)
+    if ((rc = validate_volume(&vols[i]))) return rc;
+  if (model == DDVR_EMISSION_ABSORPTION)
+    for (int i = 0; i < ntf; ++i)
+      if ((rc = validate_tf(&tfs[i], model))) return rc;
+  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  ddvr_batch* b = new (std::nothrow) ddvr_batch;
+  if (!b) return fail(DDVR_ERR_VALUE, "out of host memory");
+  b->model = model;
+  b->flags = flags;
+  b->views.resize(nview);
+  b->view_dtype.resize(nview);
+  int gmask = 0;
+  for (int i = 0; i < nview; ++i) {
+    const ddvr_view& v = views[i];
+    if (v.volume < 0 || v.volume >= nvol) { delete b; return fail(DDVR_ERR_SHAPE, "view %d: bad volume index", i); }
+    if (model == DDVR_EMISSION_ABSORPTION && (v.tf < 0 || v.tf >= ntf)) {
+      delete b; return fail(DDVR_ERR_SHAPE, "view %d: bad TF index", i);
+    }
+    if ((rc = validate_camera(&v.cam)) || (rc = validate_step(&vols[v.volume], v.step_world))) {
+      delete b; return rc;
+    }
+    if (!v.image) { delete b; return fail(DDVR_ERR_NULL, "view %d: image is NULL", i); }
+    const ddvr_tf* tf = model == DDVR_EMISSION_ABSORPTION ? &tfs[v.tf] : nullptr;
+    ViewDesc& d = b->views[i];
+    fill_view(d, &vols[v.volume], tf, &v.cam, v.step_world, model, cap);
+    d.image = v.image;
+    d.trans = v.transmittance;
+    d.d_image = v.d_image;
+    d.target = v.target;
+    d.dV = d_volumes ? d_volumes[v.volume] : nullptr;
+    d.dTF = (model == DDVR_EMISSION_ABSORPTION && d_tfs) ? d_tfs[v.tf] : nullptr;
+    d.dcam = v.d_camera;
+    d.dstep = v.d_step;
+    gmask |= (d.dV ? GRAD_V : 0) | (d.dTF ? GRAD_TF : 0) | (d.dcam ? GRAD_CAM : 0) |
+             (d.dstep ? GRAD_STEP : 0);
+    b->view_dtype[i] = vols[v.volume].dtype;
+    b->total_rays += (int64_t)v.cam.width * v.cam.height;
+    b->max_n = std::max<int64_t>(b->max_n, max_samples(&vols[v.volume], v.step_world));
+    if ((int64_t)d.tiles_x * d.tiles_y >= (1 << 20)) {
+      delete b; return fail(DDVR_ERR_SHAPE, "view %d: too many tiles", i);
+    }
+  }
+  b->grad_mask = gmask;
+  // work list: grouped by storage dtype, views in order, tiles in raster order
+  std::vector<int32_t> work;
+  for (int dt = 0; dt < 3; ++dt) {
+    ddvr_batch::Group g{dt, (int)work.size(), 0, 2};
+    for (int i = 0; i < nview; ++i) {
+      if (b->view_dtype[i] != dt) continue;
+      const int nt = b->views[i].tiles_x * b->views[i].tiles_y;
+      for (int t = 0; t < nt; ++t) work.push_back((i << 20) | t);
+      g.maxR = std::max(g.maxR, (int)b->views[i].R);
+    }
+    g.count = (int)work.size() - g.first;
+    if (g.count > 0) b->groups.push_back(g);
+  }
+  hipError_t e = hipMalloc(&b->d_views, sizeof(ViewDesc) * nview);
+  if (e == hipSuccess) e = hipMalloc(&b->d_work, sizeof(int32_t) * work.size());
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_views, b->views.data(), sizeof(ViewDesc) * nview, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_work, work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    ddvr_batch_destroy(b);
+    return hip_fail(e, "batch descriptor upload");
+  }
+  *out = b;
+  return DDVR_OK;
+}
+
+void ddvr_batch_destroy(ddvr_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_views) (void)hipFree(b->d_views);
+  if (b->d_work) (void)hipFree(b->d_work);
+  delete b;
+}
+
+int ddvr_batch_workspace_size(const ddvr_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(DDVR_ERR_NULL, "batch or bytes is NULL");
+  *bytes = needs_fallback(b->model, b->flags) ? fallback_layout(b->total_rays, b->max_n).bytes : 0;
+  return DDVR_OK;
+}
+
+static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss_out, void* ws,
+                         size_t ws_bytes, hipStream_t s) {
+  if (pass < PASS_FWD || pass > PASS_FUSED) return fail(DDVR_ERR_VALUE, "unknown pass %d", pass);
+  if (!std::isfinite(loss_scale)) return fail(DDVR_ERR_VALUE, "loss_scale is not finite");
+  for (size_t i = 0; i < b->views.size(); ++i) {
+    const ViewDesc& d = b->views[i];
+    if (pass == PASS_ADJ && (!d.d_image || !d.trans))
+      return fail(DDVR_ERR_NULL, "view %zu: adjoint needs d_image and transmittance", i);
+    if (pass == PASS_FUSED && !d.target) return fail(DDVR_ERR_NULL, "view %zu: target is NULL", i);
+  }
+  const bool fb = pass != PASS_FWD && needs_fallback(b->model, b->flags);
+  FbLayout L;
+  if (fb) {
+    L = fallback_layout(b->total_rays, b->max_n);
+    if (!ws || ws_bytes < L.bytes)
+      return fail(DDVR_ERR_WORKSPACE, "workspace of %zu bytes needed", L.bytes);
+  }
+  LaunchParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.views = b->d_views;
+  p.flags = b->flags;
+  p.grad_mask = b->grad_mask;
+  p.lds_cap = (b->flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  p.loss_scale = loss_scale;
+  p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
+  if (fb) attach_fallback(p, L, ws, b->flags);
+  hipError_t e;
+  if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, s)) != hipSuccess)
+    return hip_fail(e, "zeroing the fallback queue");
+  for (const auto& g : b->groups) {
+    p.work = b->d_work + g.first;
+    p.n_items = g.count;
+    e = (hipError_t)launch_render(p, pass, b->model, g.dtype, kWaves, g.count,
+                                  lds_bytes(p.lds_cap, b->model, g.maxR), s);
+    if (e != hipSuccess) return hip_fail(e, "batch render launch");
+    if (fb) {
+      e = (hipError_t)launch_fallback(p, b->model, g.dtype, pass == PASS_FUSED ? 1 : 0, s);
+      if (e != hipSuccess) return hip_fail(e, "batch fallback launch");
+      if (b->groups.size() > 1 && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, s)) != hipSuccess)
+        return hip_fail(e, "zeroing the fallback queue");
+    }
+  }
+  return DDVR_OK;
+}
+
+int ddvr_batch_run(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
+                   void* workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!b) return fail(DDVR_ERR_NULL, "batch is NULL");
+  int rc = check_pending();
+  if (rc) return rc;
+  return batch_enqueue(b, pass, loss_scale, loss_out, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(hip_stream));
+}
+
+int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
+                         void* workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!b) return fail(DDVR_ERR_NULL, "batch is NULL");
+  int rc = check_pending();
+  if (rc) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool same = b->exec && b->g_pass == pass && b->g_scale == loss_scale &&
+                    b->g_loss == loss_out && b->g_ws == workspace;
+  hipError_t e;
+  if (!same) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    rc = batch_enqueue(b, pass, loss_scale, loss_out, workspace, workspace_bytes, b->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    b->graph = g;
+    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+      return hip_fail(e, "graph instantiate");
+    b->g_pass = pass;
+    b->g_scale = loss_scale;
+    b->g_loss = loss_out;
+    b->g_ws = workspace;
+  }
+  if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+  return DDVR_OK;
+}
+
+int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples) {
+  if (!b || !samples) return fail(DDVR_ERR_NULL, "batch or samples is NULL");
+  // exact count, replaying the ray setup of the kernels on the host in float32
+  int64_t total = 0;
+  for (const ViewDesc& d : b->views) {
+    for (int py = 0; py < d.H; ++py)
+      for (int px = 0; px < d.W; ++px) {
+        const float u = 2.0f * ((float)px + 0.5f) / (float)d.W - 1.0f;
+        const float v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)d.H;
+        float w[3], om[3];
+        for (int a = 0; a < 3; ++a) w[a] = d.fwd[a] + u * d.right[a] + v * d.up[a];
+        const float wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int a = 0; a < 3; ++a) om[a] = w[a] / wl;
+        float tn = -INFINITY, tf = INFINITY;
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+          if (om[a] == 0.0f) {
+            if (d.eye[a] < d.bmin[a] || d.eye[a] > d.bmax[a]) ok = false;
+            continue;
+          }
+          const float ta = (d.bmin[a] - d.eye[a]) / om[a], tb = (d.bmax[a] - d.eye[a]) / om[a];
+          tn = std::max(tn, std::min(ta, tb));
+          tf = std::min(tf, std::max(ta, tb));
+        }
+        const float t0 = tn > 0.0f ? tn : 0.0f;
+        if (ok && tf > t0) total += (int64_t)std::ceil((tf - t0) / d.step);
+      }
+  }
+  *samples = total;
+  return DDVR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Internal launch descriptors shared by the host API and the HIP kernels.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ddvr {
+
+// One view of one grid, as the kernels see it (prepared on the host).
+struct ViewDesc {
+  // camera frame (Sec. 4.1 f_camera): eye, forward, pre-scaled right / up
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t W, H;
+  float step;             // dt, world units
+  // grid (Sec. 3.1): vertex values [nz][ny][nx]
+  const void* vol;
+  int32_t nx, ny, nz;
+  float h, inv_h;
+  float bmin[3], bmax[3];
+  // transfer function [R][4]
+  const float* tf;
+  int32_t R;
+  // outputs / inputs of the passes
+  float* image;           // [H][W][C]
+  float* trans;           // [H][W] or null
+  const float* d_image;   // adjoint seed, or null
+  const float* target;    // fused L2 target, or null
+  // gradients (null = not requested)
+  float* dV;
+  float* dTF;
+  float* dcam;            // [12]
+  float* dstep;           // [1]
+  // tiling
+  int32_t tiles_x, tiles_y;
+  int32_t slab_k;         // samples per slab (LDS staging granularity)
+  int32_t pad_;
+};
+
+// Per-launch parameters (passed by value as the kernel argument).
+struct LaunchParams {
+  const ViewDesc* views;  // device array (batched) or null -> use `one`
+  ViewDesc one;           // inline descriptor of a single-view launch
+  const int32_t* work;    // device list of (view << 20 | tile) items, or null
+  int32_t n_items;        // number of tiles in the launch
+  int32_t flags;          // adjoint mode | launch flags
+  int32_t grad_mask;      // bit 0 dV, 1 dTF, 2 camera, 3 step
+  int32_t lds_cap;        // voxels per LDS staging buffer (0 = never stage)
+  float loss_scale;       // fused L2
+  double* loss_out;       // fused L2 accumulator or null
+  // checkpoint fallback queue (workspace)
+  int32_t* fb_count;      // [1] number of queued rays
+  int64_t* fb_list;       // [fb_cap] (view << 32 | pixel)
+  int64_t fb_cap;
+  float fb_tmin;          // T_N threshold below which rays fall back
+  int32_t fb_all;         // 1: every hit ray takes the checkpoint path
+  float* fb_scratch;      // per-slot scratch for checkpointing
+  int32_t fb_slots;       // number of concurrent checkpoint slots
+  int32_t fb_slot_floats; // floats per slot
+};
+
+enum GradBits { GRAD_V = 1, GRAD_TF = 2, GRAD_CAM = 4, GRAD_STEP = 8 };
+
+enum Pass { PASS_FWD = 0, PASS_ADJ = 1, PASS_FUSED = 2 };
+
+// Host-side launchers implemented in ddvr_kernels.hip.
+int launch_render(const LaunchParams& p, int pass, int model, int dtype, int waves, int n_blocks,
+                  size_t lds_bytes, void* stream);
+int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void* stream);
+int launch_zero_i32(int32_t* ptr, int n, void* stream);
+int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
+
+constexpr int kMaxSamples = 1 << 22;    // per-ray sample cap (validated on the host)
+constexpr float kFallbackTmin = 7.888609052210118e-31f;   // 2^-100 (T-form inversion)
+constexpr float kFallbackTminAlpha = 9.765625e-4f;         // 2^-10 (alpha-form inversion)
+
+}  // namespace ddvr

@@ -1,0 +1,1031 @@
+// HIP kernels (gfx950) of the differentiable direct volume renderer.
+//
+// Forward: Alg. 1 of Weiss & Westermann (arXiv 2107.12672, Sec. 4.1).
+// Adjoint: Alg. 2 (Sec. 4.3) with the inversion trick of Sec. 4.4.
+//
+// Mapping to CDNA4:
+//   * one ray per lane; a wave owns an 8x8 pixel block, a workgroup owns a
+//     tile of WAVES such blocks (16x16 pixels for 4 waves);
+//   * the tile marches slab-synchronously: its rays' samples are grouped into
+//     slabs of K samples at the same distance from the eye; for every slab the
+//     workgroup computes the bounding box of the grid cells its samples touch,
+//     stages that brick of the density grid into LDS (converted to float32)
+//     and, in the adjoint, accumulates the density gradient of the slab in an
+//     LDS brick with ds_add_f32 that is flushed once per slab with one global
+//     atomic per touched voxel (the paper accumulates per ray "on exit of the
+//     current cell", Sec. 4.4 implementation paragraph; the brick is the same
+//     idea at workgroup granularity);
+//   * the transfer function lives in LDS; its gradient is accumulated per ray
+//     in registers while the ray stays on one TF segment and flushed to an
+//     LDS table on segment change (Sec. 5.2 "adjoint-delayed"), then to global
+//     memory once per workgroup;
+//   * camera and step-size gradients stay in registers per ray and are reduced
+//     over the workgroup before one atomic per value;
+//   * blockIdx is remapped so that each XCD (own L2) gets a contiguous range
+//     of tiles.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "ddvr_internal.h"
+#include "ddvr.h"
+
+namespace ddvr {
+
+// ---------------------------------------------------------------------------
+// storage types of the density grid
+// ---------------------------------------------------------------------------
+template <int DT> struct Vox;
+template <> struct Vox<DDVR_F32> {
+  static __device__ __forceinline__ float ld(const void* p, int64_t i) {
+    return static_cast<const float*>(p)[i];
+  }
+};
+template <> struct Vox<DDVR_F16> {
+  static __device__ __forceinline__ float ld(const void* p, int64_t i) {
+    return __half2float(static_cast<const __half*>(p)[i]);
+  }
+};
+template <> struct Vox<DDVR_BF16> {
+  static __device__ __forceinline__ float ld(const void* p, int64_t i) {
+    const uint32_t u = static_cast<const uint16_t*>(p)[i];
+    return __uint_as_float(u << 16);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// f_camera: ray of one pixel, clipped against the grid box.
+// Positions are carried in grid units: q = (x - b_min)/h.
+// ---------------------------------------------------------------------------
+struct RayG {
+  float qo[3];   // entry point in grid units
+  float dq[3];   // per-sample increment dt*omega/h
+  float om[3];   // unit direction
+  float t0;      // entry distance
+  float wlen;    // |fwd + u*right + v*up|
+  float u, v;    // pixel-plane coordinates
+  int N;         // samples (0: miss or not a pixel)
+  int axis;      // slab plane that defines t0 (-1: t0 = 0)
+};
+
+__device__ __forceinline__ void setup_ray(const ViewDesc& vd, int px, int py, bool valid,
+                                          RayG& r) {
+  r.u = 2.0f * ((float)px + 0.5f) / (float)vd.W - 1.0f;
+  r.v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)vd.H;
+  float w[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) w[a] = vd.fwd[a] + r.u * vd.right[a] + r.v * vd.up[a];
+  r.wlen = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r.om[a] = w[a] / r.wlen;
+  float tn = -INFINITY, tf = INFINITY;
+  int ax = -1;
+  bool ok = valid;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float o = r.om[a], e = vd.eye[a];
+    if (o == 0.0f) {
+      if (e < vd.bmin[a] || e > vd.bmax[a]) ok = false;
+      continue;
+    }
+    const float ta = (vd.bmin[a] - e) / o, tb = (vd.bmax[a] - e) / o;
+    const float lo = fminf(ta, tb), hi = fmaxf(ta, tb);
+    if (lo > tn) { tn = lo; ax = a; }
+    tf = fminf(tf, hi);
+  }
+  float t0 = tn;
+  if (!(tn > 0.0f)) { t0 = 0.0f; ax = -1; }
+  r.t0 = t0;
+  r.axis = ax;
+  r.N = 0;
+  // a degenerate frame (zero or non-finite direction) yields no samples
+  if (!(r.wlen > 0.0f) || !(r.wlen < INFINITY)) ok = false;
+  if (ok && tf > t0 && (tf - t0) < 1e30f) {
+    const float n = ceilf((tf - t0) / vd.step);
+    r.N = (int)fminf(n, (float)kMaxSamples);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = vd.eye[a] + t0 * r.om[a];
+    r.qo[a] = (x - vd.bmin[a]) * vd.inv_h;
+    r.dq[a] = vd.step * r.om[a] * vd.inv_h;
+  }
+}
+
+// Trilinear cell of sample i: k = clamp(floor(q), 0, n-2), f = q - k.
+// fmaf(i, dq, qo) is monotone in i, so the cells of a run of samples lie
+// inside the box spanned by the run's first and last cells.
+struct Cell {
+  int k[3];
+  float f[3];
+};
+
+__device__ __forceinline__ void locate(const RayG& r, int i, int nx, int ny, int nz, Cell& c) {
+  const float fi = (float)i;
+  const int n[3] = {nx, ny, nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = fmaf(fi, r.dq[a], r.qo[a]);
+    int k = (int)floorf(q);
+    k = min(max(k, 0), n[a] - 2);
+    c.k[a] = k;
+    c.f[a] = q - (float)k;
+  }
+}
+
+// 8 corner values, index = cx + 2*cy + 4*cz
+template <int DT>
+__device__ __forceinline__ void fetch_global(const ViewDesc& vd, const Cell& c, float* v) {
+  const int64_t sx = 1, sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  const int64_t b = c.k[2] * sz + c.k[1] * sy + c.k[0];
+  v[0] = Vox<DT>::ld(vd.vol, b);
+  v[1] = Vox<DT>::ld(vd.vol, b + sx);
+  v[2] = Vox<DT>::ld(vd.vol, b + sy);
+  v[3] = Vox<DT>::ld(vd.vol, b + sy + sx);
+  v[4] = Vox<DT>::ld(vd.vol, b + sz);
+  v[5] = Vox<DT>::ld(vd.vol, b + sz + sx);
+  v[6] = Vox<DT>::ld(vd.vol, b + sz + sy);
+  v[7] = Vox<DT>::ld(vd.vol, b + sz + sy + sx);
+}
+
+struct Brick {   // LDS brick of the current slab
+  int x0, y0, z0;
+  int bx, bxy;
+  int size;
+  float inv_bx, inv_bxy;
+};
+
+__device__ __forceinline__ int brick_base(const Brick& br, const Cell& c) {
+  return (c.k[2] - br.z0) * br.bxy + (c.k[1] - br.y0) * br.bx + (c.k[0] - br.x0);
+}
+
+__device__ __forceinline__ void fetch_lds(const float* st, const Brick& br, int base, float* v) {
+  v[0] = st[base];
+  v[1] = st[base + 1];
+  v[2] = st[base + br.bx];
+  v[3] = st[base + br.bx + 1];
+  v[4] = st[base + br.bxy];
+  v[5] = st[base + br.bxy + 1];
+  v[6] = st[base + br.bxy + br.bx];
+  v[7] = st[base + br.bxy + br.bx + 1];
+}
+
+// f_interpolate and its derivative w.r.t. the cell-local coordinates f.
+__device__ __forceinline__ float trilerp(const float* v, const float* f) {
+  const float c00 = fmaf(f[0], v[1] - v[0], v[0]);
+  const float c10 = fmaf(f[0], v[3] - v[2], v[2]);
+  const float c01 = fmaf(f[0], v[5] - v[4], v[4]);
+  const float c11 = fmaf(f[0], v[7] - v[6], v[6]);
+  const float c0 = fmaf(f[1], c10 - c00, c00);
+  const float c1 = fmaf(f[1], c11 - c01, c01);
+  return fmaf(f[2], c1 - c0, c0);
+}
+
+__device__ __forceinline__ void trilerp_grad(const float* v, const float* f, float* g) {
+  const float c00 = fmaf(f[0], v[1] - v[0], v[0]);
+  const float c10 = fmaf(f[0], v[3] - v[2], v[2]);
+  const float c01 = fmaf(f[0], v[5] - v[4], v[4]);
+  const float c11 = fmaf(f[0], v[7] - v[6], v[6]);
+  const float c0 = fmaf(f[1], c10 - c00, c00);
+  const float c1 = fmaf(f[1], c11 - c01, c01);
+  g[2] = c1 - c0;
+  g[1] = fmaf(f[2], (c11 - c01) - (c10 - c00), c10 - c00);
+  const float x00 = v[1] - v[0], x10 = v[3] - v[2], x01 = v[5] - v[4], x11 = v[7] - v[6];
+  const float x0 = fmaf(f[1], x10 - x00, x00), x1 = fmaf(f[1], x11 - x01, x01);
+  g[0] = fmaf(f[2], x1 - x0, x0);
+}
+
+__device__ __forceinline__ void trilerp_weights(const float* f, float* w) {
+  const float gx = 1.0f - f[0], gy = 1.0f - f[1], gz = 1.0f - f[2];
+  const float a00 = gy * gz, a10 = f[1] * gz, a01 = gy * f[2], a11 = f[1] * f[2];
+  w[0] = gx * a00; w[1] = f[0] * a00;
+  w[2] = gx * a10; w[3] = f[0] * a10;
+  w[4] = gx * a01; w[5] = f[0] * a01;
+  w[6] = gx * a11; w[7] = f[0] * a11;
+}
+
+// f_TF: knots at k/(R-1), density clamped to [0,1].
+struct TFv {
+  float r, g, b, tau, phi;
+  int j;
+  bool inside;
+};
+
+__device__ __forceinline__ void tf_eval(const float4* tf, int R, float d, TFv& s) {
+  s.inside = (d >= 0.0f) && (d <= 1.0f);
+  const float dc = fminf(fmaxf(d, 0.0f), 1.0f);
+  const float u = dc * (float)(R - 1);
+  const int j = min((int)u, R - 2);
+  s.j = j;
+  s.phi = u - (float)j;
+  const float4 a = tf[j], b = tf[j + 1];
+  s.r = fmaf(s.phi, b.x - a.x, a.x);
+  s.g = fmaf(s.phi, b.y - a.y, a.y);
+  s.b = fmaf(s.phi, b.z - a.z, a.z);
+  s.tau = fmaf(s.phi, b.w - a.w, a.w);
+}
+
+// ---------------------------------------------------------------------------
+// workgroup helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <int NT>
+__device__ __forceinline__ void wg_max_n(int* v, int n, int* scratch) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < n; ++k) {
+    int x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+    v[k] = x;
+  }
+  if (NW == 1) return;
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < n; ++k) scratch[wid * 8 + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    int x = scratch[k];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) x = max(x, scratch[w * 8 + k]);
+    v[k] = x;
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ float wg_min_f(float x, float* scratch) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
+  if (NW == 1) return x;
+  __syncthreads();
+  if (lane == 0) scratch[wid] = x;
+  __syncthreads();
+  float r = scratch[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = fminf(r, scratch[w]);
+  return r;
+}
+
+// sum of n floats over the workgroup; result valid in thread 0
+template <int NT>
+__device__ __forceinline__ void wg_sum_n(float* v, int n, float* scratch) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < n; ++k) {
+    float x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[k] = x;
+  }
+  if (NW == 1) return;
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < n; ++k) scratch[wid * 16 + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < n; ++k) {
+      float x = scratch[k];
+      for (int w = 1; w < NW; ++w) x += scratch[w * 16 + k];
+      v[k] = x;
+    }
+}
+
+// Sample range [a, b) of a ray in slab s: samples are grouped by their index
+// offset relative to the earliest entry point of the tile.
+__device__ __forceinline__ void slab_range(int s, int K, int off, int N, int& a, int& b) {
+  a = min(max(s * K - off, 0), N);
+  b = min(max((s + 1) * K - off, 0), N);
+}
+
+// Brick of the slab: bounding box of the cells of every sample in the slab.
+// Returns 0 = empty slab, 1 = staged in LDS, 2 = too large (direct access).
+template <int NT, int DT>
+__device__ __forceinline__ int prepare_slab(const ViewDesc& vd, const RayG& r, int a, int b,
+                                            int cap, bool stage_v, float* stage, float* acc,
+                                            int* iscratch, Brick& br) {
+  int v[6];
+  if (a < b) {
+    Cell c0, c1;
+    locate(r, a, vd.nx, vd.ny, vd.nz, c0);
+    locate(r, b - 1, vd.nx, vd.ny, vd.nz, c1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[k] = -min(c0.k[k], c1.k[k]);
+      v[3 + k] = max(c0.k[k], c1.k[k]) + 1;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = -0x3fffffff;
+  }
+  wg_max_n<NT>(v, 6, iscratch);
+  if (v[3] < 0) return 0;
+  br.x0 = -v[0]; br.y0 = -v[1]; br.z0 = -v[2];
+  const int bx = v[3] - br.x0 + 1, by = v[4] - br.y0 + 1, bz = v[5] - br.z0 + 1;
+  br.bx = bx;
+  br.bxy = bx * by;
+  br.size = br.bxy * bz;
+  if (cap <= 0 || br.size > cap) return 2;
+  br.inv_bx = 1.0f / (float)bx;
+  br.inv_bxy = 1.0f / (float)br.bxy;
+  if (stage_v || acc) {
+    const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+    for (int idx = threadIdx.x; idx < br.size; idx += NT) {
+      if (stage_v) {
+        const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
+        const int rem = idx - z * br.bxy;
+        const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
+        const int x = rem - y * bx;
+        stage[idx] = Vox<DT>::ld(vd.vol, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
+      }
+      if (acc) acc[idx] = 0.0f;
+    }
+  }
+  __syncthreads();
+  return 1;
+}
+
+template <int NT>
+__device__ __forceinline__ void flush_brick(const ViewDesc& vd, const Brick& br, const float* acc) {
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  for (int idx = threadIdx.x; idx < br.size; idx += NT) {
+    const float g = acc[idx];
+    if (g != 0.0f) {
+      const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
+      const int rem = idx - z * br.bxy;
+      const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
+      const int x = rem - y * br.bx;
+      atomicAdd(vd.dV + (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x), g);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-sample forward (Alg. 1 body)
+// ---------------------------------------------------------------------------
+struct FwdState {
+  float C[3];
+  float T;      // emission-absorption: running transmittance
+  float sigma;  // absorption-only: running optical depth / dt
+};
+
+template <int MODEL, int DT, bool LDS>
+__device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int a, int b,
+                                          const float* stage, const Brick& br,
+                                          const float4* tfl, FwdState& s) {
+  for (int i = a; i < b; ++i) {
+    Cell c;
+    locate(r, i, vd.nx, vd.ny, vd.nz, c);
+    float v[8];
+    if (LDS) fetch_lds(stage, br, brick_base(br, c), v);
+    else fetch_global<DT>(vd, c, v);
+    const float d = trilerp(v, c.f);
+    if (MODEL == DDVR_ABSORPTION) {
+      s.sigma += d;
+    } else {
+      TFv t;
+      tf_eval(tfl, vd.R, d, t);
+      const float e = __expf(-vd.step * t.tau);
+      const float w = s.T * (1.0f - e);
+      s.C[0] = fmaf(w, t.r, s.C[0]);
+      s.C[1] = fmaf(w, t.g, s.C[1]);
+      s.C[2] = fmaf(w, t.b, s.C[2]);
+      s.T *= e;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-ray adjoint state and per-sample adjoint (Alg. 2 body)
+// ---------------------------------------------------------------------------
+struct AdjState {
+  float Chat[3];   // adjoint of the accumulated colour (constant along the ray)
+  float ahat;      // adjoint of the accumulated opacity alpha^(i+1)
+  float Tn;        // T^(i+1) (inversion state)
+  float an;        // alpha^(i+1) (alpha-form inversion state)
+  float P;         // absorption-only closed form: T^(i+1)*ahat^(i+1), constant
+  float xo_hat[3]; // sum of position adjoints
+  float si[3];     // sum of i * position adjoints
+  float dstep;     // Beer-Lambert part of the step adjoint
+  // TF gradient of the current segment (registers, flushed on change)
+  int tj;
+  float tg0[4], tg1[4];
+};
+
+__device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
+  if (s.tj >= 0) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      if (s.tg0[ch] != 0.0f) atomicAdd(dtf + 4 * s.tj + ch, s.tg0[ch]);
+      if (s.tg1[ch] != 0.0f) atomicAdd(dtf + 4 * (s.tj + 1) + ch, s.tg1[ch]);
+      s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f;
+    }
+  }
+}
+
+// Adjoint of one sample i given T^(i) source.  `mode` selects how T^(i) is
+// recovered: 0 closed form (AO), 1 T-form inversion, 2 alpha-form inversion,
+// 3 caller supplies Ti (checkpoint).
+template <int MODEL, int DT, bool LDS, int MODE>
+__device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, int i,
+                                           const float* stage, float* acc, const Brick& br,
+                                           const float4* tfl, float* dtf, int gmask,
+                                           bool need_v, AdjState& s, float Ti_given) {
+  Cell c;
+  locate(r, i, vd.nx, vd.ny, vd.nz, c);
+  const bool need_xhat = (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
+  float v[8];
+  float d = 0.0f;
+  int base = 0;
+  if (LDS) base = brick_base(br, c);
+  if (need_v) {
+    if (LDS) fetch_lds(stage, br, base, v);
+    else fetch_global<DT>(vd, c, v);
+    d = trilerp(v, c.f);
+  }
+  float d_hat;
+  if (MODEL == DDVR_ABSORPTION && MODE == 0) {
+    // T^(i)*e_i*ahat^(i+1) = T^(i+1)*ahat^(i+1) is invariant under the
+    // inversion T^(i) = T^(i+1)/e_i, ahat^(i) = e_i*ahat^(i+1) (no emission).
+    d_hat = vd.step * s.P;
+    s.dstep += d * s.P;
+  } else {
+    float rgb[3] = {0.0f, 0.0f, 0.0f}, tau;
+    TFv t;
+    if (MODEL == DDVR_EMISSION_ABSORPTION) {
+      tf_eval(tfl, vd.R, d, t);
+      rgb[0] = t.r; rgb[1] = t.g; rgb[2] = t.b;
+      tau = t.tau;
+    } else {
+      tau = d;
+    }
+    const float e = __expf(-vd.step * tau);
+    const float alpha = 1.0f - e;
+    float Ti;
+    if (MODE == 1) {
+      Ti = s.Tn * __builtin_amdgcn_rcpf(e);
+    } else if (MODE == 2) {
+      const float ap = (alpha - s.an) / (alpha - 1.0f);   // eq. (inv-blend-forward)
+      s.an = ap;
+      Ti = 1.0f - ap;
+    } else {
+      Ti = Ti_given;
+    }
+    s.Tn = Ti;
+    const float rc = rgb[0] * s.Chat[0] + rgb[1] * s.Chat[1] + rgb[2] * s.Chat[2];
+    const float as_hat = Ti * (s.ahat + rc);            // adjoint of alpha_i
+    s.ahat = fmaf(e, s.ahat, -alpha * rc);              // ahat^(i)
+    const float ase = as_hat * e;
+    const float tau_hat = ase * vd.step;
+    s.dstep = fmaf(ase, tau, s.dstep);
+    if (MODEL == DDVR_EMISSION_ABSORPTION) {
+      const float w = alpha * Ti;
+      const float g4[4] = {w * s.Chat[0], w * s.Chat[1], w * s.Chat[2], tau_hat};
+      if (gmask & GRAD_TF) {
+        if (t.j != s.tj) {
+          tf_flush(s, dtf);
+          s.tj = t.j;
+        }
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+          s.tg0[ch] = fmaf(1.0f - t.phi, g4[ch], s.tg0[ch]);
+          s.tg1[ch] = fmaf(t.phi, g4[ch], s.tg1[ch]);
+        }
+      }
+      const float4 ta = tfl[t.j], tb = tfl[t.j + 1];
+      const float u_hat = (tb.x - ta.x) * g4[0] + (tb.y - ta.y) * g4[1] +
+                          (tb.z - ta.z) * g4[2] + (tb.w - ta.w) * g4[3];
+      d_hat = t.inside ? (float)(vd.R - 1) * u_hat : 0.0f;
+    } else {
+      d_hat = tau_hat;
+    }
+  }
+  if (gmask & GRAD_V) {
+    float w[8];
+    trilerp_weights(c.f, w);
+    if (LDS) {
+      atomicAdd(acc + base, w[0] * d_hat);
+      atomicAdd(acc + base + 1, w[1] * d_hat);
+      atomicAdd(acc + base + br.bx, w[2] * d_hat);
+      atomicAdd(acc + base + br.bx + 1, w[3] * d_hat);
+      atomicAdd(acc + base + br.bxy, w[4] * d_hat);
+      atomicAdd(acc + base + br.bxy + 1, w[5] * d_hat);
+      atomicAdd(acc + base + br.bxy + br.bx, w[6] * d_hat);
+      atomicAdd(acc + base + br.bxy + br.bx + 1, w[7] * d_hat);
+    } else {
+      const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+      float* g = vd.dV + (c.k[2] * sz + c.k[1] * sy + c.k[0]);
+      atomicAdd(g, w[0] * d_hat);
+      atomicAdd(g + 1, w[1] * d_hat);
+      atomicAdd(g + sy, w[2] * d_hat);
+      atomicAdd(g + sy + 1, w[3] * d_hat);
+      atomicAdd(g + sz, w[4] * d_hat);
+      atomicAdd(g + sz + 1, w[5] * d_hat);
+      atomicAdd(g + sz + sy, w[6] * d_hat);
+      atomicAdd(g + sz + sy + 1, w[7] * d_hat);
+    }
+  }
+  if (need_xhat) {
+    float gd[3];
+    trilerp_grad(v, c.f, gd);
+    const float sc = d_hat * vd.inv_h;
+    const float fi = (float)i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float xh = sc * gd[a];
+      s.xo_hat[a] += xh;
+      s.si[a] = fmaf(fi, xh, s.si[a]);
+    }
+  }
+}
+
+template <int MODEL, int DT, bool LDS, int MODE>
+__device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int a, int b,
+                                          const float* stage, float* acc, const Brick& br,
+                                          const float4* tfl, float* dtf, int gmask, bool need_v,
+                                          AdjState& s) {
+  for (int i = b - 1; i >= a; --i)
+    adj_sample<MODEL, DT, LDS, MODE>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v, s, 0.0f);
+}
+
+// Camera adjoint of one ray (last line of Alg. 2 on [x_o_hat; omega_hat]).
+// out[0..11] = d frame, out[12] = d step.
+__device__ __forceinline__ void camera_adjoint(const ViewDesc& vd, const RayG& r,
+                                               const AdjState& s, bool hit, float* out) {
+#pragma unroll
+  for (int k = 0; k < 13; ++k) out[k] = 0.0f;
+  if (!hit) return;
+  out[12] = s.dstep + r.om[0] * s.si[0] + r.om[1] * s.si[1] + r.om[2] * s.si[2];
+  float oh[3], eh[3];
+  float t0h = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    oh[a] = vd.step * s.si[a] + r.t0 * s.xo_hat[a];
+    eh[a] = s.xo_hat[a];
+    t0h += r.om[a] * s.xo_hat[a];
+  }
+  if (r.axis >= 0) {
+    const float o = r.om[r.axis];
+    eh[r.axis] -= t0h / o;
+    oh[r.axis] -= t0h * r.t0 / o;
+  }
+  const float od = r.om[0] * oh[0] + r.om[1] * oh[1] + r.om[2] * oh[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float wh = (oh[a] - r.om[a] * od) / r.wlen;
+    out[a] = eh[a];
+    out[3 + a] = wh;
+    out[6 + a] = r.u * wh;
+    out[9 + a] = r.v * wh;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the render kernel: forward, adjoint, or fused forward + L2 + adjoint
+// ---------------------------------------------------------------------------
+template <int WAVES> struct TileShape;
+template <> struct TileShape<1> { static constexpr int BX = 1, BY = 1; };
+template <> struct TileShape<2> { static constexpr int BX = 2, BY = 1; };
+template <> struct TileShape<4> { static constexpr int BX = 2, BY = 2; };
+
+template <int MODEL, int DT, int WAVES, int PASS>
+__global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
+  constexpr int NT = WAVES * 64;
+  constexpr int TW = 8 * TileShape<WAVES>::BX, TH = 8 * TileShape<WAVES>::BY;
+  constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
+  extern __shared__ __align__(16) float smem[];
+
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  int view = 0, tile = item;
+  if (p.work) {
+    const int w = p.work[item];
+    view = w >> 20;
+    tile = w & 0xFFFFF;
+  }
+  const ViewDesc vd = p.views ? p.views[view] : p.one;
+  const int cap = p.lds_cap;
+  const bool adj_pass = PASS != PASS_FWD;
+  const bool want_dv = adj_pass && (p.grad_mask & GRAD_V) && vd.dV != nullptr;
+  int gmask = p.grad_mask;
+  if (!vd.dV) gmask &= ~GRAD_V;
+  if (!vd.dTF) gmask &= ~GRAD_TF;
+  if (!vd.dcam) gmask &= ~GRAD_CAM;
+  if (!vd.dstep) gmask &= ~GRAD_STEP;
+
+  // LDS carve-up
+  float* stage = smem;
+  float* acc = smem + cap;
+  float4* tfl = reinterpret_cast<float4*>(smem + 2 * cap);
+  float* dtf = smem + 2 * cap + (EA ? 4 * vd.R : 0);
+  int* iscratch = reinterpret_cast<int*>(dtf + (EA ? 4 * vd.R : 0));
+  float* fscratch = reinterpret_cast<float*>(iscratch);
+
+  if (EA) {
+    for (int k = threadIdx.x; k < 4 * vd.R; k += NT) {
+      reinterpret_cast<float*>(tfl)[k] = vd.tf[k];
+      dtf[k] = 0.0f;
+    }
+  }
+
+  const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = tx * TW + (wid % TileShape<WAVES>::BX) * 8 + (lane & 7);
+  const int py = ty * TH + (wid / TileShape<WAVES>::BX) * 8 + (lane >> 3);
+  const bool valid = px < vd.W && py < vd.H;
+  const int64_t pix = (int64_t)py * vd.W + px;
+  RayG r;
+  setup_ray(vd, px, py, valid, r);
+  const bool hit = r.N > 0;
+
+  // slab bookkeeping (shared by both passes)
+  int K, off = 0, nslab;
+  if (cap > 0) {
+    K = vd.slab_k;
+    const float tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
+    off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
+    int ns = hit ? (off + r.N + K - 1) / K : 0;
+    wg_max_n<NT>(&ns, 1, iscratch);
+    nslab = ns;
+  } else {
+    K = kMaxSamples + 1;
+    int ns = hit ? 1 : 0;
+    wg_max_n<NT>(&ns, 1, iscratch);
+    nslab = ns;
+  }
+  __syncthreads();   // TF table visible
+
+  const int C = EA ? 4 : 1;
+  float gimg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float TN = 1.0f;
+
+  if (PASS == PASS_FWD || PASS == PASS_FUSED) {
+    FwdState fs;
+    fs.C[0] = fs.C[1] = fs.C[2] = 0.0f;
+    fs.T = 1.0f;
+    fs.sigma = 0.0f;
+    for (int s = 0; s < nslab; ++s) {
+      int a, b;
+      slab_range(s, K, off, r.N, a, b);
+      Brick br;
+      const int st = prepare_slab<NT, DT>(vd, r, a, b, cap, true, stage, nullptr, iscratch, br);
+      if (st == 1) march_fwd<MODEL, DT, true>(vd, r, a, b, stage, br, tfl, fs);
+      else if (st == 2) march_fwd<MODEL, DT, false>(vd, r, a, b, stage, br, tfl, fs);
+    }
+    float out[4];
+    if (EA) {
+      TN = fs.T;
+      out[0] = fs.C[0]; out[1] = fs.C[1]; out[2] = fs.C[2]; out[3] = 1.0f - TN;
+    } else {
+      TN = __expf(-vd.step * fs.sigma);
+      out[0] = 1.0f - TN;
+    }
+    if (valid) {
+      if (EA) reinterpret_cast<float4*>(vd.image)[pix] = make_float4(out[0], out[1], out[2], out[3]);
+      else vd.image[pix] = out[0];
+      if (vd.trans) vd.trans[pix] = TN;
+    }
+    if (PASS == PASS_FUSED) {
+      float loss = 0.0f;
+      if (valid) {
+        for (int ch = 0; ch < C; ++ch) {
+          const float dlt = out[ch] - vd.target[pix * C + ch];
+          loss = fmaf(dlt, dlt, loss);
+          gimg[ch] = 2.0f * p.loss_scale * dlt;
+        }
+      }
+      if (p.loss_out) {
+        float l = loss * p.loss_scale;
+        wg_sum_n<NT>(&l, 1, fscratch);
+        if (threadIdx.x == 0 && l != 0.0f) atomicAdd(p.loss_out, (double)l);
+      }
+    }
+  }
+  if (PASS == PASS_FWD) return;
+
+  if (PASS == PASS_ADJ && valid) {
+    TN = vd.trans[pix];
+    for (int ch = 0; ch < C; ++ch) gimg[ch] = vd.d_image[pix * C + ch];
+  }
+
+  // choose the adjoint route of this ray
+  const int mode = p.flags & DDVR_ADJ_MODE_MASK;
+  bool fallback = false;
+  if (hit) {
+    if (p.fb_all) fallback = true;
+    else if (((EA && mode == DDVR_ADJ_AUTO) || mode == DDVR_ADJ_INVERT_ALPHA) &&
+             !(TN >= p.fb_tmin))
+      fallback = true;
+    if (!p.fb_count) fallback = false;
+  }
+  {
+    const uint64_t m = __ballot(fallback);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(p.fb_count, __popcll(m));
+      base = __shfl(base, leader, 64);
+      if (fallback) {
+        const int my = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (my < p.fb_cap) p.fb_list[my] = ((int64_t)view << 32) | pix;
+      }
+    }
+  }
+  const int Nadj = fallback ? 0 : r.N;
+
+  AdjState s;
+  s.Chat[0] = EA ? gimg[0] : 0.0f;
+  s.Chat[1] = EA ? gimg[1] : 0.0f;
+  s.Chat[2] = EA ? gimg[2] : 0.0f;
+  s.ahat = EA ? gimg[3] : gimg[0];
+  s.Tn = TN;
+  s.an = 1.0f - TN;
+  s.P = TN * s.ahat;
+  s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0f;
+  s.si[0] = s.si[1] = s.si[2] = 0.0f;
+  s.dstep = 0.0f;
+  s.tj = -1;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
+
+  const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || mode != DDVR_ADJ_AUTO;
+  for (int s_ = nslab - 1; s_ >= 0; --s_) {
+    int a, b;
+    slab_range(s_, K, off, Nadj, a, b);
+    Brick br;
+    const int st = prepare_slab<NT, DT>(vd, r, a, b, cap, need_v, stage,
+                                        want_dv ? acc : nullptr, iscratch, br);
+    if (st == 0) continue;
+    if (st == 1) {
+      if (!EA && mode == DDVR_ADJ_AUTO)
+        march_adj<MODEL, DT, true, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+      else if (mode == DDVR_ADJ_INVERT_ALPHA)
+        march_adj<MODEL, DT, true, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+      else
+        march_adj<MODEL, DT, true, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+      __syncthreads();
+      if (want_dv) flush_brick<NT>(vd, br, acc);
+    } else {
+      if (!EA && mode == DDVR_ADJ_AUTO)
+        march_adj<MODEL, DT, false, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+      else if (mode == DDVR_ADJ_INVERT_ALPHA)
+        march_adj<MODEL, DT, false, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+      else
+        march_adj<MODEL, DT, false, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+    }
+  }
+  if (EA && (gmask & GRAD_TF)) tf_flush(s, dtf);
+
+  if (gmask & (GRAD_CAM | GRAD_STEP)) {
+    float cg[13];
+    camera_adjoint(vd, r, s, Nadj > 0, cg);
+    wg_sum_n<NT>(cg, 13, fscratch);
+    if (threadIdx.x == 0) {
+      if (gmask & GRAD_CAM)
+        for (int k = 0; k < 12; ++k)
+          if (cg[k] != 0.0f) atomicAdd(vd.dcam + k, cg[k]);
+      if ((gmask & GRAD_STEP) && cg[12] != 0.0f) atomicAdd(vd.dstep, cg[12]);
+    }
+  }
+  if (EA && (gmask & GRAD_TF)) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < 4 * vd.R; k += NT)
+      if (dtf[k] != 0.0f) atomicAdd(vd.dTF + k, dtf[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// segment-checkpoint fallback (one ray per thread, queued by the main kernel)
+// ---------------------------------------------------------------------------
+template <int MODEL, int DT, int FUSED>
+__global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
+  constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= p.fb_slots) return;
+  float* ws = p.fb_scratch + (int64_t)slot * p.fb_slot_floats;
+  const int64_t count = min((int64_t)*p.fb_count, p.fb_cap);
+  const int64_t stride = (int64_t)p.fb_slots;
+  for (int64_t q = slot; q < count; q += stride) {
+    const int64_t code = p.fb_list[q];
+    const int view = (int)(code >> 32);
+    const int64_t pix = code & 0xFFFFFFFFll;
+    const ViewDesc vd = p.views ? p.views[view] : p.one;
+    int gmask = p.grad_mask;
+    if (!vd.dV) gmask &= ~GRAD_V;
+    if (!vd.dTF) gmask &= ~GRAD_TF;
+    if (!vd.dcam) gmask &= ~GRAD_CAM;
+    if (!vd.dstep) gmask &= ~GRAD_STEP;
+    const int px = (int)(pix % vd.W), py = (int)(pix / vd.W);
+    RayG r;
+    setup_ray(vd, px, py, true, r);
+    if (r.N <= 0) continue;
+    const int C = EA ? 4 : 1;
+    float gimg[4];
+    for (int ch = 0; ch < C; ++ch) {
+      if (FUSED) gimg[ch] = 2.0f * p.loss_scale * (vd.image[pix * C + ch] - vd.target[pix * C + ch]);
+      else gimg[ch] = vd.d_image[pix * C + ch];
+    }
+    const float4* tfl = reinterpret_cast<const float4*>(vd.tf);
+    const int N = r.N;
+    int K = (int)ceilf(sqrtf((float)N));
+    while (K * K < N) ++K;
+    const int nseg = (N + K - 1) / K;
+    float* ck = ws;             // T at the start of every segment
+    float* tseg = ws + nseg;    // T^(i) inside the current segment
+    // forward: keep T at segment starts
+    {
+      float T = 1.0f;
+      for (int i = 0; i < N; ++i) {
+        if (i % K == 0) ck[i / K] = T;
+        Cell c;
+        locate(r, i, vd.nx, vd.ny, vd.nz, c);
+        float v[8];
+        fetch_global<DT>(vd, c, v);
+        const float d = trilerp(v, c.f);
+        float tau = d;
+        if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
+        T *= __expf(-vd.step * tau);
+      }
+    }
+    AdjState s;
+    s.Chat[0] = EA ? gimg[0] : 0.0f;
+    s.Chat[1] = EA ? gimg[1] : 0.0f;
+    s.Chat[2] = EA ? gimg[2] : 0.0f;
+    s.ahat = EA ? gimg[3] : gimg[0];
+    s.Tn = 0.0f; s.an = 0.0f; s.P = 0.0f;
+    s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0f;
+    s.si[0] = s.si[1] = s.si[2] = 0.0f;
+    s.dstep = 0.0f;
+    s.tj = -1;
+    for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
+    Brick br{};
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int i0 = sg * K, i1 = min(N, i0 + K);
+      tseg[0] = ck[sg];
+      for (int i = i0; i < i1; ++i) {
+        Cell c;
+        locate(r, i, vd.nx, vd.ny, vd.nz, c);
+        float v[8];
+        fetch_global<DT>(vd, c, v);
+        const float d = trilerp(v, c.f);
+        float tau = d;
+        if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
+        tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
+      }
+      for (int i = i1 - 1; i >= i0; --i)
+        adj_sample<MODEL, DT, false, 3>(vd, r, i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
+                                        true, s, tseg[i - i0]);
+    }
+    if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
+    if (gmask & (GRAD_CAM | GRAD_STEP)) {
+      float cg[13];
+      camera_adjoint(vd, r, s, true, cg);
+      if (gmask & GRAD_CAM)
+        for (int k = 0; k < 12; ++k) atomicAdd(vd.dcam + k, cg[k]);
+      if (gmask & GRAD_STEP) atomicAdd(vd.dstep, cg[12]);
+    }
+  }
+}
+
+// float32 master -> storage copy (round to nearest even), 4 values per lane
+__global__ void k_cast(const float* __restrict__ src, void* __restrict__ dst, int dtype,
+                       int64_t n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  if (i0 + 4 <= n && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+    const float4 v = *reinterpret_cast<const float4*>(src + i0);
+    const float x[4] = {v.x, v.y, v.z, v.w};
+    if (dtype == DDVR_F16) {
+      __half* d = static_cast<__half*>(dst) + i0;
+      for (int k = 0; k < 4; ++k) d[k] = __float2half_rn(x[k]);
+    } else if (dtype == DDVR_BF16) {
+      uint16_t* d = static_cast<uint16_t*>(dst) + i0;
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t u = __float_as_uint(x[k]);
+        const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+        d[k] = nan ? (uint16_t)((u >> 16) | 0x40u)
+                   : (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+      }
+    } else {
+      *reinterpret_cast<float4*>(static_cast<float*>(dst) + i0) = v;
+    }
+    return;
+  }
+  for (int64_t i = i0; i < n && i < i0 + 4; ++i) {
+    const float x = src[i];
+    if (dtype == DDVR_F16) {
+      static_cast<__half*>(dst)[i] = __float2half_rn(x);
+    } else if (dtype == DDVR_BF16) {
+      const uint32_t u = __float_as_uint(x);
+      const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+      static_cast<uint16_t*>(dst)[i] = nan ? (uint16_t)((u >> 16) | 0x40u)
+                                           : (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    } else {
+      static_cast<float*>(dst)[i] = x;
+    }
+  }
+}
+
+int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  const int64_t threads = (n + 3) / 4;
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), src, dst, dtype, n);
+  return (int)hipGetLastError();
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int MODEL, int DT, int WAVES>
+static hipError_t launch3(const LaunchParams& p, int pass, int n_blocks, size_t lds,
+                          hipStream_t s) {
+  const dim3 grid(n_blocks), block(WAVES * 64);
+  switch (pass) {
+    case PASS_FWD:
+      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_FWD>), grid, block, lds, s, p);
+      break;
+    case PASS_ADJ:
+      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_ADJ>), grid, block, lds, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_FUSED>), grid, block, lds, s, p);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODEL, int DT>
+static hipError_t launch2(const LaunchParams& p, int pass, int waves, int n_blocks, size_t lds,
+                          hipStream_t s) {
+  switch (waves) {
+    case 1: return launch3<MODEL, DT, 1>(p, pass, n_blocks, lds, s);
+    case 2: return launch3<MODEL, DT, 2>(p, pass, n_blocks, lds, s);
+    default: return launch3<MODEL, DT, 4>(p, pass, n_blocks, lds, s);
+  }
+}
+
+template <int MODEL>
+static hipError_t launch1(const LaunchParams& p, int pass, int dtype, int waves, int n_blocks,
+                          size_t lds, hipStream_t s) {
+  switch (dtype) {
+    case DDVR_F16: return launch2<MODEL, DDVR_F16>(p, pass, waves, n_blocks, lds, s);
+    case DDVR_BF16: return launch2<MODEL, DDVR_BF16>(p, pass, waves, n_blocks, lds, s);
+    default: return launch2<MODEL, DDVR_F32>(p, pass, waves, n_blocks, lds, s);
+  }
+}
+
+int launch_render(const LaunchParams& p, int pass, int model, int dtype, int waves, int n_blocks,
+                  size_t lds_bytes, void* stream) {
+  if (n_blocks <= 0) return 0;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = model == DDVR_EMISSION_ABSORPTION
+      ? launch1<DDVR_EMISSION_ABSORPTION>(p, pass, dtype, waves, n_blocks, lds_bytes, s)
+      : launch1<DDVR_ABSORPTION>(p, pass, dtype, waves, n_blocks, lds_bytes, s);
+  return (int)e;
+}
+
+template <int MODEL, int DT>
+static hipError_t launch_fb2(const LaunchParams& p, int fused, int blocks, hipStream_t s) {
+  if (fused) hipLaunchKernelGGL((k_fallback<MODEL, DT, 1>), dim3(blocks), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL((k_fallback<MODEL, DT, 0>), dim3(blocks), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int MODEL>
+static hipError_t launch_fb1(const LaunchParams& p, int dtype, int fused, int blocks,
+                             hipStream_t s) {
+  switch (dtype) {
+    case DDVR_F16: return launch_fb2<MODEL, DDVR_F16>(p, fused, blocks, s);
+    case DDVR_BF16: return launch_fb2<MODEL, DDVR_BF16>(p, fused, blocks, s);
+    default: return launch_fb2<MODEL, DDVR_F32>(p, fused, blocks, s);
+  }
+}
+
+int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void* stream) {
+  if (p.fb_slots <= 0) return 0;
+  const int blocks = (p.fb_slots + 255) / 256;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = model == DDVR_EMISSION_ABSORPTION
+      ? launch_fb1<DDVR_EMISSION_ABSORPTION>(p, dtype, fused, blocks, s)
+      : launch_fb1<DDVR_ABSORPTION>(p, dtype, fused, blocks, s);
+  return (int)e;
+}
+
+int launch_zero_i32(int32_t* ptr, int n, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), ptr, n);
+  return (int)hipGetLastError();
+}
+
+}  // namespace ddvr

@@ -1,0 +1,283 @@
+"""Thin ctypes binding of ``libddvr.so`` (declared in include/ddvr.h).
+
+Names follow the C ABI without the ``ddvr_`` prefix.  The functions only
+marshal arguments: torch tensors supply device pointers and torch's current
+HIP stream supplies the stream; every step of the rendering runs in the HIP
+kernels of the library.  Loading fails loudly when the library has not been
+built -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddvr.so")
+
+OK = 0
+ERR_NULL, ERR_SHAPE, ERR_DTYPE, ERR_VALUE, ERR_HIP, ERR_UNSUPPORTED, ERR_WORKSPACE = \
+    -1, -2, -3, -4, -5, -6, -7
+F32, F16, BF16 = 0, 1, 2
+ABSORPTION, EMISSION_ABSORPTION = 0, 1
+ADJ_AUTO, ADJ_INVERT_T, ADJ_INVERT_ALPHA, ADJ_CHECKPOINT = 0, 1, 2, 3
+LAUNCH_PLAIN = 0x10
+PASS_FORWARD, PASS_ADJOINT, PASS_FUSED = 0, 1, 2
+
+EXPORTED = [
+    "ddvr_abi_version", "ddvr_last_error", "ddvr_camera_from_sphere",
+    "ddvr_camera_grad_to_sphere", "ddvr_render_forward", "ddvr_adjoint_workspace_size",
+    "ddvr_render_adjoint", "ddvr_render_fused_l2", "ddvr_batch_create", "ddvr_batch_destroy",
+    "ddvr_batch_workspace_size", "ddvr_batch_run", "ddvr_batch_run_graph",
+    "ddvr_batch_sample_count", "ddvr_cast_volume",
+]
+
+
+class DDVRError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ddvr status {status}: {message}")
+        self.status = status
+
+
+class Volume(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class TF(ctypes.Structure):
+    _fields_ = [("rgba_tau", ctypes.c_void_p), ("R", ctypes.c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("fwd", ctypes.c_float * 3),
+                ("right", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+    def frame(self) -> List[float]:
+        return list(self.eye) + list(self.fwd) + list(self.right) + list(self.up)
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("d_volume", ctypes.c_void_p), ("d_tf", ctypes.c_void_p),
+                ("d_camera", ctypes.c_void_p), ("d_step", ctypes.c_void_p)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_int32), ("tf", ctypes.c_int32), ("cam", Camera),
+                ("step_world", ctypes.c_float), ("image", ctypes.c_void_p),
+                ("transmittance", ctypes.c_void_p), ("d_image", ctypes.c_void_p),
+                ("target", ctypes.c_void_p), ("d_camera", ctypes.c_void_p),
+                ("d_step", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raw ctypes handle)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2107_12672_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, F, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+    sig = {
+        "ddvr_abi_version": ([], ctypes.c_int),
+        "ddvr_last_error": ([], ctypes.c_char_p),
+        "ddvr_camera_from_sphere": ([F, F, F, F, I32, I32, P], ctypes.c_int),
+        "ddvr_camera_grad_to_sphere": ([F, F, F, F, I32, I32, P, P], ctypes.c_int),
+        "ddvr_render_forward": ([P, P, P, F, I32, P, P, I32, P], ctypes.c_int),
+        "ddvr_adjoint_workspace_size": ([P, P, F, I32, I32, P], ctypes.c_int),
+        "ddvr_render_adjoint": ([P, P, P, F, I32, P, P, P, P, I32, P, SZ, P, P], ctypes.c_int),
+        "ddvr_render_fused_l2": ([P, P, P, F, I32, P, F, P, P, P, I32, P, SZ, P, P, P],
+                                 ctypes.c_int),
+        "ddvr_batch_create": ([P, I32, P, I32, P, I32, I32, I32, P, P, P, P], ctypes.c_int),
+        "ddvr_batch_destroy": ([P], None),
+        "ddvr_batch_workspace_size": ([P, P], ctypes.c_int),
+        "ddvr_batch_run": ([P, I32, F, P, P, SZ, P], ctypes.c_int),
+        "ddvr_batch_run_graph": ([P, I32, F, P, P, SZ, P], ctypes.c_int),
+        "ddvr_batch_sample_count": ([P, P], ctypes.c_int),
+        "ddvr_cast_volume": ([P, P, I32, ctypes.c_int64, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().ddvr_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise DDVRError(status, last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def dtype_code(t) -> int:
+    import torch
+    return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t.dtype]
+
+
+def volume_desc(vol) -> Volume:
+    """Descriptor of a contiguous [nz][ny][nx] device tensor."""
+    assert vol.is_contiguous() and vol.dim() == 3
+    nz, ny, nx = vol.shape
+    return Volume(vol.data_ptr(), dtype_code(vol), nx, ny, nz)
+
+
+def tf_desc(tf) -> TF:
+    if tf is None:
+        return TF(None, 0)
+    assert tf.is_contiguous() and tf.dim() == 2 and tf.shape[1] == 4
+    return TF(tf.data_ptr(), tf.shape[0])
+
+
+def grads_desc(d_volume=None, d_tf=None, d_camera=None, d_step=None) -> Grads:
+    return Grads(_ptr(d_volume), _ptr(d_tf), _ptr(d_camera), _ptr(d_step))
+
+
+def abi_version() -> int:
+    return lib().ddvr_abi_version()
+
+
+def camera_from_sphere(yaw: float, pitch: float, dist: float, fovy: float, width: int,
+                       height: int) -> Camera:
+    """Angles in radians (see include/ddvr.h)."""
+    cam = Camera()
+    _check(lib().ddvr_camera_from_sphere(yaw, pitch, dist, fovy, width, height,
+                                         ctypes.byref(cam)))
+    return cam
+
+
+def camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, d_frame: Sequence[float]):
+    df = (ctypes.c_float * 12)(*[float(x) for x in d_frame])
+    out = (ctypes.c_float * 4)()
+    _check(lib().ddvr_camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, df, out))
+    return list(out)
+
+
+def cast_volume(src, dst, stream=None):
+    """dst (f32/f16/bf16 device tensor) <- src (float32 device tensor), RNE."""
+    assert src.numel() == dst.numel() and src.is_contiguous() and dst.is_contiguous()
+    _check(lib().ddvr_cast_volume(_ptr(src), _ptr(dst), dtype_code(dst), src.numel(),
+                                  _stream(stream)))
+
+
+def render_forward(volume, tf, cam: Camera, step: float, model: int, image, transmittance=None,
+                   flags: int = 0, stream=None):
+    v, t = volume_desc(volume), tf_desc(tf)
+    _check(lib().ddvr_render_forward(ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step,
+                                     model, _ptr(image), _ptr(transmittance), flags,
+                                     _stream(stream)))
+
+
+def adjoint_workspace_size(volume, cam: Camera, step: float, model: int, flags: int = 0) -> int:
+    v = volume_desc(volume)
+    n = ctypes.c_size_t(0)
+    _check(lib().ddvr_adjoint_workspace_size(ctypes.byref(v), ctypes.byref(cam), step, model,
+                                             flags, ctypes.byref(n)))
+    return n.value
+
+
+def render_adjoint(volume, tf, cam: Camera, step: float, model: int, image, transmittance,
+                   d_image, grads: Grads, flags: int = 0, workspace=None,
+                   count_fallback: bool = False, stream=None) -> int:
+    v, t = volume_desc(volume), tf_desc(tf)
+    nfb = ctypes.c_int32(0)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().ddvr_render_adjoint(
+        ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step, model, _ptr(image),
+        _ptr(transmittance), _ptr(d_image), ctypes.byref(grads), flags, _ptr(workspace),
+        ws_bytes, ctypes.byref(nfb) if count_fallback else None, _stream(stream)))
+    return nfb.value
+
+
+def render_fused_l2(volume, tf, cam: Camera, step: float, model: int, target, loss_scale: float,
+                    image, transmittance, grads: Grads, flags: int = 0, workspace=None,
+                    loss_out=None, count_fallback: bool = False, stream=None) -> int:
+    v, t = volume_desc(volume), tf_desc(tf)
+    nfb = ctypes.c_int32(0)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().ddvr_render_fused_l2(
+        ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step, model, _ptr(target),
+        loss_scale, _ptr(image), _ptr(transmittance), ctypes.byref(grads), flags,
+        _ptr(workspace), ws_bytes, ctypes.byref(nfb) if count_fallback else None,
+        _ptr(loss_out), _stream(stream)))
+    return nfb.value
+
+
+class Batch:
+    """Many views (of one or several grids) rendered in one launch per pass."""
+
+    def __init__(self, volumes, tfs, views: Sequence[View], model: int, flags: int = 0,
+                 d_volumes=None, d_tfs=None, stream=None):
+        self._keep = (volumes, tfs, views, d_volumes, d_tfs)
+        nv = len(volumes)
+        vd = (Volume * nv)(*[volume_desc(v) for v in volumes])
+        ntf = 0 if not tfs else len(tfs)
+        td = (TF * max(ntf, 1))(*[tf_desc(t) for t in (tfs or [])])
+        vw = (View * len(views))(*views)
+        dvs = None
+        if d_volumes is not None:
+            dvs = (ctypes.c_void_p * nv)(*[_ptr(d) for d in d_volumes])
+        dts = None
+        if d_tfs is not None:
+            dts = (ctypes.c_void_p * max(ntf, 1))(*[_ptr(d) for d in d_tfs])
+        h = ctypes.c_void_p()
+        _check(lib().ddvr_batch_create(vd, nv, td if ntf else None, ntf, vw, len(views), model,
+                                       flags, dvs, dts, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check(lib().ddvr_batch_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def sample_count(self) -> int:
+        n = ctypes.c_int64(0)
+        _check(lib().ddvr_batch_sample_count(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def run(self, pass_: int, loss_scale: float = 0.0, loss_out=None, workspace=None,
+            graph: bool = False, stream=None):
+        ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        fn = lib().ddvr_batch_run_graph if graph else lib().ddvr_batch_run
+        _check(fn(self.handle, pass_, loss_scale, _ptr(loss_out), _ptr(workspace), ws_bytes,
+                  _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ddvr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_view(volume_index: int, cam: Camera, step: float, image, transmittance=None,
+              d_image=None, target=None, d_camera=None, d_step=None, tf_index: int = -1) -> View:
+    return View(volume_index, tf_index, cam, step, _ptr(image), _ptr(transmittance),
+                _ptr(d_image), _ptr(target), _ptr(d_camera), _ptr(d_step))
