@@ -132,6 +132,26 @@ typedef struct {
   float* d_step;
 } ddvr_grads;
 
+/* Launch shape of the render kernels (process-wide default, captured by a
+ * batch when it is created).
+ *   waves      waves per workgroup: 1 (8x8-pixel tiles), 2 (16x8) or 4 (16x16)
+ *   lds_cap    voxels per LDS brick (64..16384); the forward stages the grid
+ *              values of each slab's brick, the adjoint accumulates the density
+ *              gradient of the brick before one global atomic per voxel
+ *   slab_k     initial samples per ray in a slab (>= 4); the kernel halves it
+ *              while a slab's brick exceeds lds_cap and doubles it after small
+ *              bricks, up to slab_kmax (<= 4096).
+ * Results do not depend on the tuning beyond float32 summation order. */
+typedef struct {
+  int32_t waves;
+  int32_t lds_cap;
+  int32_t slab_k;
+  int32_t slab_kmax;
+} ddvr_tuning;
+
+int ddvr_set_tuning(const ddvr_tuning* t);
+int ddvr_get_tuning(ddvr_tuning* t);
+
 /* Version of this ABI (DDVR_ABI_VERSION). */
 int ddvr_abi_version(void);
 

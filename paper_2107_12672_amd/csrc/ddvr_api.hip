@@ -43,10 +43,31 @@ bool finite3(const float* v) {
   return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
-constexpr int kWaves = 4;                 // 16x16 pixel tiles
-constexpr int kTileW = 16, kTileH = 16;
-constexpr int kLdsCap = 4096;             // voxels per LDS brick (x2: values + gradient)
 constexpr int kFallbackSlots = 65536;     // concurrent checkpoint slots
+
+// Launch shape of the render kernels (process-wide; see ddvr_set_tuning).
+struct Tuning {
+  int waves = 4;        // waves per workgroup: 1 -> 8x8, 2 -> 16x8, 4 -> 16x16 pixel tiles
+  int lds_cap = 6144;   // voxels per LDS brick
+  int slab_k = 32;      // initial samples per slab
+  int slab_kmax = 256;  // longest slab tried
+};
+Tuning g_tuning;
+
+// Largest dynamic LDS allocation of one workgroup on the current device.
+int check_lds(size_t bytes) {
+  int dev = 0, lim = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(e, "querying the LDS limit");
+  if (bytes > (size_t)lim)
+    return fail(DDVR_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS, the device allows %d (lower "
+                "lds_cap or the TF size)", bytes, lim);
+  return DDVR_OK;
+}
+
+int tile_w(int waves) { return waves == 1 ? 8 : 16; }
+int tile_h(int waves) { return waves == 4 ? 16 : 8; }
 
 int validate_volume(const ddvr_volume* v) {
   if (!v) return fail(DDVR_ERR_NULL, "volume descriptor is NULL");
@@ -102,40 +123,6 @@ int validate_step(const ddvr_volume* v, float step) {
   return DDVR_OK;
 }
 
-// Samples per slab: the longest run whose estimated brick fits the LDS budget.
-int choose_slab_k(const ddvr_volume* v, const ddvr_camera* c, float step, int cap) {
-  if (cap <= 0) return kMaxSamples + 1;
-  const int nmax = std::max(v->nx, std::max(v->ny, v->nz));
-  const double inv_h = 0.5 * (nmax - 1);
-  const double ry = std::sqrt((double)c->up[0] * c->up[0] + (double)c->up[1] * c->up[1] +
-                              (double)c->up[2] * c->up[2]);
-  const double rx = std::sqrt((double)c->right[0] * c->right[0] +
-                              (double)c->right[1] * c->right[1] +
-                              (double)c->right[2] * c->right[2]);
-  const double pitch = std::max(2.0 * ry / c->height, 2.0 * rx / c->width);
-  const double dist = std::sqrt((double)c->eye[0] * c->eye[0] + (double)c->eye[1] * c->eye[1] +
-                                (double)c->eye[2] * c->eye[2]) + half_diag(v);
-  const double wv = std::max(kTileW, kTileH) * pitch * dist * inv_h + 2.0;
-  double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
-  const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-  for (double& x : f) x /= fl;
-  auto box = [&](double l) {
-    double b = 1.0;
-    for (int a = 0; a < 3; ++a)
-      b *= std::fabs(f[a]) * l + wv * std::sqrt(std::max(0.0, 1.0 - f[a] * f[a])) + 2.0;
-    return b;
-  };
-  const double budget = 0.85 * cap;
-  if (box(0.0) > budget) return 8;   // slabs will mostly go the direct route
-  double lo = 0.0, hi = 4096.0;
-  for (int it = 0; it < 60; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    (box(mid) <= budget ? lo : hi) = mid;
-  }
-  const double k = lo / (step * inv_h);
-  return (int)std::min(4096.0, std::max(4.0, std::floor(k)));
-}
-
 void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_camera* c,
                float step, int model, int cap) {
   std::memset(&d, 0, sizeof(d));
@@ -157,14 +144,24 @@ void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_
     d.bmax[a] = (float)(0.5 * (n[a] - 1) * h);
   }
   if (model == DDVR_EMISSION_ABSORPTION) { d.tf = tf->rgba_tau; d.R = tf->R; }
-  d.tiles_x = (c->width + kTileW - 1) / kTileW;
-  d.tiles_y = (c->height + kTileH - 1) / kTileH;
-  d.slab_k = choose_slab_k(v, c, step, cap);
+  const int tw = tile_w(g_tuning.waves), th = tile_h(g_tuning.waves);
+  d.tiles_x = (c->width + tw - 1) / tw;
+  d.tiles_y = (c->height + th - 1) / th;
+  d.slab_k = cap > 0 ? g_tuning.slab_k : kMaxSamples + 1;
 }
 
-size_t lds_bytes(int cap, int model, int R) {
+size_t lds_bytes(int cap, int two, int model, int R) {
   const size_t tf = model == DDVR_EMISSION_ABSORPTION ? (size_t)R * 8 : 0;
-  return ((size_t)2 * cap + tf) * sizeof(float) + 64 * sizeof(int);
+  return ((size_t)(two ? 2 : 1) * cap + tf) * sizeof(float) + 64 * sizeof(int);
+}
+
+// Whether the adjoint needs the grid values and the gradient brick at once.
+int needs_two_bricks(int pass, int model, int flags, int gmask) {
+  if (pass == PASS_FWD) return 0;
+  const int mode = flags & DDVR_ADJ_MODE_MASK;
+  const bool need_v = model == DDVR_EMISSION_ABSORPTION || (gmask & (GRAD_CAM | GRAD_STEP)) ||
+                      mode != DDVR_ADJ_AUTO;
+  return need_v && (gmask & GRAD_V) ? 1 : 0;
 }
 
 int grad_mask_of(const ddvr_grads* g) {
@@ -266,7 +263,7 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   }
   if ((rc = check_pending())) return rc;
 
-  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : g_tuning.lds_cap;
   LaunchParams p;
   std::memset(&p, 0, sizeof(p));
   fill_view(p.one, vol, tf, cam, step, model, cap);
@@ -287,15 +284,19 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.grad_mask = grad_mask_of(grads);
   if (model != DDVR_EMISSION_ABSORPTION) p.grad_mask &= ~GRAD_TF;
   p.lds_cap = cap;
+  p.lds_two = needs_two_bricks(pass, model, flags, p.grad_mask);
+  p.slab_kmax = g_tuning.slab_kmax;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, flags);
 
+  const size_t lds = lds_bytes(cap, p.lds_two, model, p.one.R);
+  if ((rc = check_lds(lds))) return rc;
   hipError_t e;
   if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, stream)) != hipSuccess)
     return hip_fail(e, "zeroing the fallback queue");
-  e = (hipError_t)launch_render(p, pass, model, vol->dtype, kWaves, p.n_items,
-                                lds_bytes(cap, model, p.one.R), stream);
+  e = (hipError_t)launch_render(p, pass, model, vol->dtype, g_tuning.waves, p.n_items, lds,
+                                stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   if (fb) {
     e = (hipError_t)launch_fallback(p, model, vol->dtype, pass == PASS_FUSED ? 1 : 0, stream);
@@ -372,6 +373,7 @@ int validate_sphere(float yaw, float pitch, float dist, float fovy, int W, int H
 // ===========================================================================
 struct ddvr_batch {
   int model = 0, flags = 0;
+  Tuning tuning;
   std::vector<ViewDesc> views;
   std::vector<int> view_dtype;
   // launch groups: one per storage dtype, each a contiguous range of `work`
@@ -428,6 +430,30 @@ int ddvr_camera_grad_to_sphere(float yaw, float pitch, float dist, float fovy, i
     for (int j = 0; j < 12; ++j) acc += f[j].d[k] * (double)d_frame[j];
     d_sphere[k] = (float)acc;
   }
+  return DDVR_OK;
+}
+
+int ddvr_set_tuning(const ddvr_tuning* t) {
+  if (!t) return fail(DDVR_ERR_NULL, "tuning is NULL");
+  if (t->waves != 1 && t->waves != 2 && t->waves != 4)
+    return fail(DDVR_ERR_VALUE, "waves must be 1, 2 or 4");
+  if (t->lds_cap < 64 || t->lds_cap > 16384)
+    return fail(DDVR_ERR_VALUE, "lds_cap must be in [64, 16384] voxels");
+  if (t->slab_k < 4 || t->slab_kmax < t->slab_k || t->slab_kmax > 4096)
+    return fail(DDVR_ERR_VALUE, "need 4 <= slab_k <= slab_kmax <= 4096");
+  g_tuning.waves = t->waves;
+  g_tuning.lds_cap = t->lds_cap;
+  g_tuning.slab_k = t->slab_k;
+  g_tuning.slab_kmax = t->slab_kmax;
+  return DDVR_OK;
+}
+
+int ddvr_get_tuning(ddvr_tuning* t) {
+  if (!t) return fail(DDVR_ERR_NULL, "tuning is NULL");
+  t->waves = g_tuning.waves;
+  t->lds_cap = g_tuning.lds_cap;
+  t->slab_k = g_tuning.slab_k;
+  t->slab_kmax = g_tuning.slab_kmax;
   return DDVR_OK;
 }
 
@@ -507,9 +533,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
   if (model == DDVR_EMISSION_ABSORPTION)
     for (int i = 0; i < ntf; ++i)
       if ((rc = validate_tf(&tfs[i], model))) return rc;
-  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : g_tuning.lds_cap;
   ddvr_batch* b = new (std::nothrow) ddvr_batch;
   if (!b) return fail(DDVR_ERR_VALUE, "out of host memory");
+  b->tuning = g_tuning;
   b->model = model;
   b->flags = flags;
   b->views.resize(nview);
@@ -613,18 +640,24 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.views = b->d_views;
   p.flags = b->flags;
   p.grad_mask = b->grad_mask;
-  p.lds_cap = (b->flags & DDVR_LAUNCH_PLAIN) ? 0 : kLdsCap;
+  p.lds_cap = (b->flags & DDVR_LAUNCH_PLAIN) ? 0 : b->tuning.lds_cap;
+  p.lds_two = needs_two_bricks(pass, b->model, b->flags, b->grad_mask);
+  p.slab_kmax = b->tuning.slab_kmax;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, b->flags);
+  for (const auto& g : b->groups) {
+    const int rc = check_lds(lds_bytes(p.lds_cap, p.lds_two, b->model, g.maxR));
+    if (rc) return rc;
+  }
   hipError_t e;
   if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, s)) != hipSuccess)
     return hip_fail(e, "zeroing the fallback queue");
   for (const auto& g : b->groups) {
     p.work = b->d_work + g.first;
     p.n_items = g.count;
-    e = (hipError_t)launch_render(p, pass, b->model, g.dtype, kWaves, g.count,
-                                  lds_bytes(p.lds_cap, b->model, g.maxR), s);
+    e = (hipError_t)launch_render(p, pass, b->model, g.dtype, b->tuning.waves, g.count,
+                                  lds_bytes(p.lds_cap, p.lds_two, b->model, g.maxR), s);
     if (e != hipSuccess) return hip_fail(e, "batch render launch");
     if (fb) {
       e = (hipError_t)launch_fallback(p, b->model, g.dtype, pass == PASS_FUSED ? 1 : 0, s);

@@ -31,7 +31,7 @@ struct ViewDesc {
   float* dstep;           // [1]
   // tiling
   int32_t tiles_x, tiles_y;
-  int32_t slab_k;         // samples per slab (LDS staging granularity)
+  int32_t slab_k;         // initial samples per slab (adapted per slab in the kernel)
   int32_t pad_;
 };
 
@@ -43,7 +43,9 @@ struct LaunchParams {
   int32_t n_items;        // number of tiles in the launch
   int32_t flags;          // adjoint mode | launch flags
   int32_t grad_mask;      // bit 0 dV, 1 dTF, 2 camera, 3 step
-  int32_t lds_cap;        // voxels per LDS staging buffer (0 = never stage)
+  int32_t lds_cap;        // voxels per LDS brick (0 = never stage)
+  int32_t lds_two;        // 1: separate brick regions for grid values and gradients
+  int32_t slab_kmax;      // longest slab (samples per ray) the adaptive march tries
   float loss_scale;       // fused L2
   double* loss_out;       // fused L2 accumulator or null
   // checkpoint fallback queue (workspace)

@@ -296,19 +296,22 @@ __device__ __forceinline__ void wg_sum_n(float* v, int n, float* scratch) {
     }
 }
 
-// Sample range [a, b) of a ray in slab s: samples are grouped by their index
-// offset relative to the earliest entry point of the tile.
-__device__ __forceinline__ void slab_range(int s, int K, int off, int N, int& a, int& b) {
-  a = min(max(s * K - off, 0), N);
-  b = min(max((s + 1) * K - off, 0), N);
+// Samples of a ray inside the slab [lo, hi) of tile sample offsets: the
+// tile's samples are grouped by their index offset from the earliest entry
+// point of the tile, so a slab is a shell of roughly constant distance from
+// the eye.
+__device__ __forceinline__ void slab_range(int lo, int hi, int off, int N, int& a, int& b) {
+  a = min(max(lo - off, 0), N);
+  b = min(max(hi - off, 0), N);
 }
 
-// Brick of the slab: bounding box of the cells of every sample in the slab.
-// Returns 0 = empty slab, 1 = staged in LDS, 2 = too large (direct access).
-template <int NT, int DT>
-__device__ __forceinline__ int prepare_slab(const ViewDesc& vd, const RayG& r, int a, int b,
-                                            int cap, bool stage_v, float* stage, float* acc,
-                                            int* iscratch, Brick& br) {
+// Bounding box of the cells of every sample in the slab [lo, hi).
+// Returns false if no ray has a sample in it.
+template <int NT>
+__device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, int off, int N,
+                                           int lo, int hi, int* iscratch, Brick& br) {
+  int a, b;
+  slab_range(lo, hi, off, N, a, b);
   int v[6];
   if (a < b) {
     Cell c0, c1;
@@ -324,30 +327,60 @@ __device__ __forceinline__ int prepare_slab(const ViewDesc& vd, const RayG& r, i
     for (int k = 0; k < 6; ++k) v[k] = -0x3fffffff;
   }
   wg_max_n<NT>(v, 6, iscratch);
-  if (v[3] < 0) return 0;
+  if (v[3] < 0) return false;
   br.x0 = -v[0]; br.y0 = -v[1]; br.z0 = -v[2];
   const int bx = v[3] - br.x0 + 1, by = v[4] - br.y0 + 1, bz = v[5] - br.z0 + 1;
   br.bx = bx;
   br.bxy = bx * by;
   br.size = br.bxy * bz;
-  if (cap <= 0 || br.size > cap) return 2;
   br.inv_bx = 1.0f / (float)bx;
   br.inv_bxy = 1.0f / (float)br.bxy;
-  if (stage_v || acc) {
-    const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
-    for (int idx = threadIdx.x; idx < br.size; idx += NT) {
-      if (stage_v) {
-        const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
-        const int rem = idx - z * br.bxy;
-        const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
-        const int x = rem - y * bx;
-        stage[idx] = Vox<DT>::ld(vd.vol, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
-      }
-      if (acc) acc[idx] = 0.0f;
+  return true;
+}
+
+// Choose the next slab of the march: starting at `pos` and running forward
+// (dir = +1: [pos, pos+K)) or backward (dir = -1: [pos-K, pos)), with K
+// halved until the brick fits `cap` voxels and doubled again after a slab
+// that used less than a quarter of it.  Returns 0 = empty slab, 1 = fits
+// (stage in LDS), 2 = does not fit even at the minimum length (direct global
+// access); [lo, hi) is the chosen slab.
+template <int NT>
+__device__ __forceinline__ int pick_slab(const ViewDesc& vd, const RayG& r, int off, int N,
+                                         int pos, int dir, int end, int cap, int& K, int kmax,
+                                         int& lo, int& hi, int* iscratch, Brick& br) {
+  constexpr int kmin = 4;
+  for (;;) {
+    if (dir > 0) { lo = pos; hi = min(pos + K, end); }
+    else { hi = pos; lo = max(pos - K, end); }
+    if (!slab_brick<NT>(vd, r, off, N, lo, hi, iscratch, br)) {
+      K = min(2 * K, kmax);
+      return 0;
     }
+    if (cap > 0 && br.size <= cap) {
+      if (4 * br.size < cap) K = min(2 * K, kmax);
+      return 1;
+    }
+    if (cap <= 0 || K <= kmin) return 2;
+    K = max(K >> 1, kmin);
   }
-  __syncthreads();
-  return 1;
+}
+
+// Stage the brick's grid values (as float32) and/or zero its gradient
+// accumulator.  The caller synchronises before the brick is read.
+template <int NT, int DT>
+__device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br, float* stage,
+                                            float* acc) {
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  for (int idx = threadIdx.x; idx < br.size; idx += NT) {
+    if (stage) {
+      const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
+      const int rem = idx - z * br.bxy;
+      const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
+      const int x = rem - y * br.bx;
+      stage[idx] = Vox<DT>::ld(vd.vol, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
+    }
+    if (acc) acc[idx] = 0.0f;
+  }
 }
 
 template <int NT>
@@ -617,10 +650,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   if (!vd.dcam) gmask &= ~GRAD_CAM;
   if (!vd.dstep) gmask &= ~GRAD_STEP;
 
-  // LDS carve-up
+  // LDS carve-up: one brick region, or two when the adjoint needs the grid
+  // values and a gradient accumulator at the same time
   float* stage = smem;
-  float* acc = smem + cap;
-  float4* tfl = reinterpret_cast<float4*>(smem + 2 * cap);
+  float* acc = smem + (p.lds_two ? cap : 0);
+  float4* tfl = reinterpret_cast<float4*>(smem + (p.lds_two ? 2 * cap : cap));
   float* dtf = smem + 2 * cap + (EA ? 4 * vd.R : 0);
   int* iscratch = reinterpret_cast<int*>(dtf + (EA ? 4 * vd.R : 0));
   float* fscratch = reinterpret_cast<float*>(iscratch);
@@ -642,20 +676,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   setup_ray(vd, px, py, valid, r);
   const bool hit = r.N > 0;
 
-  // slab bookkeeping (shared by both passes)
-  int K, off = 0, nslab;
+  // slab bookkeeping (shared by both passes): sample offsets relative to the
+  // earliest entry point of the tile
+  int off = 0, tile_end;
+  const int kmax = cap > 0 ? max(p.slab_kmax, 4) : kMaxSamples + 1;
   if (cap > 0) {
-    K = vd.slab_k;
     const float tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
     off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
-    int ns = hit ? (off + r.N + K - 1) / K : 0;
-    wg_max_n<NT>(&ns, 1, iscratch);
-    nslab = ns;
-  } else {
-    K = kMaxSamples + 1;
-    int ns = hit ? 1 : 0;
-    wg_max_n<NT>(&ns, 1, iscratch);
-    nslab = ns;
+  }
+  {
+    int e = hit ? off + r.N : 0;
+    wg_max_n<NT>(&e, 1, iscratch);
+    tile_end = e;
   }
   __syncthreads();   // TF table visible
 
@@ -668,13 +700,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
     fs.C[0] = fs.C[1] = fs.C[2] = 0.0f;
     fs.T = 1.0f;
     fs.sigma = 0.0f;
-    for (int s = 0; s < nslab; ++s) {
-      int a, b;
-      slab_range(s, K, off, r.N, a, b);
+    int K = min(vd.slab_k, kmax);
+    for (int pos = 0; pos < tile_end;) {
+      int lo, hi;
       Brick br;
-      const int st = prepare_slab<NT, DT>(vd, r, a, b, cap, true, stage, nullptr, iscratch, br);
-      if (st == 1) march_fwd<MODEL, DT, true>(vd, r, a, b, stage, br, tfl, fs);
-      else if (st == 2) march_fwd<MODEL, DT, false>(vd, r, a, b, stage, br, tfl, fs);
+      const int st = pick_slab<NT>(vd, r, off, r.N, pos, +1, tile_end, cap, K, kmax, lo, hi,
+                                   iscratch, br);
+      int a, b;
+      slab_range(lo, hi, off, r.N, a, b);
+      if (st == 1) {
+        stage_brick<NT, DT>(vd, br, stage, nullptr);
+        __syncthreads();
+        march_fwd<MODEL, DT, true>(vd, r, a, b, stage, br, tfl, fs);
+      } else if (st == 2) {
+        march_fwd<MODEL, DT, false>(vd, r, a, b, stage, br, tfl, fs);
+      }
+      pos = hi;
     }
     float out[4];
     if (EA) {
@@ -753,14 +794,24 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
 
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || mode != DDVR_ADJ_AUTO;
-  for (int s_ = nslab - 1; s_ >= 0; --s_) {
-    int a, b;
-    slab_range(s_, K, off, Nadj, a, b);
+  {
+    int e = Nadj > 0 ? off + Nadj : 0;
+    wg_max_n<NT>(&e, 1, iscratch);
+    tile_end = e;
+  }
+  int K = min(vd.slab_k, kmax);
+  for (int pos = tile_end; pos > 0;) {
+    int lo, hi;
     Brick br;
-    const int st = prepare_slab<NT, DT>(vd, r, a, b, cap, need_v, stage,
-                                        want_dv ? acc : nullptr, iscratch, br);
+    const int st = pick_slab<NT>(vd, r, off, Nadj, pos, -1, 0, cap, K, kmax, lo, hi, iscratch,
+                                 br);
+    pos = lo;
     if (st == 0) continue;
+    int a, b;
+    slab_range(lo, hi, off, Nadj, a, b);
     if (st == 1) {
+      stage_brick<NT, DT>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
+      __syncthreads();
       if (!EA && mode == DDVR_ADJ_AUTO)
         march_adj<MODEL, DT, true, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)

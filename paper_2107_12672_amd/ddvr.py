@@ -29,7 +29,7 @@ EXPORTED = [
     "ddvr_camera_grad_to_sphere", "ddvr_render_forward", "ddvr_adjoint_workspace_size",
     "ddvr_render_adjoint", "ddvr_render_fused_l2", "ddvr_batch_create", "ddvr_batch_destroy",
     "ddvr_batch_workspace_size", "ddvr_batch_run", "ddvr_batch_run_graph",
-    "ddvr_batch_sample_count", "ddvr_cast_volume",
+    "ddvr_batch_sample_count", "ddvr_cast_volume", "ddvr_set_tuning", "ddvr_get_tuning",
 ]
 
 
@@ -55,6 +55,11 @@ class Camera(ctypes.Structure):
 
     def frame(self) -> List[float]:
         return list(self.eye) + list(self.fwd) + list(self.right) + list(self.up)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
+                ("slab_k", ctypes.c_int32), ("slab_kmax", ctypes.c_int32)]
 
 
 class Grads(ctypes.Structure):
@@ -100,6 +105,8 @@ def lib():
         "ddvr_batch_run_graph": ([P, I32, F, P, P, SZ, P], ctypes.c_int),
         "ddvr_batch_sample_count": ([P, P], ctypes.c_int),
         "ddvr_cast_volume": ([P, P, I32, ctypes.c_int64, P], ctypes.c_int),
+        "ddvr_set_tuning": ([P], ctypes.c_int),
+        "ddvr_get_tuning": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -174,6 +181,17 @@ def camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, d_frame: Sequen
     out = (ctypes.c_float * 4)()
     _check(lib().ddvr_camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, df, out))
     return list(out)
+
+
+def set_tuning(waves: int = 4, lds_cap: int = 6144, slab_k: int = 32, slab_kmax: int = 256):
+    t = Tuning(waves, lds_cap, slab_k, slab_kmax)
+    _check(lib().ddvr_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().ddvr_get_tuning(ctypes.byref(t)))
+    return {"waves": t.waves, "lds_cap": t.lds_cap, "slab_k": t.slab_k, "slab_kmax": t.slab_kmax}
 
 
 def cast_volume(src, dst, stream=None):
