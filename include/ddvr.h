@@ -141,12 +141,19 @@ typedef struct {
  *   slab_k     initial samples per ray in a slab (>= 4); the kernel halves it
  *              while a slab's brick exceeds lds_cap and doubles it after small
  *              bricks, up to slab_kmax (<= 4096).
+ *   cell_acc   1: keep a ray's density gradient for its current cell in
+ *              registers and add it to the brick when the ray leaves the cell
+ *              (Sec. 4.4, "on exit of the current cell"); 0: add every sample.
+ *   lane_map   1: the lanes of a wave take every other pixel of the tile;
+ *              0: a wave takes an 8x8 block of adjacent pixels.
  * Results do not depend on the tuning beyond float32 summation order. */
 typedef struct {
   int32_t waves;
   int32_t lds_cap;
   int32_t slab_k;
   int32_t slab_kmax;
+  int32_t cell_acc;
+  int32_t lane_map;
 } ddvr_tuning;
 
 int ddvr_set_tuning(const ddvr_tuning* t);

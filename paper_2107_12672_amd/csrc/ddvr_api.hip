@@ -48,21 +48,49 @@ constexpr int kFallbackSlots = 65536;     // concurrent checkpoint slots
 // Launch shape of the render kernels (process-wide; see ddvr_set_tuning).
 struct Tuning {
   int waves = 4;        // waves per workgroup: 1 -> 8x8, 2 -> 16x8, 4 -> 16x16 pixel tiles
-  int lds_cap = 6144;   // voxels per LDS brick
-  int slab_k = 32;      // initial samples per slab
+  int lds_cap = 12288;  // voxels per LDS brick (clamped to the device's LDS per workgroup)
+  int slab_k = 64;      // initial samples per slab
   int slab_kmax = 256;  // longest slab tried
+  int cell_acc = 1;     // per-cell register accumulation of the density gradient
+  int lane_map = 1;     // interleaved lane -> pixel mapping
 };
 Tuning g_tuning;
 
+size_t lds_bytes(int cap, int two, int model, int R) {
+  const size_t tf = model == DDVR_EMISSION_ABSORPTION ? (size_t)R * 8 : 0;
+  return ((size_t)(two ? 2 : 1) * cap + tf) * sizeof(float) + 64 * sizeof(int);
+}
+
 // Largest dynamic LDS allocation of one workgroup on the current device.
-int check_lds(size_t bytes) {
-  int dev = 0, lim = 0;
+int lds_limit(int* lim) {
+  int dev = 0;
+  *lim = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return hip_fail(e, "querying the LDS limit");
+  return DDVR_OK;
+}
+
+int check_lds(size_t bytes) {
+  int lim = 0, rc = lds_limit(&lim);
+  if (rc) return rc;
   if (bytes > (size_t)lim)
     return fail(DDVR_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS, the device allows %d (lower "
                 "lds_cap or the TF size)", bytes, lim);
+  return DDVR_OK;
+}
+
+// Brick capacity that fits the device next to the TF tables and scratch.
+int fit_cap(int cap, int two, int model, int R, int* out) {
+  *out = cap;
+  if (cap <= 0) return DDVR_OK;
+  int lim = 0, rc = lds_limit(&lim);
+  if (rc) return rc;
+  const size_t fixed = lds_bytes(0, two, model, R);
+  if ((size_t)lim <= fixed + 256 * sizeof(float))
+    return fail(DDVR_ERR_UNSUPPORTED, "TF of %d entries leaves no LDS for bricks", R);
+  const int most = (int)((lim - fixed) / ((two ? 2 : 1) * sizeof(float)));
+  *out = std::min(cap, most);
   return DDVR_OK;
 }
 
@@ -150,10 +178,6 @@ void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_
   d.slab_k = cap > 0 ? g_tuning.slab_k : kMaxSamples + 1;
 }
 
-size_t lds_bytes(int cap, int two, int model, int R) {
-  const size_t tf = model == DDVR_EMISSION_ABSORPTION ? (size_t)R * 8 : 0;
-  return ((size_t)(two ? 2 : 1) * cap + tf) * sizeof(float) + 64 * sizeof(int);
-}
 
 // Whether the adjoint needs the grid values and the gradient brick at once.
 int needs_two_bricks(int pass, int model, int flags, int gmask) {
@@ -283,14 +307,16 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.flags = flags;
   p.grad_mask = grad_mask_of(grads);
   if (model != DDVR_EMISSION_ABSORPTION) p.grad_mask &= ~GRAD_TF;
-  p.lds_cap = cap;
   p.lds_two = needs_two_bricks(pass, model, flags, p.grad_mask);
+  if ((rc = fit_cap(cap, p.lds_two, model, p.one.R, &p.lds_cap))) return rc;
   p.slab_kmax = g_tuning.slab_kmax;
+  p.cell_acc = g_tuning.cell_acc;
+  p.lane_map = g_tuning.lane_map;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, flags);
 
-  const size_t lds = lds_bytes(cap, p.lds_two, model, p.one.R);
+  const size_t lds = lds_bytes(p.lds_cap, p.lds_two, model, p.one.R);
   if ((rc = check_lds(lds))) return rc;
   hipError_t e;
   if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, stream)) != hipSuccess)
@@ -441,10 +467,14 @@ int ddvr_set_tuning(const ddvr_tuning* t) {
     return fail(DDVR_ERR_VALUE, "lds_cap must be in [64, 16384] voxels");
   if (t->slab_k < 4 || t->slab_kmax < t->slab_k || t->slab_kmax > 4096)
     return fail(DDVR_ERR_VALUE, "need 4 <= slab_k <= slab_kmax <= 4096");
+  if ((t->cell_acc != 0 && t->cell_acc != 1) || (t->lane_map != 0 && t->lane_map != 1))
+    return fail(DDVR_ERR_VALUE, "cell_acc and lane_map are 0 or 1");
   g_tuning.waves = t->waves;
   g_tuning.lds_cap = t->lds_cap;
   g_tuning.slab_k = t->slab_k;
   g_tuning.slab_kmax = t->slab_kmax;
+  g_tuning.cell_acc = t->cell_acc;
+  g_tuning.lane_map = t->lane_map;
   return DDVR_OK;
 }
 
@@ -454,6 +484,8 @@ int ddvr_get_tuning(ddvr_tuning* t) {
   t->lds_cap = g_tuning.lds_cap;
   t->slab_k = g_tuning.slab_k;
   t->slab_kmax = g_tuning.slab_kmax;
+  t->cell_acc = g_tuning.cell_acc;
+  t->lane_map = g_tuning.lane_map;
   return DDVR_OK;
 }
 
@@ -640,9 +672,17 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.views = b->d_views;
   p.flags = b->flags;
   p.grad_mask = b->grad_mask;
-  p.lds_cap = (b->flags & DDVR_LAUNCH_PLAIN) ? 0 : b->tuning.lds_cap;
   p.lds_two = needs_two_bricks(pass, b->model, b->flags, b->grad_mask);
+  {
+    int maxR = 2;
+    for (const auto& g : b->groups) maxR = std::max(maxR, g.maxR);
+    const int rc = fit_cap((b->flags & DDVR_LAUNCH_PLAIN) ? 0 : b->tuning.lds_cap, p.lds_two,
+                           b->model, maxR, &p.lds_cap);
+    if (rc) return rc;
+  }
   p.slab_kmax = b->tuning.slab_kmax;
+  p.cell_acc = b->tuning.cell_acc;
+  p.lane_map = b->tuning.lane_map;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, b->flags);

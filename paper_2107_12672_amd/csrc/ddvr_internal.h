@@ -46,6 +46,8 @@ struct LaunchParams {
   int32_t lds_cap;        // voxels per LDS brick (0 = never stage)
   int32_t lds_two;        // 1: separate brick regions for grid values and gradients
   int32_t slab_kmax;      // longest slab (samples per ray) the adaptive march tries
+  int32_t cell_acc;       // 1: density gradient kept in registers per cell
+  int32_t lane_map;       // 1: lanes of a wave on every other pixel
   float loss_scale;       // fused L2
   double* loss_out;       // fused L2 accumulator or null
   // checkpoint fallback queue (workspace)

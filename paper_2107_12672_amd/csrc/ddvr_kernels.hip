@@ -448,7 +448,43 @@ struct AdjState {
   // TF gradient of the current segment (registers, flushed on change)
   int tj;
   float tg0[4], tg1[4];
+  // density gradient of the current cell (registers, flushed on cell exit)
+  int64_t ckey;    // LDS brick offset or global index of the cell's corner 0; -1: none
+  float cg[8];
 };
+
+// Add the registered density gradient of the current cell to the LDS brick
+// (LDS) or to global memory (direct slabs), then clear it.
+template <bool LDS>
+__device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, float* acc,
+                                           AdjState& s) {
+  if (s.ckey < 0) return;
+  if (LDS) {
+    const int base = (int)s.ckey;
+    atomicAdd(acc + base, s.cg[0]);
+    atomicAdd(acc + base + 1, s.cg[1]);
+    atomicAdd(acc + base + br.bx, s.cg[2]);
+    atomicAdd(acc + base + br.bx + 1, s.cg[3]);
+    atomicAdd(acc + base + br.bxy, s.cg[4]);
+    atomicAdd(acc + base + br.bxy + 1, s.cg[5]);
+    atomicAdd(acc + base + br.bxy + br.bx, s.cg[6]);
+    atomicAdd(acc + base + br.bxy + br.bx + 1, s.cg[7]);
+  } else {
+    const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+    float* g = vd.dV + s.ckey;
+    atomicAdd(g, s.cg[0]);
+    atomicAdd(g + 1, s.cg[1]);
+    atomicAdd(g + sy, s.cg[2]);
+    atomicAdd(g + sy + 1, s.cg[3]);
+    atomicAdd(g + sz, s.cg[4]);
+    atomicAdd(g + sz + 1, s.cg[5]);
+    atomicAdd(g + sz + sy, s.cg[6]);
+    atomicAdd(g + sz + sy + 1, s.cg[7]);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
+  s.ckey = -1;
+}
 
 __device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
   if (s.tj >= 0) {
@@ -468,7 +504,8 @@ template <int MODEL, int DT, bool LDS, int MODE>
 __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, int i,
                                            const float* stage, float* acc, const Brick& br,
                                            const float4* tfl, float* dtf, int gmask,
-                                           bool need_v, AdjState& s, float Ti_given) {
+                                           bool need_v, bool cell_acc, AdjState& s,
+                                           float Ti_given) {
   Cell c;
   locate(r, i, vd.nx, vd.ny, vd.nz, c);
   const bool need_xhat = (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
@@ -538,7 +575,20 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
       d_hat = tau_hat;
     }
   }
-  if (gmask & GRAD_V) {
+  if ((gmask & GRAD_V) && cell_acc) {
+    // accumulate while the ray stays in this cell (Sec. 4.4: per-ray registers
+    // flushed on exit of the current cell)
+    float w[8];
+    trilerp_weights(c.f, w);
+    const int64_t key = LDS ? (int64_t)base
+                            : (int64_t)c.k[2] * vd.nx * vd.ny + (int64_t)c.k[1] * vd.nx + c.k[0];
+    if (key != s.ckey) {
+      cell_flush<LDS>(vd, br, acc, s);
+      s.ckey = key;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s.cg[k] = fmaf(w[k], d_hat, s.cg[k]);
+  } else if (gmask & GRAD_V) {
     float w[8];
     trilerp_weights(c.f, w);
     if (LDS) {
@@ -581,9 +631,11 @@ template <int MODEL, int DT, bool LDS, int MODE>
 __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int a, int b,
                                           const float* stage, float* acc, const Brick& br,
                                           const float4* tfl, float* dtf, int gmask, bool need_v,
-                                          AdjState& s) {
+                                          bool cell_acc, AdjState& s) {
   for (int i = b - 1; i >= a; --i)
-    adj_sample<MODEL, DT, LDS, MODE>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v, s, 0.0f);
+    adj_sample<MODEL, DT, LDS, MODE>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v,
+                                     cell_acc, s, 0.0f);
+  if (cell_acc) cell_flush<LDS>(vd, br, acc, s);   // the brick changes with the slab
 }
 
 // Camera adjoint of one ray (last line of Alg. 2 on [x_o_hat; omega_hat]).
@@ -655,7 +707,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   float* stage = smem;
   float* acc = smem + (p.lds_two ? cap : 0);
   float4* tfl = reinterpret_cast<float4*>(smem + (p.lds_two ? 2 * cap : cap));
-  float* dtf = smem + 2 * cap + (EA ? 4 * vd.R : 0);
+  float* dtf = reinterpret_cast<float*>(tfl) + (EA ? 4 * vd.R : 0);
   int* iscratch = reinterpret_cast<int*>(dtf + (EA ? 4 * vd.R : 0));
   float* fscratch = reinterpret_cast<float*>(iscratch);
 
@@ -668,8 +720,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
 
   const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int px = tx * TW + (wid % TileShape<WAVES>::BX) * 8 + (lane & 7);
-  const int py = ty * TH + (wid / TileShape<WAVES>::BX) * 8 + (lane >> 3);
+  // lane -> pixel: each wave an 8x8 block of the tile, or (lane_map = 1) an
+  // 8x8 lattice of every other pixel, so that the lanes of a wave are two
+  // pixels apart and collide less on shared grid corners
+  int px, py;
+  if (p.lane_map && WAVES > 1) {
+    px = tx * TW + 2 * (lane & 7) + (wid % TileShape<WAVES>::BX);
+    py = ty * TH + (TileShape<WAVES>::BY == 2 ? 2 * (lane >> 3) + wid / 2 : (lane >> 3));
+  } else {
+    px = tx * TW + (wid % TileShape<WAVES>::BX) * 8 + (lane & 7);
+    py = ty * TH + (wid / TileShape<WAVES>::BX) * 8 + (lane >> 3);
+  }
   const bool valid = px < vd.W && py < vd.H;
   const int64_t pix = (int64_t)py * vd.W + px;
   RayG r;
@@ -792,6 +853,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   s.tj = -1;
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
+  s.ckey = -1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
 
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || mode != DDVR_ADJ_AUTO;
   {
@@ -813,20 +877,26 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
       stage_brick<NT, DT>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
       if (!EA && mode == DDVR_ADJ_AUTO)
-        march_adj<MODEL, DT, true, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, true, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                      p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
-        march_adj<MODEL, DT, true, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, true, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                      p.cell_acc, s);
       else
-        march_adj<MODEL, DT, true, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, true, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                      p.cell_acc, s);
       __syncthreads();
       if (want_dv) flush_brick<NT>(vd, br, acc);
     } else {
       if (!EA && mode == DDVR_ADJ_AUTO)
-        march_adj<MODEL, DT, false, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, false, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                       p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
-        march_adj<MODEL, DT, false, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, false, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                       p.cell_acc, s);
       else
-        march_adj<MODEL, DT, false, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v, s);
+        march_adj<MODEL, DT, false, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+                                       p.cell_acc, s);
     }
   }
   if (EA && (gmask & GRAD_TF)) tf_flush(s, dtf);
@@ -913,6 +983,8 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
     s.dstep = 0.0f;
     s.tj = -1;
     for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
+    s.ckey = -1;
+    for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
     Brick br{};
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int i0 = sg * K, i1 = min(N, i0 + K);
@@ -929,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       }
       for (int i = i1 - 1; i >= i0; --i)
         adj_sample<MODEL, DT, false, 3>(vd, r, i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
-                                        true, s, tseg[i - i0]);
+                                        true, false, s, tseg[i - i0]);
     }
     if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
     if (gmask & (GRAD_CAM | GRAD_STEP)) {

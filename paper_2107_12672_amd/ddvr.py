@@ -59,7 +59,8 @@ class Camera(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
-                ("slab_k", ctypes.c_int32), ("slab_kmax", ctypes.c_int32)]
+                ("slab_k", ctypes.c_int32), ("slab_kmax", ctypes.c_int32),
+                ("cell_acc", ctypes.c_int32), ("lane_map", ctypes.c_int32)]
 
 
 class Grads(ctypes.Structure):
@@ -183,15 +184,22 @@ def camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, d_frame: Sequen
     return list(out)
 
 
-def set_tuning(waves: int = 4, lds_cap: int = 6144, slab_k: int = 32, slab_kmax: int = 256):
-    t = Tuning(waves, lds_cap, slab_k, slab_kmax)
+TUNING_DEFAULT = {"waves": 4, "lds_cap": 12288, "slab_k": 64, "slab_kmax": 256, "cell_acc": 1,
+                  "lane_map": 1}
+
+
+def set_tuning(**kw):
+    """Set the process-wide launch shape; unspecified fields keep their value."""
+    cur = get_tuning()
+    cur.update(kw)
+    t = Tuning(*[int(cur[f]) for f, _ in Tuning._fields_])
     _check(lib().ddvr_set_tuning(ctypes.byref(t)))
 
 
 def get_tuning() -> dict:
     t = Tuning()
     _check(lib().ddvr_get_tuning(ctypes.byref(t)))
-    return {"waves": t.waves, "lds_cap": t.lds_cap, "slab_k": t.slab_k, "slab_kmax": t.slab_kmax}
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
 
 def cast_volume(src, dst, stream=None):

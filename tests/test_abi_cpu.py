@@ -166,3 +166,22 @@ def test_batch_create_validation():
     assert L.ddvr_batch_create(vols, 1, tfs, 1, bad, 1, 1, 0, None, None, None, B(h)) == d.ERR_NULL
     assert L.ddvr_batch_create(vols, 1, None, 0, views, 1, 1, 0, None, None, None, B(h)) == d.ERR_NULL
     assert L.ddvr_batch_create(vols, 1, tfs, 1, views, 1, 1, 0, None, None, None, None) == d.ERR_NULL
+
+
+def test_tuning_roundtrip_and_validation():
+    d = _ddvr()
+    L = d.lib()
+    old = d.get_tuning()
+    try:
+        d.set_tuning(waves=2, lds_cap=4096, slab_k=16, slab_kmax=64, cell_acc=0, lane_map=0)
+        assert d.get_tuning() == {"waves": 2, "lds_cap": 4096, "slab_k": 16, "slab_kmax": 64,
+                                  "cell_acc": 0, "lane_map": 0}
+        for bad in ({"waves": 3}, {"lds_cap": 10}, {"lds_cap": 1 << 20}, {"slab_k": 2},
+                    {"slab_k": 128, "slab_kmax": 64}, {"cell_acc": 2}, {"lane_map": -1}):
+            with pytest.raises(d.DDVRError) as ei:
+                d.set_tuning(**bad)
+            assert ei.value.status == d.ERR_VALUE
+        assert L.ddvr_set_tuning(None) == d.ERR_NULL
+    finally:
+        d.set_tuning(**old)
+    assert d.get_tuning() == old
