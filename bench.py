@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-views", type=int, default=0,
                     help="views of the plain path to time (0 = all)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a float32 copy of MIB MiB through the library (3 times), "
+                         "to calibrate HBM byte counters, and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -123,6 +126,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            d.cast_volume(src, dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
     work = synth.make_c3(args.n, args.views, args.image, args.step_vox)
     W = H = args.image
     nv = len(work.views)
