@@ -137,7 +137,8 @@ def render(volume, tf, cam, W, H, step, model, pix=None):
     return {"image": image, "trans": trans, "nsamp": nsamp, "ratio": ratio}
 
 
-def adjoint(volume, tf, cam, W, H, step, model, d_image, variant=TAPE, pix=None, ck_K=0):
+def adjoint(volume, tf, cam, W, H, step, model, d_image, variant=TAPE, pix=None, ck_K=0,
+            want_dV=True):
     """Gradients of <d_image, image> -> dict(dV, dTF, dcam, dstep)."""
     V = _f64(volume)
     nz, ny, nx = V.shape
@@ -146,7 +147,7 @@ def adjoint(volume, tf, cam, W, H, step, model, d_image, variant=TAPE, pix=None,
     cam = _f64(cam)
     p, npix = _pix(pix)
     g = _f64(d_image)
-    dV = np.zeros_like(V)
+    dV = np.zeros_like(V) if want_dV else None
     dTF = np.zeros((max(R, 1), 4), np.float64) if T is not None else None
     dcam = np.zeros(12, np.float64)
     dstep = np.zeros(1, np.float64)

@@ -309,8 +309,10 @@ struct GradAcc {
   std::vector<double> dV, dTF;
   double dcam[12];
   double dstep;
-  void init(size_t nv, size_t ntf) {
-    dV.assign(nv, 0.0); dTF.assign(ntf, 0.0);
+  bool want_dV = true;
+  void init(size_t nv, size_t ntf, bool with_dV) {
+    want_dV = with_dV;
+    dV.assign(with_dV ? nv : 0, 0.0); dTF.assign(ntf, 0.0);
     std::fill(dcam, dcam + 12, 0.0); dstep = 0.0;
   }
 };
@@ -351,7 +353,7 @@ void adjoint_below_blend(const Grid& g, const double* V, const double* T, int R,
         double wy = cy ? c.f[1] : 1.0 - c.f[1];
         double wz = cz ? c.f[2] : 1.0 - c.f[2];
         int64_t id = vidx(g, c.k[0] + cx, c.k[1] + cy, c.k[2] + cz);
-        acc.dV[id] += wx * wy * wz * d_hat;
+        if (acc.want_dV) acc.dV[id] += wx * wy * wz * d_hat;
         double v = V[id];
         dd_df[0] += (cx ? 1.0 : -1.0) * wy * wz * v;
         dd_df[1] += wx * (cy ? 1.0 : -1.0) * wz * v;
@@ -621,12 +623,17 @@ int oracle_adjoint(const double* V, int nx, int ny, int nz, const double* tf, in
   const int C = ea ? 4 : 1;
   const size_t nv = size_t(nx) * ny * nz;
   const size_t ntf = ea ? size_t(R) * 4 : 0;
-  const int nt = nthreads_max();
+  // one float64 gradient copy per thread; bound their total to ~2 GiB so that
+  // sparse pixel sets on large grids stay cheap
+  int nt = nthreads_max();
+  const double copy_bytes = 8.0 * double((dV ? nv : 0) + ntf) + 1.0;
+  nt = std::max(1, std::min(nt, int((2.0 * (1 << 30)) / copy_bytes)));
+  nt = int(std::max<int64_t>(1, std::min<int64_t>(nt, (n + 63) / 64)));
   std::vector<GradAcc> accs(nt);
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
   {
     GradAcc& acc = accs[thread_id()];
-    acc.init(nv, ntf);
+    acc.init(nv, ntf, dV != nullptr);
 #pragma omp for schedule(dynamic, 16)
     for (int64_t q = 0; q < n; ++q) {
       const int64_t p = pix ? int64_t(pix[q]) : q;

@@ -5,3 +5,4 @@ The rendering and its adjoint run in the HIP library ``libddvr.so``
 binding and :mod:`paper_2107_12672_amd.autograd` the PyTorch autograd wrapper.
 """
 from . import ddvr  # noqa: F401
+from . import autograd  # noqa: F401

@@ -1,0 +1,130 @@
+"""PyTorch autograd wrappers over the C ABI (the paper exposes its renderer as
+a PyTorch custom operation with a backward pass, Sec. 4.4 last paragraph).
+
+* :class:`SphereCamera` -- camera frame (12 floats: eye, fwd, right, up) from
+  a pose on the enclosing sphere (yaw, pitch, dist, fovy in radians; Sec. 5.1);
+  backward runs ``ddvr_camera_grad_to_sphere``.
+* :class:`DDVRFunction` -- forward = ``ddvr_render_forward`` on the stored copy
+  of a float32 master grid (f32 / f16 / bf16 storage, cast by
+  ``ddvr_cast_volume``); backward = ``ddvr_render_adjoint`` in AUTO mode, i.e.
+  the inversion trick with the segment-checkpoint fallback for nearly opaque
+  rays.  Gradients are returned in float32 for the master grid.
+
+All arithmetic runs in the HIP library; these classes only allocate outputs
+and pass pointers.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import ddvr as _d
+
+
+def _camera_struct(frame: torch.Tensor, width: int, height: int) -> _d.Camera:
+    f = [float(x) for x in frame.detach().to("cpu", torch.float64).tolist()]
+    cam = _d.Camera()
+    for a in range(3):
+        cam.eye[a], cam.fwd[a], cam.right[a], cam.up[a] = f[a], f[3 + a], f[6 + a], f[9 + a]
+    cam.width, cam.height = int(width), int(height)
+    return cam
+
+
+class SphereCamera(torch.autograd.Function):
+    """(yaw, pitch, dist, fovy) scalar tensors -> frame [12] (float32, CPU)."""
+
+    @staticmethod
+    def forward(ctx, yaw, pitch, dist, fovy, width: int, height: int):
+        vals = [float(t) for t in (yaw, pitch, dist, fovy)]
+        cam = _d.camera_from_sphere(*vals, width, height)
+        ctx.vals = vals
+        ctx.wh = (int(width), int(height))
+        return torch.tensor(cam.frame(), dtype=torch.float32)
+
+    @staticmethod
+    def backward(ctx, g_frame):
+        gs = _d.camera_grad_to_sphere(*ctx.vals, *ctx.wh, g_frame.to("cpu").tolist())
+        out = [torch.tensor(v, dtype=torch.float32) for v in gs]
+        return out[0], out[1], out[2], out[3], None, None
+
+
+class DDVRFunction(torch.autograd.Function):
+    """image = render(volume, tf, frame, step).
+
+    volume  float32 [nz][ny][nx] device tensor (the master copy)
+    tf      float32 [R][4] device tensor, or None (absorption-only)
+    frame   float32 [12] tensor (any device) -- camera frame
+    step    scalar tensor, world units
+    Returns [H][W][4] (emission-absorption) or [H][W] (absorption-only).
+    """
+
+    @staticmethod
+    def forward(ctx, volume, tf, frame, step, model: int, width: int, height: int,
+                storage: torch.dtype = torch.float32, flags: int = 0):
+        if not volume.is_cuda:
+            raise ValueError("volume must be a device tensor")
+        volume = volume.contiguous()
+        if volume.dtype != torch.float32:
+            raise ValueError("the master grid is float32; choose the stored form with `storage`")
+        if storage == torch.float32:
+            stored = volume
+        else:
+            stored = torch.empty_like(volume, dtype=storage)
+            _d.cast_volume(volume, stored)
+        if model == _d.EMISSION_ABSORPTION:
+            if tf is None:
+                raise ValueError("emission-absorption needs a transfer function")
+            tf = tf.contiguous()
+        cam = _camera_struct(frame, width, height)
+        C = 4 if model == _d.EMISSION_ABSORPTION else 1
+        image = torch.empty((height, width, C) if C == 4 else (height, width),
+                            device=volume.device, dtype=torch.float32)
+        trans = torch.empty((height, width), device=volume.device, dtype=torch.float32)
+        s = float(step)
+        _d.render_forward(stored, tf, cam, s, model, image, trans, flags=flags & _d.LAUNCH_PLAIN)
+        ctx.save_for_backward(stored, tf if tf is not None else torch.empty(0), image, trans)
+        ctx.has_tf = tf is not None
+        ctx.cam = cam
+        ctx.step = s
+        ctx.model = model
+        ctx.flags = flags
+        ctx.frame_device = frame.device
+        ctx.step_device = step.device if isinstance(step, torch.Tensor) else torch.device("cpu")
+        return image
+
+    @staticmethod
+    def backward(ctx, g_image):
+        stored, tf, image, trans = ctx.saved_tensors
+        tf = tf if ctx.has_tf else None
+        need_v, need_tf, need_cam, need_step = ctx.needs_input_grad[:4]
+        dev = stored.device
+        dV = torch.zeros(stored.shape, device=dev, dtype=torch.float32) if need_v else None
+        dTF = torch.zeros_like(tf) if (need_tf and tf is not None) else None
+        dcam = torch.zeros(12, device=dev, dtype=torch.float32) if need_cam else None
+        dstep = torch.zeros(1, device=dev, dtype=torch.float32) if need_step else None
+        if dV is None and dTF is None and dcam is None and dstep is None:
+            return (None,) * 9
+        n = _d.adjoint_workspace_size(stored, ctx.cam, ctx.step, ctx.model, ctx.flags)
+        ws = torch.empty((n + 3) // 4, device=dev, dtype=torch.int32) if n else None
+        _d.render_adjoint(stored, tf, ctx.cam, ctx.step, ctx.model, image, trans,
+                          g_image.contiguous().to(torch.float32),
+                          _d.grads_desc(dV, dTF, dcam, dstep), flags=ctx.flags, workspace=ws)
+        g_frame = dcam.to(ctx.frame_device) if dcam is not None else None
+        g_step = dstep.reshape(()).to(ctx.step_device) if dstep is not None else None
+        return dV, dTF, g_frame, g_step, None, None, None, None, None
+
+
+def camera_frame(yaw, pitch, dist, fovy, width: int, height: int) -> torch.Tensor:
+    """Differentiable camera frame from a sphere pose (radians)."""
+    t = [x if isinstance(x, torch.Tensor) else torch.tensor(float(x)) for x in (yaw, pitch, dist, fovy)]
+    return SphereCamera.apply(t[0], t[1], t[2], t[3], width, height)
+
+
+def render(volume: torch.Tensor, tf: Optional[torch.Tensor], frame: torch.Tensor, step,
+           model: int, width: int, height: int, storage: torch.dtype = torch.float32,
+           flags: int = 0) -> torch.Tensor:
+    """Differentiable render of one view (see DDVRFunction)."""
+    if not isinstance(step, torch.Tensor):
+        step = torch.tensor(float(step))
+    return DDVRFunction.apply(volume, tf, frame, step, model, width, height, storage, flags)

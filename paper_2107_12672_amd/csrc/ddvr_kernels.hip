@@ -442,9 +442,12 @@ struct AdjState {
   float Tn;        // T^(i+1) (inversion state)
   float an;        // alpha^(i+1) (alpha-form inversion state)
   float P;         // absorption-only closed form: T^(i+1)*ahat^(i+1), constant
-  float xo_hat[3]; // sum of position adjoints
-  float si[3];     // sum of i * position adjoints
-  float dstep;     // Beer-Lambert part of the step adjoint
+  // Ray sums behind the camera and step gradients, kept in float64: they add
+  // up to thousands of terms of both signs (weighted by i), and float32 would
+  // lose ~1e-3 of the result to cancellation on long rays.
+  double xo_hat[3]; // sum of position adjoints
+  double si[3];     // sum of i * position adjoints
+  double dstep;     // Beer-Lambert part of the step adjoint
   // TF gradient of the current segment (registers, flushed on change)
   int tj;
   float tg0[4], tg1[4];
@@ -523,7 +526,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     // T^(i)*e_i*ahat^(i+1) = T^(i+1)*ahat^(i+1) is invariant under the
     // inversion T^(i) = T^(i+1)/e_i, ahat^(i) = e_i*ahat^(i+1) (no emission).
     d_hat = vd.step * s.P;
-    s.dstep += d * s.P;
+    s.dstep += (double)(d * s.P);
   } else {
     float rgb[3] = {0.0f, 0.0f, 0.0f}, tau;
     TFv t;
@@ -552,7 +555,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     s.ahat = fmaf(e, s.ahat, -alpha * rc);              // ahat^(i)
     const float ase = as_hat * e;
     const float tau_hat = ase * vd.step;
-    s.dstep = fmaf(ase, tau, s.dstep);
+    s.dstep += (double)(ase * tau);
     if (MODEL == DDVR_EMISSION_ABSORPTION) {
       const float w = alpha * Ti;
       const float g4[4] = {w * s.Chat[0], w * s.Chat[1], w * s.Chat[2], tau_hat};
@@ -621,8 +624,8 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float xh = sc * gd[a];
-      s.xo_hat[a] += xh;
-      s.si[a] = fmaf(fi, xh, s.si[a]);
+      s.xo_hat[a] += (double)xh;
+      s.si[a] += (double)fi * (double)xh;
     }
   }
 }
@@ -645,14 +648,15 @@ __device__ __forceinline__ void camera_adjoint(const ViewDesc& vd, const RayG& r
 #pragma unroll
   for (int k = 0; k < 13; ++k) out[k] = 0.0f;
   if (!hit) return;
-  out[12] = s.dstep + r.om[0] * s.si[0] + r.om[1] * s.si[1] + r.om[2] * s.si[2];
+  out[12] = (float)(s.dstep + (double)r.om[0] * s.si[0] + (double)r.om[1] * s.si[1] +
+                    (double)r.om[2] * s.si[2]);
   float oh[3], eh[3];
   float t0h = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    oh[a] = vd.step * s.si[a] + r.t0 * s.xo_hat[a];
-    eh[a] = s.xo_hat[a];
-    t0h += r.om[a] * s.xo_hat[a];
+    oh[a] = (float)((double)vd.step * s.si[a] + (double)r.t0 * s.xo_hat[a]);
+    eh[a] = (float)s.xo_hat[a];
+    t0h += r.om[a] * (float)s.xo_hat[a];
   }
   if (r.axis >= 0) {
     const float o = r.om[r.axis];
@@ -814,10 +818,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
     for (int ch = 0; ch < C; ++ch) gimg[ch] = vd.d_image[pix * C + ch];
   }
 
-  // choose the adjoint route of this ray
+  // choose the adjoint route of this ray; a ray with a zero upstream gradient
+  // contributes nothing and is skipped
   const int mode = p.flags & DDVR_ADJ_MODE_MASK;
+  const bool seeded = gimg[0] != 0.0f || gimg[1] != 0.0f || gimg[2] != 0.0f || gimg[3] != 0.0f;
   bool fallback = false;
-  if (hit) {
+  if (hit && seeded) {
     if (p.fb_all) fallback = true;
     else if (((EA && mode == DDVR_ADJ_AUTO) || mode == DDVR_ADJ_INVERT_ALPHA) &&
              !(TN >= p.fb_tmin))
@@ -837,7 +843,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
       }
     }
   }
-  const int Nadj = fallback ? 0 : r.N;
+  const int Nadj = (fallback || !seeded) ? 0 : r.N;
 
   AdjState s;
   s.Chat[0] = EA ? gimg[0] : 0.0f;
@@ -847,9 +853,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   s.Tn = TN;
   s.an = 1.0f - TN;
   s.P = TN * s.ahat;
-  s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0f;
-  s.si[0] = s.si[1] = s.si[2] = 0.0f;
-  s.dstep = 0.0f;
+  s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0;
+  s.si[0] = s.si[1] = s.si[2] = 0.0;
+  s.dstep = 0.0;
   s.tj = -1;
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
@@ -978,9 +984,9 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
     s.Chat[2] = EA ? gimg[2] : 0.0f;
     s.ahat = EA ? gimg[3] : gimg[0];
     s.Tn = 0.0f; s.an = 0.0f; s.P = 0.0f;
-    s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0f;
-    s.si[0] = s.si[1] = s.si[2] = 0.0f;
-    s.dstep = 0.0f;
+    s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0;
+    s.si[0] = s.si[1] = s.si[2] = 0.0;
+    s.dstep = 0.0;
     s.tj = -1;
     for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
     s.ckey = -1;

@@ -116,27 +116,19 @@ def ellipsoid_volume(shape_zyx, n_ell: int, rng: np.random.Generator, *,
 
 
 def _value_noise(shape_zyx, lattice: int, rng: np.random.Generator) -> np.ndarray:
-    """Trilinearly upsampled i.i.d. lattice noise (one octave)."""
+    """Trilinearly upsampled i.i.d. lattice noise (one octave), separable."""
     nz, ny, nx = shape_zyx
     lat = rng.uniform(0.0, 1.0, size=(lattice + 1,) * 3)
 
-    def coords(n):
+    def upsample(a, n, axis):
         t = np.arange(n) * (lattice / max(n - 1, 1))
         i = np.minimum(np.floor(t).astype(np.int64), lattice - 1)
-        return i, t - i
+        f = (t - i).reshape([-1 if k == axis else 1 for k in range(3)])
+        return np.take(a, i, axis=axis) * (1.0 - f) + np.take(a, i + 1, axis=axis) * f
 
-    iz, fz = coords(nz)
-    iy, fy = coords(ny)
-    ix, fx = coords(nx)
-    out = np.zeros(shape_zyx, dtype=np.float64)
-    for dz in (0, 1):
-        wz = (fz if dz else 1 - fz)[:, None, None]
-        for dy in (0, 1):
-            wy = (fy if dy else 1 - fy)[None, :, None]
-            for dx in (0, 1):
-                wx = (fx if dx else 1 - fx)[None, None, :]
-                out += wz * wy * wx * lat[np.ix_(iz + dz, iy + dy, ix + dx)]
-    return out
+    out = upsample(lat, nx, 2)
+    out = upsample(out, ny, 1)
+    return upsample(out, nz, 0)
 
 
 def sparse_noise_volume(shape_zyx, rng: np.random.Generator, *,

@@ -17,6 +17,12 @@ not differentiable (interior cell face: the trilinear gradient jumps; TF knot
 or clamp end: the TF slope jumps) have two valid one-sided gradients; float32
 and float64 may pick different sides, so such rays also carry zero upstream
 gradient where camera / step gradients are compared (kink_mask).
+At full size, emission-absorption camera gradients of long rays through steep
+TFs are ill-conditioned away from kinks too: a 1e-7 relative perturbation of
+the camera frame (float32 rounding of the input alone) moves some rays' float64
+camera gradient by more than 1e-3 of its size.  Such rays are screened by
+re-running the oracle at perturbed frames (sensitive_mask) and carry zero
+upstream gradient where camera / step gradients are compared.
 """
 from __future__ import annotations
 
@@ -156,6 +162,33 @@ def kink_mask(p: Problem, pix=None) -> np.ndarray:
     face_tol = 1e-6 * nmax + 1e-4
     knot_tol = 1e-5 * (p.tf.shape[0] if p.tf is not None else 1)
     return (face < face_tol) | (knot < knot_tol)
+
+
+def sensitive_mask(p: Problem, pix, g, rel=1e-7, thresh=1e-3, trials=3, seed=0):
+    """True for rays whose oracle camera / step gradient moves by more than
+    `thresh` (relative to its own size) when the camera frame is perturbed by
+    `rel` relative, the size of float32 rounding.  Such rays are
+    ill-conditioned: no float32 evaluation can match the float64 gradient
+    better than that spread."""
+    V = dequantized(p)
+    cam = oracle_camera(p)
+    rng = np.random.default_rng(seed)
+    out = np.zeros(len(pix), dtype=bool)
+    for q in range(len(pix)):
+        gq = g[q:q + 1]
+        if not np.any(gq):
+            continue
+        base = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, gq, pix=pix[q:q + 1],
+                              want_dV=False)
+        b = np.r_[base["dcam"], base["dstep"]]
+        worst = 0.0
+        for _ in range(trials):
+            pc = cam * (1.0 + rel * rng.normal(size=12))
+            a = oracle.adjoint(V, p.tf, pc, p.W, p.H, p.step, p.model, gq, pix=pix[q:q + 1],
+                               want_dV=False)
+            worst = max(worst, float(np.abs(np.r_[a["dcam"], a["dstep"]] - b).max()))
+        out[q] = worst > thresh * max(float(np.abs(b).max()), 1e-30)
+    return out
 
 
 def tie_mask(ratio: np.ndarray) -> np.ndarray:

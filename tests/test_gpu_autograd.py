@@ -1,0 +1,107 @@
+"""The torch.autograd wrapper on the GPU against the FP64 oracle, and a
+directional finite difference of the oracle's own forward (independent of
+any adjoint) at a full configuration."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from harness import (Problem, assert_dv_close, assert_grad_close, dequantized, kink_mask,
+                     oracle_adjoint, oracle_camera, oracle_forward, tie_mask)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _ea(storage="f32", W=64, H=48):
+    rng = np.random.default_rng(21)
+    vol = synth.blob_volume((36, 40, 32), 5, rng, sigma_world=(0.12, 0.3), amplitude=0.6,
+                            noise=0.02)
+    tf = synth.random_tf(12, rng, 10.0)
+    return Problem(1, vol, storage, tf, 117.0, 28.0, 2.4, 55.0, W, H, 0.5 * 2 / 39)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_autograd_matches_oracle_all_parameters(storage):
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    p = _ea(storage)
+    _say(f"autograd EA storage={storage}")
+    ora = oracle_forward(p)
+    mask = tie_mask(ora["ratio"]) | kink_mask(p)
+    rng = np.random.default_rng(22)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[mask] = 0.0
+    dev = torch.device("cuda")
+    V = torch.from_numpy(p.volume).to(dev).requires_grad_(True)
+    T = torch.from_numpy(p.tf).to(dev).requires_grad_(True)
+    yaw, pitch, dist = (torch.tensor(math.radians(p.yaw), requires_grad=True),
+                        torch.tensor(math.radians(p.pitch), requires_grad=True),
+                        torch.tensor(p.dist, requires_grad=True))
+    step = torch.tensor(p.step, requires_grad=True)
+    frame = ag.camera_frame(yaw, pitch, dist, math.radians(p.fovy), p.W, p.H)
+    sdt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
+    img = ag.render(V, T, frame, step, d.EMISSION_ABSORPTION, p.W, p.H, storage=sdt)
+    gt = torch.from_numpy(g.reshape(p.H, p.W, 4).astype(np.float32)).to(dev)
+    (img * gt).sum().backward()
+    ref = oracle_adjoint(p, g)
+    assert_dv_close(V.grad.double().cpu().numpy(), ref["dV"], "autograd dV")
+    assert_grad_close(T.grad.double().cpu().numpy(), ref["dTF"], "autograd dTF")
+    sph = oracle.sphere_grad(ref["dcam"], p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H)
+    got = np.array([yaw.grad.item(), pitch.grad.item(), dist.grad.item()])
+    assert_grad_close(got, sph[:3], "autograd yaw/pitch/dist", rtol=2e-3)
+    assert_grad_close([step.grad.item()], [ref["dstep"]], "autograd step")
+
+
+def test_directional_derivative_against_oracle_finite_difference_c2():
+    """(L(th + e v) - L(th - e v)) / 2e of the FP64 oracle forward on a pixel
+    subset vs <grad L, v> from the GPU adjoint (autograd path), full C2 size."""
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    w = synth.make_c2()
+    v = w.views[0]
+    p = Problem(1, w.volume, "f32", w.tf, v.yaw, v.pitch, v.dist, v.fovy, v.width, v.height,
+                w.step_world)
+    _say("C2 directional FD")
+    rng = np.random.default_rng(23)
+    pix = np.sort(rng.choice(p.W * p.H, size=1500, replace=False)).astype(np.int32)
+    ora = oracle_forward(p, pix=pix)
+    hit = ora["nsamp"] > 0
+    keep = hit & ~tie_mask(ora["ratio"]) & ~kink_mask(p, pix=pix)
+    pix = pix[keep]
+    wts = rng.normal(size=(pix.size, 4))
+    dev = torch.device("cuda")
+    V = torch.from_numpy(p.volume).to(dev).requires_grad_(True)
+    T = torch.from_numpy(p.tf).to(dev).requires_grad_(True)
+    yaw = torch.tensor(math.radians(p.yaw), requires_grad=True)
+    step = torch.tensor(p.step, requires_grad=True)
+    frame = ag.camera_frame(yaw, math.radians(p.pitch), p.dist, math.radians(p.fovy), p.W, p.H)
+    img = ag.render(V, T, frame, step, d.EMISSION_ABSORPTION, p.W, p.H)
+    gfull = torch.zeros(p.H * p.W, 4, device=dev)
+    gfull[torch.from_numpy(pix.astype(np.int64)).to(dev)] = torch.from_numpy(
+        wts.astype(np.float32)).to(dev)
+    (img.reshape(-1, 4) * gfull).sum().backward()
+    # random direction in (V, TF, yaw, step)
+    dV = rng.normal(size=p.volume.shape) * 0.01
+    dT = rng.normal(size=p.tf.shape) * np.array([0.05, 0.05, 0.05, 0.5])
+    dyaw, dstep = 0.01, 0.01 * p.step
+    lin = float((V.grad.double().cpu().numpy() * dV).sum() + (T.grad.double().cpu().numpy() * dT).sum()
+                + yaw.grad.item() * dyaw + step.grad.item() * dstep)
+
+    def loss(eps):
+        vol = p.volume.astype(np.float64) + eps * dV
+        tf = p.tf.astype(np.float64) + eps * dT
+        cam = oracle.camera_from_sphere(p.yaw + math.degrees(eps * dyaw), p.pitch, p.dist,
+                                        p.fovy, p.W, p.H)
+        out = oracle.render(vol, tf, cam, p.W, p.H, p.step + eps * dstep, 1, pix=pix)
+        return float((out["image"] * wts).sum())
+
+    eps = 1e-4
+    fd = (loss(eps) - loss(-eps)) / (2 * eps)
+    assert abs(fd - lin) <= 2e-3 * abs(fd) + 1e-6, (fd, lin)
