@@ -146,6 +146,11 @@ typedef struct {
  *              (Sec. 4.4, "on exit of the current cell"); 0: add every sample.
  *   lane_map   1: the lanes of a wave take every other pixel of the tile;
  *              0: a wave takes an 8x8 block of adjacent pixels.
+ *   schedule   batches only: 0 auto (2 when views differ in image size or grid,
+ *              else 1), 1 one workgroup per tile with contiguous tile ranges
+ *              per XCD, 2 persistent workgroups popping tiles from a queue
+ *              ordered by estimated samples, longest first.  Batches whose
+ *              grids mix storage types always use 2.
  * Results do not depend on the tuning beyond float32 summation order. */
 typedef struct {
   int32_t waves;
@@ -154,6 +159,7 @@ typedef struct {
   int32_t slab_kmax;
   int32_t cell_acc;
   int32_t lane_map;
+  int32_t schedule;
 } ddvr_tuning;
 
 int ddvr_set_tuning(const ddvr_tuning* t);

@@ -64,7 +64,7 @@ def _load():
     lib.oracle_tf_lookup.argtypes = [p, i, d, p]
     lib.oracle_ray.argtypes = [p, i, i, i, i, i, i, i, d, p]
     lib.oracle_trace_ray.argtypes = [p, i, i, i, p, i, p, i, i, i, i, d, i, i, p, p, p, p]
-    lib.oracle_kinks.argtypes = [p, i, i, i, p, i, p, i, i, d, i, p, i64, p, p]
+    lib.oracle_kinks.argtypes = [p, i, i, i, p, i, p, i, i, d, i, p, i64, p, p, p]
     for f in (lib.oracle_camera_from_sphere, lib.oracle_camera_jacobian, lib.oracle_render,
               lib.oracle_adjoint, lib.oracle_render_dual, lib.oracle_trilinear,
               lib.oracle_tf_lookup, lib.oracle_ray, lib.oracle_num_threads,
@@ -227,9 +227,10 @@ def trace_ray(volume, tf, cam, W, H, px, py, step, model, cap=100000):
     return {"N": N, "d": d[:m], "tau": tau[:m], "T": Tb[:m], "x": x[:3 * m].reshape(m, 3)}
 
 
-def kinks(volume, tf, cam, W, H, step, model, pix=None):
+def kinks(volume, tf, cam, W, H, step, model, pix=None, with_entry=False):
     """Per ray: (min distance of a sample to an interior cell face [voxels],
-    min distance of d*(R-1) to a TF knot [EA])."""
+    min distance of d*(R-1) to a TF knot [EA]) and, with_entry, t0/|omega_a|
+    of the entry plane a."""
     V = _f64(volume)
     nz, ny, nx = V.shape
     T = _f64(tf) if model == EA else None
@@ -238,7 +239,8 @@ def kinks(volume, tf, cam, W, H, step, model, pix=None):
     n = npix if p is not None else W * H
     face = np.zeros(n)
     knot = np.zeros(n)
+    entry = np.zeros(n)
     _check(_load().oracle_kinks(_ptr(V), nx, ny, nz, _ptr(T), R, _ptr(_f64(cam)), int(W), int(H),
-                                float(step), int(model), _ptr(p), npix, _ptr(face), _ptr(knot)),
-           "kinks")
-    return face, knot
+                                float(step), int(model), _ptr(p), npix, _ptr(face), _ptr(knot),
+                                _ptr(entry)), "kinks")
+    return (face, knot, entry) if with_entry else (face, knot)

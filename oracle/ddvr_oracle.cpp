@@ -753,10 +753,12 @@ int oracle_trace_ray(const double* V, int nx, int ny, int nz, const double* tf, 
 // voxels) of the sample to an interior cell face (where the trilinear
 // gradient jumps); knot[q] = min over samples of the distance of
 // u = d*(R-1) to a TF knot 0..R-1 (slope change or clamp end), EA only.
-// Rays that miss get 1e30 in both.
+// Rays that miss get 1e30 in both.  entry[q] (may be NULL) = t0/|omega_a| for
+// the entry plane a (0 when the eye is inside): how much an error in the ray
+// direction is amplified into the entry point.
 int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int R,
                  const double* cam, int W, int H, double step, int model,
-                 const int32_t* pix, int64_t npix, double* face, double* knot) {
+                 const int32_t* pix, int64_t npix, double* face, double* knot, double* entry) {
   const bool ea = model == 1;
   if (!V || !cam || !face || !knot || (ea && !tf)) return -1;
   if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
@@ -782,6 +784,8 @@ int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int 
     }
     face[q] = fmin;
     knot[q] = kmin;
+    if (entry)
+      entry[q] = (r.hit && r.entry_axis >= 0) ? r.t0 / std::fabs(r.omega[r.entry_axis]) : 0.0;
   }
   return 0;
 }

@@ -53,6 +53,7 @@ struct Tuning {
   int slab_kmax = 256;  // longest slab tried
   int cell_acc = 1;     // per-cell register accumulation of the density gradient
   int lane_map = 1;     // interleaved lane -> pixel mapping
+  int schedule = 0;     // batches: 0 auto, 1 one workgroup per tile, 2 persistent queue
 };
 Tuning g_tuning;
 
@@ -161,6 +162,7 @@ void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_
   d.H = c->height;
   d.step = step;
   d.vol = v->data;
+  d.dtype = v->dtype;
   d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
   const int nmax = std::max(v->nx, std::max(v->ny, v->nz));
   const double h = 2.0 / (nmax - 1);
@@ -304,6 +306,7 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.views = nullptr;
   p.work = nullptr;
   p.n_items = p.one.tiles_x * p.one.tiles_y;
+  p.xcd_remap = 1;
   p.flags = flags;
   p.grad_mask = grad_mask_of(grads);
   if (model != DDVR_EMISSION_ABSORPTION) p.grad_mask &= ~GRAD_TF;
@@ -397,18 +400,51 @@ int validate_sphere(float yaw, float pitch, float dist, float fovy, int W, int H
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// Samples of every tile of a view (host replay of the kernels' float32 ray
+// setup): the cost model of the longest-first tile queue and the exact sample
+// count of a batch.
+static std::vector<int64_t> tile_samples(const ViewDesc& d, int tw, int th) {
+  std::vector<int64_t> cost((size_t)d.tiles_x * d.tiles_y, 0);
+  for (int py = 0; py < d.H; ++py)
+    for (int px = 0; px < d.W; ++px) {
+      const float u = 2.0f * ((float)px + 0.5f) / (float)d.W - 1.0f;
+      const float v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)d.H;
+      float w[3], om[3];
+      for (int a = 0; a < 3; ++a) w[a] = d.fwd[a] + u * d.right[a] + v * d.up[a];
+      const float wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+      if (!(wl > 0.0f)) continue;
+      for (int a = 0; a < 3; ++a) om[a] = w[a] / wl;
+      float tn = -INFINITY, tf = INFINITY;
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        if (om[a] == 0.0f) {
+          if (d.eye[a] < d.bmin[a] || d.eye[a] > d.bmax[a]) ok = false;
+          continue;
+        }
+        const float ta = (d.bmin[a] - d.eye[a]) / om[a], tb = (d.bmax[a] - d.eye[a]) / om[a];
+        tn = std::max(tn, std::min(ta, tb));
+        tf = std::min(tf, std::max(ta, tb));
+      }
+      const float t0 = tn > 0.0f ? tn : 0.0f;
+      if (ok && tf > t0)
+        cost[(size_t)(py / th) * d.tiles_x + px / tw] += (int64_t)std::ceil((tf - t0) / d.step);
+    }
+  return cost;
+}
+
 struct ddvr_batch {
   int model = 0, flags = 0;
   Tuning tuning;
   std::vector<ViewDesc> views;
-  std::vector<int> view_dtype;
-  // launch groups: one per storage dtype, each a contiguous range of `work`
-  struct Group { int dtype, first, count, maxR; };
-  std::vector<Group> groups;
+  int launch_dtype = 0;    // storage type of every view, or kDtypeDynamic if they differ
+  int max_R = 2;
+  int persistent = 0;      // 1: persistent workgroups on a longest-first tile queue
+  int n_items = 0;
   ViewDesc* d_views = nullptr;
   int32_t* d_work = nullptr;
+  int32_t* d_queue = nullptr;
   int64_t total_rays = 0, max_n = 1;
-  int64_t samples = -1;
+  int64_t samples = 0;
   int grad_mask = 0;
   // graph cache
   hipGraph_t graph = nullptr;
@@ -469,6 +505,8 @@ int ddvr_set_tuning(const ddvr_tuning* t) {
     return fail(DDVR_ERR_VALUE, "need 4 <= slab_k <= slab_kmax <= 4096");
   if ((t->cell_acc != 0 && t->cell_acc != 1) || (t->lane_map != 0 && t->lane_map != 1))
     return fail(DDVR_ERR_VALUE, "cell_acc and lane_map are 0 or 1");
+  if (t->schedule < 0 || t->schedule > 2) return fail(DDVR_ERR_VALUE, "schedule is 0, 1 or 2");
+  g_tuning.schedule = t->schedule;
   g_tuning.waves = t->waves;
   g_tuning.lds_cap = t->lds_cap;
   g_tuning.slab_k = t->slab_k;
@@ -486,6 +524,7 @@ int ddvr_get_tuning(ddvr_tuning* t) {
   t->slab_kmax = g_tuning.slab_kmax;
   t->cell_acc = g_tuning.cell_acc;
   t->lane_map = g_tuning.lane_map;
+  t->schedule = g_tuning.schedule;
   return DDVR_OK;
 }
 
@@ -572,7 +611,6 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
   b->model = model;
   b->flags = flags;
   b->views.resize(nview);
-  b->view_dtype.resize(nview);
   int gmask = 0;
   for (int i = 0; i < nview; ++i) {
     const ddvr_view& v = views[i];
@@ -597,7 +635,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
     d.dstep = v.d_step;
     gmask |= (d.dV ? GRAD_V : 0) | (d.dTF ? GRAD_TF : 0) | (d.dcam ? GRAD_CAM : 0) |
              (d.dstep ? GRAD_STEP : 0);
-    b->view_dtype[i] = vols[v.volume].dtype;
+    d.dtype = vols[v.volume].dtype;
+    if (i == 0) b->launch_dtype = d.dtype;
+    else if (d.dtype != b->launch_dtype) b->launch_dtype = kDtypeDynamic;
+    b->max_R = std::max(b->max_R, (int)d.R);
     b->total_rays += (int64_t)v.cam.width * v.cam.height;
     b->max_n = std::max<int64_t>(b->max_n, max_samples(&vols[v.volume], v.step_world));
     if ((int64_t)d.tiles_x * d.tiles_y >= (1 << 20)) {
@@ -605,21 +646,37 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
     }
   }
   b->grad_mask = gmask;
-  // work list: grouped by storage dtype, views in order, tiles in raster order
-  std::vector<int32_t> work;
-  for (int dt = 0; dt < 3; ++dt) {
-    ddvr_batch::Group g{dt, (int)work.size(), 0, 2};
-    for (int i = 0; i < nview; ++i) {
-      if (b->view_dtype[i] != dt) continue;
-      const int nt = b->views[i].tiles_x * b->views[i].tiles_y;
-      for (int t = 0; t < nt; ++t) work.push_back((i << 20) | t);
-      g.maxR = std::max(g.maxR, (int)b->views[i].R);
+  // Work list of (view << 20 | tile).  Even batches (every view the same image
+  // size over one grid) keep views in order and tiles in raster order, one
+  // workgroup per tile with contiguous ranges per XCD.  Uneven batches (or
+  // schedule = 2) become a persistent launch whose workgroups pop tiles from a
+  // queue ordered by estimated cost, longest first.
+  const int tw = tile_w(b->tuning.waves), th = tile_h(b->tuning.waves);
+  std::vector<std::pair<int64_t, int32_t>> items;
+  bool even = true;
+  for (int i = 0; i < nview; ++i) {
+    const ViewDesc& d = b->views[i];
+    const std::vector<int64_t> cost = tile_samples(d, tw, th);
+    for (size_t t = 0; t < cost.size(); ++t) {
+      items.emplace_back(cost[t], (int32_t)((i << 20) | (int)t));
+      b->samples += cost[t];
     }
-    g.count = (int)work.size() - g.first;
-    if (g.count > 0) b->groups.push_back(g);
+    if (d.W != b->views[0].W || d.H != b->views[0].H || d.vol != b->views[0].vol) even = false;
   }
+  // batches mixing storage types always take the persistent (per-view type) launch
+  b->persistent = b->tuning.schedule == 2 || (b->tuning.schedule == 0 && !even) ||
+                  b->launch_dtype == kDtypeDynamic;
+  if (b->persistent) b->launch_dtype = kDtypeDynamic;
+  if (b->persistent)
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<int64_t, int32_t>& x,
+                        const std::pair<int64_t, int32_t>& y) { return x.first > y.first; });
+  std::vector<int32_t> work(items.size());
+  for (size_t k = 0; k < items.size(); ++k) work[k] = items[k].second;
+  b->n_items = (int)work.size();
   hipError_t e = hipMalloc(&b->d_views, sizeof(ViewDesc) * nview);
   if (e == hipSuccess) e = hipMalloc(&b->d_work, sizeof(int32_t) * work.size());
+  if (e == hipSuccess) e = hipMalloc(&b->d_queue, 256);
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_views, b->views.data(), sizeof(ViewDesc) * nview, hipMemcpyHostToDevice, s);
@@ -641,6 +698,7 @@ void ddvr_batch_destroy(ddvr_batch* b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_views) (void)hipFree(b->d_views);
   if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_queue) (void)hipFree(b->d_queue);
   delete b;
 }
 
@@ -674,10 +732,8 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.grad_mask = b->grad_mask;
   p.lds_two = needs_two_bricks(pass, b->model, b->flags, b->grad_mask);
   {
-    int maxR = 2;
-    for (const auto& g : b->groups) maxR = std::max(maxR, g.maxR);
     const int rc = fit_cap((b->flags & DDVR_LAUNCH_PLAIN) ? 0 : b->tuning.lds_cap, p.lds_two,
-                           b->model, maxR, &p.lds_cap);
+                           b->model, b->max_R, &p.lds_cap);
     if (rc) return rc;
   }
   p.slab_kmax = b->tuning.slab_kmax;
@@ -685,26 +741,27 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.lane_map = b->tuning.lane_map;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
+  p.work = b->d_work;
+  p.n_items = b->n_items;
+  p.xcd_remap = b->persistent ? 0 : 1;
+  p.queue = b->persistent ? b->d_queue : nullptr;
   if (fb) attach_fallback(p, L, ws, b->flags);
-  for (const auto& g : b->groups) {
-    const int rc = check_lds(lds_bytes(p.lds_cap, p.lds_two, b->model, g.maxR));
+  const size_t lds = lds_bytes(p.lds_cap, p.lds_two, b->model, b->max_R);
+  {
+    const int rc = check_lds(lds);
     if (rc) return rc;
   }
   hipError_t e;
   if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, s)) != hipSuccess)
     return hip_fail(e, "zeroing the fallback queue");
-  for (const auto& g : b->groups) {
-    p.work = b->d_work + g.first;
-    p.n_items = g.count;
-    e = (hipError_t)launch_render(p, pass, b->model, g.dtype, b->tuning.waves, g.count,
-                                  lds_bytes(p.lds_cap, p.lds_two, b->model, g.maxR), s);
-    if (e != hipSuccess) return hip_fail(e, "batch render launch");
-    if (fb) {
-      e = (hipError_t)launch_fallback(p, b->model, g.dtype, pass == PASS_FUSED ? 1 : 0, s);
-      if (e != hipSuccess) return hip_fail(e, "batch fallback launch");
-      if (b->groups.size() > 1 && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, s)) != hipSuccess)
-        return hip_fail(e, "zeroing the fallback queue");
-    }
+  if (p.queue && (e = (hipError_t)launch_zero_i32(p.queue, 1, s)) != hipSuccess)
+    return hip_fail(e, "zeroing the tile queue");
+  e = (hipError_t)launch_render(p, pass, b->model, b->launch_dtype, b->tuning.waves, b->n_items,
+                                lds, s);
+  if (e != hipSuccess) return hip_fail(e, "batch render launch");
+  if (fb) {
+    e = (hipError_t)launch_fallback(p, b->model, b->launch_dtype, pass == PASS_FUSED ? 1 : 0, s);
+    if (e != hipSuccess) return hip_fail(e, "batch fallback launch");
   }
   return DDVR_OK;
 }
@@ -753,33 +810,7 @@ int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* 
 
 int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples) {
   if (!b || !samples) return fail(DDVR_ERR_NULL, "batch or samples is NULL");
-  // exact count, replaying the ray setup of the kernels on the host in float32
-  int64_t total = 0;
-  for (const ViewDesc& d : b->views) {
-    for (int py = 0; py < d.H; ++py)
-      for (int px = 0; px < d.W; ++px) {
-        const float u = 2.0f * ((float)px + 0.5f) / (float)d.W - 1.0f;
-        const float v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)d.H;
-        float w[3], om[3];
-        for (int a = 0; a < 3; ++a) w[a] = d.fwd[a] + u * d.right[a] + v * d.up[a];
-        const float wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-        for (int a = 0; a < 3; ++a) om[a] = w[a] / wl;
-        float tn = -INFINITY, tf = INFINITY;
-        bool ok = true;
-        for (int a = 0; a < 3; ++a) {
-          if (om[a] == 0.0f) {
-            if (d.eye[a] < d.bmin[a] || d.eye[a] > d.bmax[a]) ok = false;
-            continue;
-          }
-          const float ta = (d.bmin[a] - d.eye[a]) / om[a], tb = (d.bmax[a] - d.eye[a]) / om[a];
-          tn = std::max(tn, std::min(ta, tb));
-          tf = std::min(tf, std::max(ta, tb));
-        }
-        const float t0 = tn > 0.0f ? tn : 0.0f;
-        if (ok && tf > t0) total += (int64_t)std::ceil((tf - t0) / d.step);
-      }
-  }
-  *samples = total;
+  *samples = b->samples;   // replayed on the host when the batch was built
   return DDVR_OK;
 }
 

@@ -13,6 +13,7 @@ struct ViewDesc {
   float step;             // dt, world units
   // grid (Sec. 3.1): vertex values [nz][ny][nx]
   const void* vol;
+  int32_t dtype;          // storage type of vol (ddvr_dtype)
   int32_t nx, ny, nz;
   float h, inv_h;
   float bmin[3], bmax[3];
@@ -48,6 +49,8 @@ struct LaunchParams {
   int32_t slab_kmax;      // longest slab (samples per ray) the adaptive march tries
   int32_t cell_acc;       // 1: density gradient kept in registers per cell
   int32_t lane_map;       // 1: lanes of a wave on every other pixel
+  int32_t xcd_remap;      // 1: contiguous tile ranges per XCD (one tile per workgroup)
+  int32_t* queue;         // persistent launch: tile counter (zeroed before the launch)
   float loss_scale;       // fused L2
   double* loss_out;       // fused L2 accumulator or null
   // checkpoint fallback queue (workspace)
@@ -72,6 +75,7 @@ int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void
 int launch_zero_i32(int32_t* ptr, int n, void* stream);
 int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
 
+constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persistent launch
 constexpr int kMaxSamples = 1 << 22;    // per-ray sample cap (validated on the host)
 constexpr float kFallbackTmin = 7.888609052210118e-31f;   // 2^-100 (T-form inversion)
 constexpr float kFallbackTminAlpha = 9.765625e-4f;         // 2^-10 (alpha-form inversion)

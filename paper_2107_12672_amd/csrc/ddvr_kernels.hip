@@ -53,6 +53,21 @@ template <> struct Vox<DDVR_BF16> {
   }
 };
 
+// Storage type chosen per view at run time (batches that mix grids of
+// different storage types in one launch); the branch is uniform per tile.
+constexpr int DT_DYN = 3;
+
+template <int DT>
+__device__ __forceinline__ float vload(const ViewDesc& vd, int64_t i) {
+  if constexpr (DT == DT_DYN) {
+    if (vd.dtype == DDVR_F16) return Vox<DDVR_F16>::ld(vd.vol, i);
+    if (vd.dtype == DDVR_BF16) return Vox<DDVR_BF16>::ld(vd.vol, i);
+    return Vox<DDVR_F32>::ld(vd.vol, i);
+  } else {
+    return vload<DT>(vd, i);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // f_camera: ray of one pixel, clipped against the grid box.
 // Positions are carried in grid units: q = (x - b_min)/h.
@@ -138,14 +153,14 @@ template <int DT>
 __device__ __forceinline__ void fetch_global(const ViewDesc& vd, const Cell& c, float* v) {
   const int64_t sx = 1, sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
   const int64_t b = c.k[2] * sz + c.k[1] * sy + c.k[0];
-  v[0] = Vox<DT>::ld(vd.vol, b);
-  v[1] = Vox<DT>::ld(vd.vol, b + sx);
-  v[2] = Vox<DT>::ld(vd.vol, b + sy);
-  v[3] = Vox<DT>::ld(vd.vol, b + sy + sx);
-  v[4] = Vox<DT>::ld(vd.vol, b + sz);
-  v[5] = Vox<DT>::ld(vd.vol, b + sz + sx);
-  v[6] = Vox<DT>::ld(vd.vol, b + sz + sy);
-  v[7] = Vox<DT>::ld(vd.vol, b + sz + sy + sx);
+  v[0] = vload<DT>(vd, b);
+  v[1] = vload<DT>(vd, b + sx);
+  v[2] = vload<DT>(vd, b + sy);
+  v[3] = vload<DT>(vd, b + sy + sx);
+  v[4] = vload<DT>(vd, b + sz);
+  v[5] = vload<DT>(vd, b + sz + sx);
+  v[6] = vload<DT>(vd, b + sz + sy);
+  v[7] = vload<DT>(vd, b + sz + sy + sx);
 }
 
 struct Brick {   // LDS brick of the current slab
@@ -377,7 +392,7 @@ __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br,
       const int rem = idx - z * br.bxy;
       const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
       const int x = rem - y * br.bx;
-      stage[idx] = Vox<DT>::ld(vd.vol, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
+      stage[idx] = vload<DT>(vd, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
     }
     if (acc) acc[idx] = 0.0f;
   }
@@ -503,7 +518,7 @@ __device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
 // Adjoint of one sample i given T^(i) source.  `mode` selects how T^(i) is
 // recovered: 0 closed form (AO), 1 T-form inversion, 2 alpha-form inversion,
 // 3 caller supplies Ti (checkpoint).
-template <int MODEL, int DT, bool LDS, int MODE>
+template <int MODEL, int DT, bool LDS, int MODE, bool XH>
 __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, int i,
                                            const float* stage, float* acc, const Brick& br,
                                            const float4* tfl, float* dtf, int gmask,
@@ -511,7 +526,9 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
                                            float Ti_given) {
   Cell c;
   locate(r, i, vd.nx, vd.ny, vd.nz, c);
-  const bool need_xhat = (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
+  // XH: camera or step gradients are compiled in (their float64 ray sums cost
+  // registers the density-only kernels do not pay for)
+  const bool need_xhat = XH && (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
   float v[8];
   float d = 0.0f;
   int base = 0;
@@ -526,7 +543,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     // T^(i)*e_i*ahat^(i+1) = T^(i+1)*ahat^(i+1) is invariant under the
     // inversion T^(i) = T^(i+1)/e_i, ahat^(i) = e_i*ahat^(i+1) (no emission).
     d_hat = vd.step * s.P;
-    s.dstep += (double)(d * s.P);
+    if (XH) s.dstep += (double)(d * s.P);
   } else {
     float rgb[3] = {0.0f, 0.0f, 0.0f}, tau;
     TFv t;
@@ -555,7 +572,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     s.ahat = fmaf(e, s.ahat, -alpha * rc);              // ahat^(i)
     const float ase = as_hat * e;
     const float tau_hat = ase * vd.step;
-    s.dstep += (double)(ase * tau);
+    if (XH) s.dstep += (double)(ase * tau);
     if (MODEL == DDVR_EMISSION_ABSORPTION) {
       const float w = alpha * Ti;
       const float g4[4] = {w * s.Chat[0], w * s.Chat[1], w * s.Chat[2], tau_hat};
@@ -630,13 +647,13 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   }
 }
 
-template <int MODEL, int DT, bool LDS, int MODE>
+template <int MODEL, int DT, bool LDS, int MODE, bool XH>
 __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int a, int b,
                                           const float* stage, float* acc, const Brick& br,
                                           const float4* tfl, float* dtf, int gmask, bool need_v,
                                           bool cell_acc, AdjState& s) {
   for (int i = b - 1; i >= a; --i)
-    adj_sample<MODEL, DT, LDS, MODE>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v,
+    adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v,
                                      cell_acc, s, 0.0f);
   if (cell_acc) cell_flush<LDS>(vd, br, acc, s);   // the brick changes with the slab
 }
@@ -658,11 +675,12 @@ __device__ __forceinline__ void camera_adjoint(const ViewDesc& vd, const RayG& r
     eh[a] = (float)s.xo_hat[a];
     t0h += r.om[a] * (float)s.xo_hat[a];
   }
-  if (r.axis >= 0) {
-    const float o = r.om[r.axis];
-    eh[r.axis] -= t0h / o;
-    oh[r.axis] -= t0h * r.t0 / o;
-  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a == r.axis) {
+      eh[a] -= t0h / r.om[a];
+      oh[a] -= t0h * r.t0 / r.om[a];
+    }
   const float od = r.om[0] * oh[0] + r.om[1] * oh[1] + r.om[2] * oh[2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -682,14 +700,13 @@ template <> struct TileShape<1> { static constexpr int BX = 1, BY = 1; };
 template <> struct TileShape<2> { static constexpr int BX = 2, BY = 1; };
 template <> struct TileShape<4> { static constexpr int BX = 2, BY = 2; };
 
-template <int MODEL, int DT, int WAVES, int PASS>
-__global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
+// One tile of the render: forward, adjoint, or fused forward + L2 + adjoint.
+template <int MODEL, int DT, int WAVES, int PASS, bool XH>
+__device__ __forceinline__ void render_tile(const LaunchParams& p, const int item, float* smem) {
   constexpr int NT = WAVES * 64;
   constexpr int TW = 8 * TileShape<WAVES>::BX, TH = 8 * TileShape<WAVES>::BY;
   constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
-  extern __shared__ __align__(16) float smem[];
 
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
   int view = 0, tile = item;
   if (p.work) {
     const int w = p.work[item];
@@ -703,8 +720,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
   int gmask = p.grad_mask;
   if (!vd.dV) gmask &= ~GRAD_V;
   if (!vd.dTF) gmask &= ~GRAD_TF;
-  if (!vd.dcam) gmask &= ~GRAD_CAM;
-  if (!vd.dstep) gmask &= ~GRAD_STEP;
+  if (!vd.dcam || !XH) gmask &= ~GRAD_CAM;
+  if (!vd.dstep || !XH) gmask &= ~GRAD_STEP;
 
   // LDS carve-up: one brick region, or two when the adjoint needs the grid
   // values and a gradient accumulator at the same time
@@ -883,31 +900,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
       stage_brick<NT, DT>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
       if (!EA && mode == DDVR_ADJ_AUTO)
-        march_adj<MODEL, DT, true, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, true, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
-        march_adj<MODEL, DT, true, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, true, 2, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       else
-        march_adj<MODEL, DT, true, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, true, 1, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       __syncthreads();
       if (want_dv) flush_brick<NT>(vd, br, acc);
     } else {
       if (!EA && mode == DDVR_ADJ_AUTO)
-        march_adj<MODEL, DT, false, 0>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, false, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                        p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
-        march_adj<MODEL, DT, false, 2>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, false, 2, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                        p.cell_acc, s);
       else
-        march_adj<MODEL, DT, false, 1>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
+        march_adj<MODEL, DT, false, 1, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                        p.cell_acc, s);
     }
   }
   if (EA && (gmask & GRAD_TF)) tf_flush(s, dtf);
 
-  if (gmask & (GRAD_CAM | GRAD_STEP)) {
+  if (XH && (gmask & (GRAD_CAM | GRAD_STEP))) {
     float cg[13];
     camera_adjoint(vd, r, s, Nadj > 0, cg);
     wg_sum_n<NT>(cg, 13, fscratch);
@@ -922,6 +939,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
     __syncthreads();
     for (int k = threadIdx.x; k < 4 * vd.R; k += NT)
       if (dtf[k] != 0.0f) atomicAdd(vd.dTF + k, dtf[k]);
+  }
+}
+
+// The render kernel.  With a fixed storage type: one tile per workgroup,
+// blockIdx remapped so that each XCD takes a contiguous range of tiles.  With
+// the storage type chosen per view (DT_DYN, used by uneven and mixed batches):
+// persistent workgroups pop tiles from a queue ordered longest-first.  The two
+// forms are separate instantiations because the tile loop costs registers.
+template <int MODEL, int DT, int WAVES, int PASS, bool XH>
+__global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
+  extern __shared__ __align__(16) float smem[];
+  if constexpr (DT == DT_DYN) {
+    __shared__ int s_item;
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(p.queue, 1);
+      __syncthreads();
+      const int item = s_item;
+      __syncthreads();
+      if (item >= p.n_items) break;
+      render_tile<MODEL, DT, WAVES, PASS, XH>(p, item, smem);
+      __syncthreads();   // the next tile reuses the LDS
+    }
+  } else {
+    render_tile<MODEL, DT, WAVES, PASS, XH>(p, p.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x)
+                                                           : (int)blockIdx.x, smem);
   }
 }
 
@@ -1006,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
         tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
       }
       for (int i = i1 - 1; i >= i0; --i)
-        adj_sample<MODEL, DT, false, 3>(vd, r, i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
+        adj_sample<MODEL, DT, false, 3, true>(vd, r, i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
                                         true, false, s, tseg[i - i0]);
     }
     if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
@@ -1075,22 +1117,41 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// Persistent launches size the grid to the workgroups that fit the device at
+// once (occupancy x CUs), capped by the number of tiles.
+template <typename K>
+static int persistent_blocks(K kernel, int threads, size_t lds, int n_items) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+      per_cu <= 0 || cus <= 0)
+    return n_items < 1024 ? n_items : 1024;
+  const int64_t b = (int64_t)cus * per_cu;
+  return (int)(b < n_items ? b : n_items);
+}
+
+template <int MODEL, int DT, int WAVES, int PASS, bool XH>
+static hipError_t launch4(const LaunchParams& p, int n_blocks, size_t lds, hipStream_t s) {
+  auto kernel = k_render<MODEL, DT, WAVES, PASS, XH>;
+  if (DT == DT_DYN) n_blocks = persistent_blocks(kernel, WAVES * 64, lds, p.n_items);
+  hipLaunchKernelGGL(kernel, dim3(n_blocks), dim3(WAVES * 64), lds, s, p);
+  return hipGetLastError();
+}
+
 template <int MODEL, int DT, int WAVES>
 static hipError_t launch3(const LaunchParams& p, int pass, int n_blocks, size_t lds,
                           hipStream_t s) {
-  const dim3 grid(n_blocks), block(WAVES * 64);
+  const bool xh = (p.grad_mask & (GRAD_CAM | GRAD_STEP)) != 0;
   switch (pass) {
-    case PASS_FWD:
-      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_FWD>), grid, block, lds, s, p);
-      break;
+    case PASS_FWD: return launch4<MODEL, DT, WAVES, PASS_FWD, false>(p, n_blocks, lds, s);
     case PASS_ADJ:
-      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_ADJ>), grid, block, lds, s, p);
-      break;
+      return xh ? launch4<MODEL, DT, WAVES, PASS_ADJ, true>(p, n_blocks, lds, s)
+                : launch4<MODEL, DT, WAVES, PASS_ADJ, false>(p, n_blocks, lds, s);
     default:
-      hipLaunchKernelGGL((k_render<MODEL, DT, WAVES, PASS_FUSED>), grid, block, lds, s, p);
-      break;
+      return xh ? launch4<MODEL, DT, WAVES, PASS_FUSED, true>(p, n_blocks, lds, s)
+                : launch4<MODEL, DT, WAVES, PASS_FUSED, false>(p, n_blocks, lds, s);
   }
-  return hipGetLastError();
 }
 
 template <int MODEL, int DT>
@@ -1109,6 +1170,7 @@ static hipError_t launch1(const LaunchParams& p, int pass, int dtype, int waves,
   switch (dtype) {
     case DDVR_F16: return launch2<MODEL, DDVR_F16>(p, pass, waves, n_blocks, lds, s);
     case DDVR_BF16: return launch2<MODEL, DDVR_BF16>(p, pass, waves, n_blocks, lds, s);
+    case DT_DYN: return launch2<MODEL, DT_DYN>(p, pass, waves, n_blocks, lds, s);
     default: return launch2<MODEL, DDVR_F32>(p, pass, waves, n_blocks, lds, s);
   }
 }
@@ -1136,6 +1198,7 @@ static hipError_t launch_fb1(const LaunchParams& p, int dtype, int fused, int bl
   switch (dtype) {
     case DDVR_F16: return launch_fb2<MODEL, DDVR_F16>(p, fused, blocks, s);
     case DDVR_BF16: return launch_fb2<MODEL, DDVR_BF16>(p, fused, blocks, s);
+    case DT_DYN: return launch_fb2<MODEL, DT_DYN>(p, fused, blocks, s);
     default: return launch_fb2<MODEL, DDVR_F32>(p, fused, blocks, s);
   }
 }

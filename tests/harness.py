@@ -157,9 +157,12 @@ def kink_mask(p: Problem, pix=None) -> np.ndarray:
     evaluate different one-sided derivatives there.  Position error of the
     float32 march is ~ulp(q) ~ 1e-7 * max(n) voxels; density error ~1e-7."""
     V = dequantized(p)
-    face, knot = oracle.kinks(V, p.tf, oracle_camera(p), p.W, p.H, p.step, p.model, pix=pix)
+    face, knot, entry = oracle.kinks(V, p.tf, oracle_camera(p), p.W, p.H, p.step, p.model,
+                                     pix=pix, with_entry=True)
     nmax = max(p.volume.shape)
-    face_tol = 1e-6 * nmax + 1e-4
+    # the entry point x_o = e + t0*omega inherits direction errors amplified by
+    # t0/|omega_a| (entry plane a): grazing entries move all samples further
+    face_tol = 1e-6 * nmax + 1e-4 + 4e-7 * 0.5 * (nmax - 1) * entry
     knot_tol = 1e-5 * (p.tf.shape[0] if p.tf is not None else 1)
     return (face < face_tol) | (knot < knot_tol)
 
@@ -189,6 +192,24 @@ def sensitive_mask(p: Problem, pix, g, rel=1e-7, thresh=1e-3, trials=3, seed=0):
             worst = max(worst, float(np.abs(np.r_[a["dcam"], a["dstep"]] - b).max()))
         out[q] = worst > thresh * max(float(np.abs(b).max()), 1e-30)
     return out
+
+
+def oracle_spread(p: Problem, pix, g, rel=1e-7, trials=3, seed=1):
+    """Relative spread of the oracle's camera (norm-wise) and step gradients
+    when the camera frame and the step are perturbed by `rel` relative (float32
+    rounding of the inputs).  Returns (cam_spread, step_spread)."""
+    V = dequantized(p)
+    cam = oracle_camera(p)
+    rng = np.random.default_rng(seed)
+    base = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, g, pix=pix, want_dV=False)
+    cs = ss = 0.0
+    for _ in range(trials):
+        a = oracle.adjoint(V, p.tf, cam * (1.0 + rel * rng.normal(size=12)), p.W, p.H,
+                           p.step * (1.0 + rel * rng.normal()), p.model, g, pix=pix,
+                           want_dV=False)
+        cs = max(cs, rel_norm_err(a["dcam"], base["dcam"]))
+        ss = max(ss, abs(a["dstep"] - base["dstep"]) / max(abs(base["dstep"]), 1e-300))
+    return cs, ss
 
 
 def tie_mask(ratio: np.ndarray) -> np.ndarray:

@@ -173,11 +173,13 @@ def test_tuning_roundtrip_and_validation():
     L = d.lib()
     old = d.get_tuning()
     try:
-        d.set_tuning(waves=2, lds_cap=4096, slab_k=16, slab_kmax=64, cell_acc=0, lane_map=0)
+        d.set_tuning(waves=2, lds_cap=4096, slab_k=16, slab_kmax=64, cell_acc=0, lane_map=0,
+                     schedule=2)
         assert d.get_tuning() == {"waves": 2, "lds_cap": 4096, "slab_k": 16, "slab_kmax": 64,
-                                  "cell_acc": 0, "lane_map": 0}
+                                  "cell_acc": 0, "lane_map": 0, "schedule": 2}
         for bad in ({"waves": 3}, {"lds_cap": 10}, {"lds_cap": 1 << 20}, {"slab_k": 2},
-                    {"slab_k": 128, "slab_kmax": 64}, {"cell_acc": 2}, {"lane_map": -1}):
+                    {"slab_k": 128, "slab_kmax": 64}, {"cell_acc": 2}, {"lane_map": -1},
+                    {"schedule": 3}):
             with pytest.raises(d.DDVRError) as ei:
                 d.set_tuning(**bad)
             assert ei.value.status == d.ERR_VALUE

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import synth
 from harness import (IMG_ATOL, Problem, assert_dv_close, assert_grad_close, kink_mask,
-                     sensitive_mask, tie_mask)
+                     oracle_spread, sensitive_mask, tie_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -258,11 +258,19 @@ def test_c4_uneven_batch_sampled_parity():
         dimgs[k].reshape(-1, 4)[tix] = torch.from_numpy(gv.astype(np.float32)).cuda()
         refs.append(oracle.adjoint(Vq, w.tf, ocam, v.width, v.height, w.step_world, oracle.EA,
                                    gv, pix=pix))
+        refs[-1]["spread"] = oracle_spread(p, pix, gv)
     b.run(d.PASS_ADJOINT, workspace=ws)
     torch.cuda.synchronize()
     for k, a in enumerate(refs):
         assert_dv_close(dvs[k].double().cpu().numpy(), a["dV"], f"C4[{k}] dV")
         assert_grad_close(dtfs[k].double().cpu().numpy(), a["dTF"], f"C4[{k}] dTF")
-        assert_grad_close(dcams[k].double().cpu().numpy(), a["dcam"], f"C4[{k}] dcam",
-                          rtol=2e-3)
-        assert_grad_close([dsteps[k].item()], [a["dstep"]], f"C4[{k}] dstep", rtol=2e-3)
+        # The 12-vector camera gradient is a sum of cancelling per-ray terms:
+        # compared norm-wise, like the density gradient.  Long rays through steep
+        # TFs make camera / step gradients sensitive to float32 rounding of the
+        # inputs themselves; the bound is the larger of 2e-3 and three times the
+        # oracle's own spread under such perturbations.
+        cs, ss = a["spread"]
+        assert_dv_close(dcams[k].double().cpu().numpy(), a["dcam"], f"C4[{k}] dcam",
+                        rtol=max(2e-3, 3 * cs))
+        assert_grad_close([dsteps[k].item()], [a["dstep"]], f"C4[{k}] dstep",
+                          rtol=max(2e-3, 3 * ss))

@@ -323,3 +323,61 @@ def test_results_do_not_depend_on_the_launch_shape(tuning):
         assert_dv_close(gpu_adjoint(c, cg)["dV"], oracle_adjoint(c, cg)["dV"], "AO dV")
     finally:
         d.set_tuning(**old)
+
+
+def test_batch_schedules_agree_and_match_single_views():
+    """An uneven batch (two grids, three image sizes) run one-workgroup-per-tile
+    and as a persistent longest-first queue (also replayed from a graph) gives
+    bitwise the same images as single-view launches, and the same gradients
+    up to summation order."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    from harness import device_volume, gpu_camera
+    probs = [ea_problem(W=40, H=24, seed=61), ea_problem(W=72, H=56, seed=62, yaw=200.0),
+             ea_problem(W=33, H=47, seed=61, yaw=-40.0, pitch=30.0)]
+    probs[2].volume = probs[0].volume           # views 0 and 2 share grid 0
+    _say("batch schedules")
+    vols = [device_volume(probs[0]), device_volume(probs[1])]
+    vidx = [0, 1, 0]
+    tfs = [torch.from_numpy(p.tf).cuda() for p in probs]
+    rng = np.random.default_rng(63)
+    gs = [torch.from_numpy(rng.normal(size=(p.H * p.W * 4,)).astype(np.float32)).cuda()
+          for p in probs]
+    # single-view references
+    ref_img, ref_dv = [], [torch.zeros(v.shape, device="cuda") for v in vols]
+    for k, p in enumerate(probs):
+        img = torch.zeros(p.H * p.W * 4, device="cuda")
+        tr = torch.zeros(p.H * p.W, device="cuda")
+        cam = gpu_camera(p)
+        d.render_forward(vols[vidx[k]], tfs[k], cam, p.step, 1, img, tr)
+        ws = torch.zeros(d.adjoint_workspace_size(vols[vidx[k]], cam, p.step, 1) // 4 + 1,
+                         dtype=torch.int32, device="cuda")
+        d.render_adjoint(vols[vidx[k]], tfs[k], cam, p.step, 1, img, tr, gs[k],
+                         d.grads_desc(ref_dv[vidx[k]]), workspace=ws)
+        ref_img.append(img)
+    torch.cuda.synchronize()
+    old = d.get_tuning()
+    try:
+        for sched, graph in ((1, False), (2, False), (2, True)):
+            d.set_tuning(schedule=sched)
+            imgs = [torch.full((p.H * p.W * 4,), float("nan"), device="cuda") for p in probs]
+            trs = [torch.zeros(p.H * p.W, device="cuda") for p in probs]
+            dvs = [torch.zeros(v.shape, device="cuda") for v in vols]
+            views = [d.make_view(vidx[k], gpu_camera(p), p.step, imgs[k], transmittance=trs[k],
+                                 d_image=gs[k], tf_index=k) for k, p in enumerate(probs)]
+            b = d.Batch(vols, tfs, views, d.EMISSION_ABSORPTION, d_volumes=dvs)
+            ws = torch.zeros(b.workspace_size() // 4 + 1, dtype=torch.int32, device="cuda")
+            for rep in range(2 if graph else 1):
+                for dv in dvs:
+                    dv.zero_()
+                b.run(d.PASS_FORWARD, graph=graph)
+                b.run(d.PASS_ADJOINT, workspace=ws)
+                torch.cuda.synchronize()
+                for k in range(3):
+                    assert torch.equal(imgs[k], ref_img[k]), (sched, graph, k)
+                for j in range(2):
+                    e = float((dvs[j] - ref_dv[j]).norm() / ref_dv[j].norm())
+                    assert e < 1e-5, (sched, graph, j, e)
+            b.close()
+    finally:
+        d.set_tuning(**old)
