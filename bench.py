@@ -155,6 +155,13 @@ def main():
     tb.close()
     del gt16
 
+    # launch shape: the autotuner's choice for this workload class, if cached
+    from paper_2107_12672_amd import autotune
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tkey = autotune.workload_key(arch, d.ABSORPTION, "bf16", 0, W, args.n, "V", d.PASS_FUSED)
+    tuned = autotune.apply(tkey)
+    log(f"tuning ({'autotuned' if tuned else 'default'}): {d.get_tuning()}")
+
     # reconstruction state: float32 master (zero-initialised), bf16 storage, gradient
     master = torch.zeros((args.n,) * 3, device=dev)
     vol16 = torch.empty_like(master, dtype=torch.bfloat16)
@@ -213,7 +220,8 @@ def main():
                                f"{args.step_vox} voxel, L2 loss, gradient w.r.t. density",
                    "storage": "bf16", "samples_per_step": S, "views": nv, "image": W,
                    "grid": args.n, "step_vox": args.step_vox,
-                   "launch": "one fused launch per step, HIP graph replay"},
+                   "launch": "one fused launch per step, HIP graph replay",
+                   "tuning": d.get_tuning(), "tuning_source": "autotuned" if tuned else "default"},
         "roofline": roofline,
     }
 

@@ -1,0 +1,193 @@
+"""Autotuner for the launch shape of the render kernels.
+
+For a workload (a function that builds a ``ddvr.Batch`` and a function that
+runs one timed pass on it) the tuner tries candidate launch shapes -- waves
+per workgroup (tile shape), LDS brick capacity, initial slab length, lane
+mapping, batch schedule -- times each with HIP events, checks that every
+candidate renders bitwise the same images (the per-ray arithmetic does not
+depend on the launch shape), and stores the fastest under a key that
+describes the workload class.  ``apply`` looks a key up and sets the
+process-wide tuning before a batch is built.
+
+Cache: JSON at $DDVR_TUNING_CACHE, else ``tuning_cache.json`` next to this
+file.  Keys: ``arch|model|storage|R<bucket>|img<bucket>|grid<bucket>|grads|pass``
+with power-of-two buckets.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+from typing import Callable, Dict, Iterable, List, Optional
+
+from . import ddvr as _d
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def cache_path() -> str:
+    return os.environ.get("DDVR_TUNING_CACHE", os.path.join(HERE, "tuning_cache.json"))
+
+
+def _bucket(x: float) -> int:
+    return 1 << max(0, int(math.ceil(math.log2(max(1.0, float(x))))))
+
+
+def workload_key(arch: str, model: int, storage: str, R: int, image_px: int, grid_edge: int,
+                 grads: str, pass_: int) -> str:
+    """Key of a workload class: image and grid sizes and R in power-of-two buckets."""
+    m = "ea" if model == _d.EMISSION_ABSORPTION else "ao"
+    return (f"{arch}|{m}|{storage}|R{_bucket(R) if model == _d.EMISSION_ABSORPTION else 0}|"
+            f"img{_bucket(image_px)}|grid{_bucket(grid_edge)}|{grads}|pass{pass_}")
+
+
+def load_cache(path: Optional[str] = None) -> Dict[str, dict]:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: Dict[str, dict], path: Optional[str] = None) -> None:
+    path = path or cache_path()
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(key: str, path: Optional[str] = None) -> Optional[dict]:
+    entry = load_cache(path).get(key)
+    if not entry:
+        return None
+    t = entry.get("tuning")
+    if not isinstance(t, dict) or set(t) != set(_d.TUNING_DEFAULT):
+        return None
+    return t
+
+
+def apply(key: str, path: Optional[str] = None) -> bool:
+    """Set the tuning cached for `key`; False (tuning unchanged) if none."""
+    t = lookup(key, path)
+    if t is None:
+        return False
+    _d.set_tuning(**t)
+    return True
+
+
+def default_candidates() -> List[dict]:
+    out = []
+    for waves, cap, k, lm in itertools.product((2, 4), (6144, 12288, 16384), (32, 64, 128),
+                                               (0, 1)):
+        out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
+                    "cell_acc": 1, "lane_map": lm, "schedule": 0})
+    return out
+
+
+def tune(key: str, make_batch: Callable[[], "object"], run: Callable[["object"], None],
+         images: Callable[[], "object"], candidates: Optional[Iterable[dict]] = None,
+         reps: int = 3, path: Optional[str] = None, verbose: bool = False) -> dict:
+    """Time every candidate on the workload and cache the fastest.
+
+    make_batch() builds a fresh batch under the current tuning; run(batch)
+    enqueues one pass on torch's current stream; images() returns a tensor of
+    the rendered images (compared bitwise across candidates)."""
+    import torch
+    old = _d.get_tuning()
+    results = []
+    ref = None
+    try:
+        for cand in (list(candidates) if candidates is not None else default_candidates()):
+            _d.set_tuning(**cand)
+            try:
+                b = make_batch()
+            except _d.DDVRError:
+                continue               # e.g. a brick that does not fit the device's LDS
+            run(b)
+            torch.cuda.synchronize()
+            img = images().clone()
+            if ref is None:
+                ref = img
+            elif not torch.equal(img, ref):
+                raise RuntimeError(f"launch shape {cand} changed the rendered images")
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                run(b)
+            z.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(z) / reps
+            results.append((ms, cand))
+            if verbose:
+                print(f"[autotune] {ms:9.3f} ms  {cand}", flush=True)
+            b.close()
+    finally:
+        _d.set_tuning(**old)
+    if not results:
+        raise RuntimeError("no candidate launch shape could run")
+    results.sort(key=lambda x: x[0])
+    best_ms, best = results[0]
+    cache = load_cache(path)
+    cache[key] = {"tuning": best, "ms": best_ms,
+                  "runner_up_ms": results[1][0] if len(results) > 1 else None,
+                  "candidates": len(results)}
+    save_cache(cache, path)
+    return {"tuning": best, "ms": best_ms, "all": results}
+
+
+def _device_arch() -> str:
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def main(argv=None) -> None:
+    """Tune the absorption-only tomography workload (256^3 bf16, 64 views at
+    512x512, fused pass) and store the result in the cache."""
+    import argparse
+    import sys
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--views", type=int, default=64)
+    ap.add_argument("--image", type=int, default=512)
+    ap.add_argument("--step-vox", type=float, default=0.2)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args(argv)
+    root = os.path.dirname(HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import synth
+    w = synth.make_c3(args.n, args.views, args.image, args.step_vox)
+    dev = torch.device("cuda:0")
+    W = args.image
+    gt = torch.from_numpy(w.target_volume).to(dev)
+    vol = torch.empty_like(gt, dtype=torch.bfloat16)
+    _d.cast_volume(gt, vol)
+    cams = [_d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                  math.radians(v.fovy), W, W) for v in w.views]
+    nv = len(cams)
+    targets = torch.rand((nv, W, W), device=dev, generator=torch.Generator("cuda").manual_seed(1))
+    images = torch.empty((nv, W, W), device=dev)
+    dV = torch.zeros_like(gt)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    scale = 1.0 / (nv * W * W)
+
+    def make():
+        views = [_d.make_view(0, cams[i], w.step_world, images[i], target=targets[i])
+                 for i in range(nv)]
+        return _d.Batch([vol], None, views, _d.ABSORPTION, d_volumes=[dV])
+
+    key = workload_key(_device_arch(), _d.ABSORPTION, "bf16", 0, W, args.n, "V", _d.PASS_FUSED)
+    res = tune(key, make, lambda b: b.run(_d.PASS_FUSED, scale, loss), lambda: images,
+               reps=args.reps, verbose=True)
+    print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
+
+
+if __name__ == "__main__":
+    main()
