@@ -64,7 +64,7 @@ __device__ __forceinline__ float vload(const ViewDesc& vd, int64_t i) {
     if (vd.dtype == DDVR_BF16) return Vox<DDVR_BF16>::ld(vd.vol, i);
     return Vox<DDVR_F32>::ld(vd.vol, i);
   } else {
-    return vload<DT>(vd, i);
+    return Vox<DT>::ld(vd.vol, i);
   }
 }
 
