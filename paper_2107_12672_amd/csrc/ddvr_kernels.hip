@@ -398,11 +398,15 @@ __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br,
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void flush_brick(const ViewDesc& vd, const Brick& br, const float* acc) {
+// Add the brick's gradient accumulator to the density gradient in global
+// memory, one atomic per touched voxel.  FIX: the accumulator holds 32-bit
+// fixed-point values (see AdjState::qs), scaled back by inv_qs.
+template <int NT, bool FIX>
+__device__ __forceinline__ void flush_brick(const ViewDesc& vd, const Brick& br, const float* acc,
+                                            float inv_qs) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
   for (int idx = threadIdx.x; idx < br.size; idx += NT) {
-    const float g = acc[idx];
+    const float g = FIX ? (float)reinterpret_cast<const int*>(acc)[idx] * inv_qs : acc[idx];
     if (g != 0.0f) {
       const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
       const int rem = idx - z * br.bxy;
@@ -469,15 +473,30 @@ struct AdjState {
   // density gradient of the current cell (registers, flushed on cell exit)
   int64_t ckey;    // LDS brick offset or global index of the cell's corner 0; -1: none
   float cg[8];
+  // Scale of the 32-bit fixed-point LDS accumulation used by the absorption-only
+  // closed form (a power of two, uniform over the tile).  LDS integer atomics
+  // run at the rate of plain stores, float ones serialise per lane.
+  float qs;
 };
 
 // Add the registered density gradient of the current cell to the LDS brick
 // (LDS) or to global memory (direct slabs), then clear it.
-template <bool LDS>
+template <bool LDS, bool FIX>
 __device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, float* acc,
                                            AdjState& s) {
   if (s.ckey < 0) return;
-  if (LDS) {
+  if (LDS && FIX) {
+    const int base = (int)s.ckey;
+    int* ia = reinterpret_cast<int*>(acc);
+    atomicAdd(ia + base, __float2int_rn(s.cg[0] * s.qs));
+    atomicAdd(ia + base + 1, __float2int_rn(s.cg[1] * s.qs));
+    atomicAdd(ia + base + br.bx, __float2int_rn(s.cg[2] * s.qs));
+    atomicAdd(ia + base + br.bx + 1, __float2int_rn(s.cg[3] * s.qs));
+    atomicAdd(ia + base + br.bxy, __float2int_rn(s.cg[4] * s.qs));
+    atomicAdd(ia + base + br.bxy + 1, __float2int_rn(s.cg[5] * s.qs));
+    atomicAdd(ia + base + br.bxy + br.bx, __float2int_rn(s.cg[6] * s.qs));
+    atomicAdd(ia + base + br.bxy + br.bx + 1, __float2int_rn(s.cg[7] * s.qs));
+  } else if (LDS) {
     const int base = (int)s.ckey;
     atomicAdd(acc + base, s.cg[0]);
     atomicAdd(acc + base + 1, s.cg[1]);
@@ -524,6 +543,8 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
                                            const float4* tfl, float* dtf, int gmask,
                                            bool need_v, bool cell_acc, AdjState& s,
                                            float Ti_given) {
+  // the absorption-only closed form accumulates the LDS brick in fixed point
+  constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
   Cell c;
   locate(r, i, vd.nx, vd.ny, vd.nz, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
@@ -603,7 +624,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     const int64_t key = LDS ? (int64_t)base
                             : (int64_t)c.k[2] * vd.nx * vd.ny + (int64_t)c.k[1] * vd.nx + c.k[0];
     if (key != s.ckey) {
-      cell_flush<LDS>(vd, br, acc, s);
+      cell_flush<LDS, FIX>(vd, br, acc, s);
       s.ckey = key;
     }
 #pragma unroll
@@ -611,7 +632,18 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   } else if (gmask & GRAD_V) {
     float w[8];
     trilerp_weights(c.f, w);
-    if (LDS) {
+    if (FIX) {
+      int* ia = reinterpret_cast<int*>(acc);
+      const float q = d_hat * s.qs;
+      atomicAdd(ia + base, __float2int_rn(w[0] * q));
+      atomicAdd(ia + base + 1, __float2int_rn(w[1] * q));
+      atomicAdd(ia + base + br.bx, __float2int_rn(w[2] * q));
+      atomicAdd(ia + base + br.bx + 1, __float2int_rn(w[3] * q));
+      atomicAdd(ia + base + br.bxy, __float2int_rn(w[4] * q));
+      atomicAdd(ia + base + br.bxy + 1, __float2int_rn(w[5] * q));
+      atomicAdd(ia + base + br.bxy + br.bx, __float2int_rn(w[6] * q));
+      atomicAdd(ia + base + br.bxy + br.bx + 1, __float2int_rn(w[7] * q));
+    } else if (LDS) {
       atomicAdd(acc + base, w[0] * d_hat);
       atomicAdd(acc + base + 1, w[1] * d_hat);
       atomicAdd(acc + base + br.bx, w[2] * d_hat);
@@ -655,7 +687,8 @@ __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int
   for (int i = b - 1; i >= a; --i)
     adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v,
                                      cell_acc, s, 0.0f);
-  if (cell_acc) cell_flush<LDS>(vd, br, acc, s);   // the brick changes with the slab
+  constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
+  if (cell_acc) cell_flush<LDS, FIX>(vd, br, acc, s);   // the brick changes with the slab
 }
 
 // Camera adjoint of one ray (last line of Alg. 2 on [x_o_hat; omega_hat]).
@@ -880,17 +913,47 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
 
-  const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || mode != DDVR_ADJ_AUTO;
+  // Fixed-point scale of the absorption-only closed form.  Every sample adds
+  // d_hat = dt*T_N*ahat (constant along the ray) times trilinear weights <= 1,
+  // and a straight ray has at most lmax samples in the 2x2x2 cells around a
+  // voxel (chord <= 2*sqrt(3) voxels), so no brick entry of the tile exceeds
+  // B = NT * max|d_hat| * lmax in magnitude; qs = 2^(29 - ceil(log2 B)) keeps
+  // every partial sum below 2^29.  A tile whose bound is not finite (NaN or
+  // Inf upstream gradients) takes the float32 T-form route without LDS
+  // bricks, which propagates them.
+  const bool closed_form = !EA && mode == DDVR_ADJ_AUTO;
+  s.qs = 1.0f;
+  float inv_qs = 1.0f;
+  bool fix_ok = true;
   {
-    int e = Nadj > 0 ? off + Nadj : 0;
-    wg_max_n<NT>(&e, 1, iscratch);
-    tile_end = e;
+    const float m = (closed_form && want_dv && Nadj > 0) ? fabsf(vd.step * s.P) : 0.0f;
+    int v2[2] = {Nadj > 0 ? off + Nadj : 0, __float_as_int(m)};
+    wg_max_n<NT>(v2, 2, iscratch);
+    tile_end = v2[0];
+    const float lmax = floorf(3.4641017f / (vd.step * vd.inv_h)) + 2.0f;
+    const float B = __int_as_float(v2[1]) * (float)NT * lmax;
+    if (!(B < INFINITY)) {
+      fix_ok = false;
+    } else if (B > 0.0f) {
+      int ex;
+      (void)frexpf(B, &ex);          // B < 2^ex
+      const int e = 29 - ex;
+      if (e > 120) {
+        fix_ok = false;              // subnormal-scale gradients: float32 route
+      } else {
+        s.qs = ldexpf(1.0f, max(e, -120));
+        inv_qs = ldexpf(1.0f, -max(e, -120));
+      }
+    }
   }
+  const bool use_fix = closed_form && fix_ok;
+  const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || !use_fix;
+  const int acap = fix_ok ? cap : 0;
   int K = min(vd.slab_k, kmax);
   for (int pos = tile_end; pos > 0;) {
     int lo, hi;
     Brick br;
-    const int st = pick_slab<NT>(vd, r, off, Nadj, pos, -1, 0, cap, K, kmax, lo, hi, iscratch,
+    const int st = pick_slab<NT>(vd, r, off, Nadj, pos, -1, 0, acap, K, kmax, lo, hi, iscratch,
                                  br);
     pos = lo;
     if (st == 0) continue;
@@ -899,7 +962,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     if (st == 1) {
       stage_brick<NT, DT>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
-      if (!EA && mode == DDVR_ADJ_AUTO)
+      if (use_fix)
         march_adj<MODEL, DT, true, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
@@ -909,9 +972,12 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
         march_adj<MODEL, DT, true, 1, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       __syncthreads();
-      if (want_dv) flush_brick<NT>(vd, br, acc);
+      if (want_dv) {
+        if (use_fix) flush_brick<NT, true>(vd, br, acc, inv_qs);
+        else flush_brick<NT, false>(vd, br, acc, 1.0f);
+      }
     } else {
-      if (!EA && mode == DDVR_ADJ_AUTO)
+      if (use_fix)
         march_adj<MODEL, DT, false, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                        p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)
@@ -1032,6 +1098,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
     s.tj = -1;
     for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
     s.ckey = -1;
+    s.qs = 1.0f;
     for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
     Brick br{};
     for (int sg = nseg - 1; sg >= 0; --sg) {
