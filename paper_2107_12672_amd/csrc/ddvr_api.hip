@@ -172,6 +172,7 @@ void fill_view(ViewDesc& d, const ddvr_volume* v, const ddvr_tf* tf, const ddvr_
   for (int a = 0; a < 3; ++a) {
     d.bmin[a] = (float)(-0.5 * (n[a] - 1) * h);
     d.bmax[a] = (float)(0.5 * (n[a] - 1) * h);
+    d.qhi[a] = std::nextafter((float)(n[a] - 1), 0.0f);
   }
   if (model == DDVR_EMISSION_ABSORPTION) { d.tf = tf->rgba_tau; d.R = tf->R; }
   const int tw = tile_w(g_tuning.waves), th = tile_h(g_tuning.waves);

@@ -17,6 +17,7 @@ struct ViewDesc {
   int32_t nx, ny, nz;
   float h, inv_h;
   float bmin[3], bmax[3];
+  float qhi[3];           // largest float below n-1 per axis (grid-unit clamp of positions)
   // transfer function [R][4]
   const float* tf;
   int32_t R;

@@ -128,6 +128,10 @@ __device__ __forceinline__ void setup_ray(const ViewDesc& vd, int px, int py, bo
 }
 
 // Trilinear cell of sample i: k = clamp(floor(q), 0, n-2), f = q - k.
+// Samples lie inside the grid box, so q leaves [0, n-1) only by rounding; the
+// position is clamped to [0, qhi] (qhi the float just below n-1) first, which
+// moves it by at most one ulp, after which truncation is the floor and the
+// fraction is exact: three instructions per axis (med3, cvt, fract).
 // fmaf(i, dq, qo) is monotone in i, so the cells of a run of samples lie
 // inside the box spanned by the run's first and last cells.
 struct Cell {
@@ -135,16 +139,13 @@ struct Cell {
   float f[3];
 };
 
-__device__ __forceinline__ void locate(const RayG& r, int i, int nx, int ny, int nz, Cell& c) {
+__device__ __forceinline__ void locate(const RayG& r, int i, const ViewDesc& vd, Cell& c) {
   const float fi = (float)i;
-  const int n[3] = {nx, ny, nz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float q = fmaf(fi, r.dq[a], r.qo[a]);
-    int k = (int)floorf(q);
-    k = min(max(k, 0), n[a] - 2);
-    c.k[a] = k;
-    c.f[a] = q - (float)k;
+    const float q = __builtin_amdgcn_fmed3f(fmaf(fi, r.dq[a], r.qo[a]), 0.0f, vd.qhi[a]);
+    c.k[a] = (int)q;
+    c.f[a] = __builtin_amdgcn_fractf(q);
   }
 }
 
@@ -167,22 +168,56 @@ struct Brick {   // LDS brick of the current slab
   int x0, y0, z0;
   int bx, bxy;
   int size;
+  int bx4, bxy4;  // row and plane strides in bytes
+  int off4;       // -4*(x0 + y0*bx + z0*bxy)
   float inv_bx, inv_bxy;
 };
 
+// Byte offset in the brick of a cell's corner 0, 4*(k0 + k1*bx + k2*bxy) +
+// off4, with 24-bit multiply-adds (operands < 2^24; the 32-bit result wraps
+// back into range).
 __device__ __forceinline__ int brick_base(const Brick& br, const Cell& c) {
-  return (c.k[2] - br.z0) * br.bxy + (c.k[1] - br.y0) * br.bx + (c.k[0] - br.x0);
+  return (int)(__umul24((unsigned)c.k[2], (unsigned)br.bxy4) +
+               __umul24((unsigned)c.k[1], (unsigned)br.bx4) +
+               (unsigned)(4 * c.k[0] + br.off4));
 }
 
+// The 8 corners of a cell in the brick (index cx + 2*cy + 4*cz), as two
+// adjacent floats at each of four byte addresses.
 __device__ __forceinline__ void fetch_lds(const float* st, const Brick& br, int base, float* v) {
-  v[0] = st[base];
-  v[1] = st[base + 1];
-  v[2] = st[base + br.bx];
-  v[3] = st[base + br.bx + 1];
-  v[4] = st[base + br.bxy];
-  v[5] = st[base + br.bxy + 1];
-  v[6] = st[base + br.bxy + br.bx];
-  v[7] = st[base + br.bxy + br.bx + 1];
+  const char* p0 = reinterpret_cast<const char*>(st) + base;
+  const char* p1 = p0 + br.bx4;
+  const char* p2 = p0 + br.bxy4;
+  const char* p3 = p2 + br.bx4;
+  v[0] = reinterpret_cast<const float*>(p0)[0];
+  v[1] = reinterpret_cast<const float*>(p0)[1];
+  v[2] = reinterpret_cast<const float*>(p1)[0];
+  v[3] = reinterpret_cast<const float*>(p1)[1];
+  v[4] = reinterpret_cast<const float*>(p2)[0];
+  v[5] = reinterpret_cast<const float*>(p2)[1];
+  v[6] = reinterpret_cast<const float*>(p3)[0];
+  v[7] = reinterpret_cast<const float*>(p3)[1];
+}
+
+// Add 8 corner values to the LDS gradient brick: float atomics, or (FIX)
+// 32-bit integer atomics of values already in fixed-point units.
+template <bool FIX>
+__device__ __forceinline__ void lds_add8(float* acc, const Brick& br, int base, const float* g) {
+  char* p0 = reinterpret_cast<char*>(acc) + base;
+  char* p1 = p0 + br.bx4;
+  char* p2 = p0 + br.bxy4;
+  char* p3 = p2 + br.bx4;
+  char* const pc[4] = {p0, p1, p2, p3};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (FIX) {
+      atomicAdd(reinterpret_cast<int*>(pc[k]), __float2int_rn(g[2 * k]));
+      atomicAdd(reinterpret_cast<int*>(pc[k]) + 1, __float2int_rn(g[2 * k + 1]));
+    } else {
+      atomicAdd(reinterpret_cast<float*>(pc[k]), g[2 * k]);
+      atomicAdd(reinterpret_cast<float*>(pc[k]) + 1, g[2 * k + 1]);
+    }
+  }
 }
 
 // f_interpolate and its derivative w.r.t. the cell-local coordinates f.
@@ -330,8 +365,8 @@ __device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, in
   int v[6];
   if (a < b) {
     Cell c0, c1;
-    locate(r, a, vd.nx, vd.ny, vd.nz, c0);
-    locate(r, b - 1, vd.nx, vd.ny, vd.nz, c1);
+    locate(r, a, vd, c0);
+    locate(r, b - 1, vd, c1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       v[k] = -min(c0.k[k], c1.k[k]);
@@ -348,6 +383,9 @@ __device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, in
   br.bx = bx;
   br.bxy = bx * by;
   br.size = br.bxy * bz;
+  br.bx4 = 4 * bx;
+  br.bxy4 = 4 * br.bxy;
+  br.off4 = -4 * (br.x0 + br.y0 * bx + br.z0 * br.bxy);
   br.inv_bx = 1.0f / (float)bx;
   br.inv_bxy = 1.0f / (float)br.bxy;
   return true;
@@ -386,16 +424,32 @@ template <int NT, int DT>
 __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br, float* stage,
                                             float* acc) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
-  for (int idx = threadIdx.x; idx < br.size; idx += NT) {
-    if (stage) {
-      const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
-      const int rem = idx - z * br.bxy;
-      const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
-      const int x = rem - y * br.bx;
-      stage[idx] = vload<DT>(vd, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
+  if (stage) {
+    // U loads in flight per lane before the first LDS write
+    constexpr int U = 4;
+    for (int i0 = threadIdx.x; i0 < br.size; i0 += U * NT) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = i0 + u * NT;
+        v[u] = 0.0f;
+        if (idx < br.size) {
+          const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
+          const int rem = idx - z * br.bxy;
+          const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
+          const int x = rem - y * br.bx;
+          v[u] = vload<DT>(vd, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = i0 + u * NT;
+        if (idx < br.size) stage[idx] = v[u];
+      }
     }
-    if (acc) acc[idx] = 0.0f;
   }
+  if (acc)
+    for (int idx = threadIdx.x; idx < br.size; idx += NT) acc[idx] = 0.0f;
 }
 
 // Add the brick's gradient accumulator to the density gradient in global
@@ -432,7 +486,7 @@ __device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int
                                           const float4* tfl, FwdState& s) {
   for (int i = a; i < b; ++i) {
     Cell c;
-    locate(r, i, vd.nx, vd.ny, vd.nz, c);
+    locate(r, i, vd, c);
     float v[8];
     if (LDS) fetch_lds(stage, br, brick_base(br, c), v);
     else fetch_global<DT>(vd, c, v);
@@ -461,6 +515,8 @@ struct AdjState {
   float Tn;        // T^(i+1) (inversion state)
   float an;        // alpha^(i+1) (alpha-form inversion state)
   float P;         // absorption-only closed form: T^(i+1)*ahat^(i+1), constant
+  float dh;        // absorption-only closed form: d_hat = dt*P of every sample
+  float dhq;       // dh * qs (fixed-point units)
   // Ray sums behind the camera and step gradients, kept in float64: they add
   // up to thousands of terms of both signs (weighted by i), and float32 would
   // lose ~1e-3 of the result to cancellation on long rays.
@@ -471,7 +527,8 @@ struct AdjState {
   int tj;
   float tg0[4], tg1[4];
   // density gradient of the current cell (registers, flushed on cell exit)
-  int64_t ckey;    // LDS brick offset or global index of the cell's corner 0; -1: none
+  int ckey;        // LDS byte offset of the cell's corner 0 (staged slabs); -1: none
+  int64_t gkey;    // global index of the cell's corner 0 (direct slabs); -1: none
   float cg[8];
   // Scale of the 32-bit fixed-point LDS accumulation used by the absorption-only
   // closed form (a power of two, uniform over the tile).  LDS integer atomics
@@ -484,31 +541,13 @@ struct AdjState {
 template <bool LDS, bool FIX>
 __device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, float* acc,
                                            AdjState& s) {
-  if (s.ckey < 0) return;
-  if (LDS && FIX) {
-    const int base = (int)s.ckey;
-    int* ia = reinterpret_cast<int*>(acc);
-    atomicAdd(ia + base, __float2int_rn(s.cg[0] * s.qs));
-    atomicAdd(ia + base + 1, __float2int_rn(s.cg[1] * s.qs));
-    atomicAdd(ia + base + br.bx, __float2int_rn(s.cg[2] * s.qs));
-    atomicAdd(ia + base + br.bx + 1, __float2int_rn(s.cg[3] * s.qs));
-    atomicAdd(ia + base + br.bxy, __float2int_rn(s.cg[4] * s.qs));
-    atomicAdd(ia + base + br.bxy + 1, __float2int_rn(s.cg[5] * s.qs));
-    atomicAdd(ia + base + br.bxy + br.bx, __float2int_rn(s.cg[6] * s.qs));
-    atomicAdd(ia + base + br.bxy + br.bx + 1, __float2int_rn(s.cg[7] * s.qs));
-  } else if (LDS) {
-    const int base = (int)s.ckey;
-    atomicAdd(acc + base, s.cg[0]);
-    atomicAdd(acc + base + 1, s.cg[1]);
-    atomicAdd(acc + base + br.bx, s.cg[2]);
-    atomicAdd(acc + base + br.bx + 1, s.cg[3]);
-    atomicAdd(acc + base + br.bxy, s.cg[4]);
-    atomicAdd(acc + base + br.bxy + 1, s.cg[5]);
-    atomicAdd(acc + base + br.bxy + br.bx, s.cg[6]);
-    atomicAdd(acc + base + br.bxy + br.bx + 1, s.cg[7]);
+  if (LDS) {
+    if (s.ckey < 0) return;
+    lds_add8<FIX>(acc, br, s.ckey, s.cg);
   } else {
+    if (s.gkey < 0) return;
     const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
-    float* g = vd.dV + s.ckey;
+    float* g = vd.dV + s.gkey;
     atomicAdd(g, s.cg[0]);
     atomicAdd(g + 1, s.cg[1]);
     atomicAdd(g + sy, s.cg[2]);
@@ -520,7 +559,8 @@ __device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, 
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
-  s.ckey = -1;
+  if (LDS) s.ckey = -1;
+  else s.gkey = -1;
 }
 
 __device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
@@ -546,7 +586,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   // the absorption-only closed form accumulates the LDS brick in fixed point
   constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
   Cell c;
-  locate(r, i, vd.nx, vd.ny, vd.nz, c);
+  locate(r, i, vd, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
   // registers the density-only kernels do not pay for)
   const bool need_xhat = XH && (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
@@ -563,7 +603,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   if (MODEL == DDVR_ABSORPTION && MODE == 0) {
     // T^(i)*e_i*ahat^(i+1) = T^(i+1)*ahat^(i+1) is invariant under the
     // inversion T^(i) = T^(i+1)/e_i, ahat^(i) = e_i*ahat^(i+1) (no emission).
-    d_hat = vd.step * s.P;
+    d_hat = s.dh;
     if (XH) s.dstep += (double)(d * s.P);
   } else {
     float rgb[3] = {0.0f, 0.0f, 0.0f}, tau;
@@ -618,40 +658,43 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   }
   if ((gmask & GRAD_V) && cell_acc) {
     // accumulate while the ray stays in this cell (Sec. 4.4: per-ray registers
-    // flushed on exit of the current cell)
-    float w[8];
-    trilerp_weights(c.f, w);
-    const int64_t key = LDS ? (int64_t)base
-                            : (int64_t)c.k[2] * vd.nx * vd.ny + (int64_t)c.k[1] * vd.nx + c.k[0];
-    if (key != s.ckey) {
-      cell_flush<LDS, FIX>(vd, br, acc, s);
-      s.ckey = key;
+    // flushed on exit of the current cell); the fixed-point route accumulates
+    // in fixed-point units.  Weights w_c * d_hat with d_hat folded into the x
+    // factors.
+    const float dv = FIX ? s.dhq : d_hat;
+    const float gx = 1.0f - c.f[0], gy = 1.0f - c.f[1], gz = 1.0f - c.f[2];
+    const float d0 = gx * dv, d1 = c.f[0] * dv;
+    const float a00 = gy * gz, a10 = c.f[1] * gz, a01 = gy * c.f[2], a11 = c.f[1] * c.f[2];
+    if (LDS) {
+      if (base != s.ckey) {
+        cell_flush<LDS, FIX>(vd, br, acc, s);
+        s.ckey = base;
+      }
+    } else {
+      const int64_t key =
+          (int64_t)c.k[2] * vd.nx * vd.ny + (int64_t)c.k[1] * vd.nx + c.k[0];
+      if (key != s.gkey) {
+        cell_flush<LDS, FIX>(vd, br, acc, s);
+        s.gkey = key;
+      }
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s.cg[k] = fmaf(w[k], d_hat, s.cg[k]);
+    s.cg[0] = fmaf(d0, a00, s.cg[0]);
+    s.cg[1] = fmaf(d1, a00, s.cg[1]);
+    s.cg[2] = fmaf(d0, a10, s.cg[2]);
+    s.cg[3] = fmaf(d1, a10, s.cg[3]);
+    s.cg[4] = fmaf(d0, a01, s.cg[4]);
+    s.cg[5] = fmaf(d1, a01, s.cg[5]);
+    s.cg[6] = fmaf(d0, a11, s.cg[6]);
+    s.cg[7] = fmaf(d1, a11, s.cg[7]);
   } else if (gmask & GRAD_V) {
     float w[8];
     trilerp_weights(c.f, w);
-    if (FIX) {
-      int* ia = reinterpret_cast<int*>(acc);
-      const float q = d_hat * s.qs;
-      atomicAdd(ia + base, __float2int_rn(w[0] * q));
-      atomicAdd(ia + base + 1, __float2int_rn(w[1] * q));
-      atomicAdd(ia + base + br.bx, __float2int_rn(w[2] * q));
-      atomicAdd(ia + base + br.bx + 1, __float2int_rn(w[3] * q));
-      atomicAdd(ia + base + br.bxy, __float2int_rn(w[4] * q));
-      atomicAdd(ia + base + br.bxy + 1, __float2int_rn(w[5] * q));
-      atomicAdd(ia + base + br.bxy + br.bx, __float2int_rn(w[6] * q));
-      atomicAdd(ia + base + br.bxy + br.bx + 1, __float2int_rn(w[7] * q));
-    } else if (LDS) {
-      atomicAdd(acc + base, w[0] * d_hat);
-      atomicAdd(acc + base + 1, w[1] * d_hat);
-      atomicAdd(acc + base + br.bx, w[2] * d_hat);
-      atomicAdd(acc + base + br.bx + 1, w[3] * d_hat);
-      atomicAdd(acc + base + br.bxy, w[4] * d_hat);
-      atomicAdd(acc + base + br.bxy + 1, w[5] * d_hat);
-      atomicAdd(acc + base + br.bxy + br.bx, w[6] * d_hat);
-      atomicAdd(acc + base + br.bxy + br.bx + 1, w[7] * d_hat);
+    if (LDS) {
+      const float q = FIX ? s.dhq : d_hat;
+      float g[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) g[k] = w[k] * q;
+      lds_add8<FIX>(acc, br, base, g);
     } else {
       const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
       float* g = vd.dV + (c.k[2] * sz + c.k[1] * sy + c.k[0]);
@@ -910,6 +953,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
   s.ckey = -1;
+  s.gkey = -1;
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
 
@@ -947,6 +991,8 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     }
   }
   const bool use_fix = closed_form && fix_ok;
+  s.dh = vd.step * s.P;
+  s.dhq = s.dh * s.qs;
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || !use_fix;
   const int acap = fix_ok ? cap : 0;
   int K = min(vd.slab_k, kmax);
@@ -1077,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       for (int i = 0; i < N; ++i) {
         if (i % K == 0) ck[i / K] = T;
         Cell c;
-        locate(r, i, vd.nx, vd.ny, vd.nz, c);
+        locate(r, i, vd, c);
         float v[8];
         fetch_global<DT>(vd, c, v);
         const float d = trilerp(v, c.f);
@@ -1098,7 +1144,9 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
     s.tj = -1;
     for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
     s.ckey = -1;
+    s.gkey = -1;
     s.qs = 1.0f;
+    s.dh = 0.0f; s.dhq = 0.0f;
     for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
     Brick br{};
     for (int sg = nseg - 1; sg >= 0; --sg) {
@@ -1106,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       tseg[0] = ck[sg];
       for (int i = i0; i < i1; ++i) {
         Cell c;
-        locate(r, i, vd.nx, vd.ny, vd.nz, c);
+        locate(r, i, vd, c);
         float v[8];
         fetch_global<DT>(vd, c, v);
         const float d = trilerp(v, c.f);
