@@ -35,20 +35,35 @@ namespace ddvr {
 // ---------------------------------------------------------------------------
 // storage types of the density grid
 // ---------------------------------------------------------------------------
+// The grid and the gradients live in global memory; loads and atomics go
+// through the global address space (not flat), so they count only against
+// the vector-memory counter and can stay in flight across LDS traffic.
+#define DDVR_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const DDVR_GLOBAL T* gmem(const void* p) {
+  return (const DDVR_GLOBAL T*)p;
+}
+// float atomic add to global memory (gradients), result unused
+__device__ __forceinline__ void gadd(float* p, float v) {
+  (void)__hip_atomic_fetch_add((DDVR_GLOBAL float*)p, v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int DT> struct Vox;
 template <> struct Vox<DDVR_F32> {
   static __device__ __forceinline__ float ld(const void* p, int64_t i) {
-    return static_cast<const float*>(p)[i];
+    return gmem<float>(p)[i];
   }
 };
 template <> struct Vox<DDVR_F16> {
   static __device__ __forceinline__ float ld(const void* p, int64_t i) {
-    return __half2float(static_cast<const __half*>(p)[i]);
+    return __half2float(__ushort_as_half(gmem<unsigned short>(p)[i]));
   }
 };
 template <> struct Vox<DDVR_BF16> {
   static __device__ __forceinline__ float ld(const void* p, int64_t i) {
-    const uint32_t u = static_cast<const uint16_t*>(p)[i];
+    const uint32_t u = gmem<unsigned short>(p)[i];
     return __uint_as_float(u << 16);
   }
 };
@@ -418,35 +433,55 @@ __device__ __forceinline__ int pick_slab(const ViewDesc& vd, const RayG& r, int 
   }
 }
 
+// Offset in the grid of brick element idx (x fastest, then y, then z)
+// relative to the brick's corner voxel.  Row and plane indices come from
+// float reciprocals (exact: idx + 0.5 stays at least 0.5/bxy from a multiple
+// of bxy and bricks hold < 2^21 elements); the offset uses 24-bit
+// multiply-adds when the brick's span in the grid fits 31 bits (`narrow`).
+template <bool NARROW>
+__device__ __forceinline__ int64_t brick_goff(const Brick& br, int idx, int64_t sy, int64_t sz) {
+  const int z = (int)fmaf((float)idx, br.inv_bxy, 0.5f * br.inv_bxy);
+  const int rem = idx - __mul24(z, br.bxy);
+  const int y = (int)fmaf((float)rem, br.inv_bx, 0.5f * br.inv_bx);
+  const int x = rem - __mul24(y, br.bx);
+  if (NARROW)
+    return (int64_t)(uint32_t)(x + __umul24((unsigned)y, (unsigned)sy) +
+                               __umul24((unsigned)z, (unsigned)sz));
+  return x + y * sy + z * sz;
+}
+
+__device__ __forceinline__ bool brick_narrow(const Brick& br, int64_t sz) {
+  return sz < (1 << 24) && (int64_t)(br.size / br.bxy) * sz < (int64_t(1) << 31);
+}
+
+// Copy the brick's grid values into LDS as float32: U loads in flight per
+// lane (lanes past the end re-read the last element, so the loads need no
+// branch) before the LDS writes.
+template <int NT, int DT, bool NARROW>
+__device__ __forceinline__ void stage_loads(const ViewDesc& vd, const Brick& br, float* stage,
+                                            int64_t org, int64_t sy, int64_t sz) {
+  constexpr int U = 8;
+  for (int i0 = threadIdx.x; i0 < br.size; i0 += U * NT) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = vload<DT>(vd, org + brick_goff<NARROW>(br, min(i0 + u * NT, br.size - 1), sy, sz));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * NT < br.size) stage[i0 + u * NT] = v[u];
+  }
+}
+
 // Stage the brick's grid values (as float32) and/or zero its gradient
 // accumulator.  The caller synchronises before the brick is read.
 template <int NT, int DT>
 __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br, float* stage,
                                             float* acc) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  const int64_t org = br.z0 * sz + br.y0 * sy + br.x0;
   if (stage) {
-    // U loads in flight per lane before the first LDS write
-    constexpr int U = 4;
-    for (int i0 = threadIdx.x; i0 < br.size; i0 += U * NT) {
-      float v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int idx = i0 + u * NT;
-        v[u] = 0.0f;
-        if (idx < br.size) {
-          const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
-          const int rem = idx - z * br.bxy;
-          const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
-          const int x = rem - y * br.bx;
-          v[u] = vload<DT>(vd, (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x));
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int idx = i0 + u * NT;
-        if (idx < br.size) stage[idx] = v[u];
-      }
-    }
+    if (brick_narrow(br, sz)) stage_loads<NT, DT, true>(vd, br, stage, org, sy, sz);
+    else stage_loads<NT, DT, false>(vd, br, stage, org, sy, sz);
   }
   if (acc)
     for (int idx = threadIdx.x; idx < br.size; idx += NT) acc[idx] = 0.0f;
@@ -459,15 +494,13 @@ template <int NT, bool FIX>
 __device__ __forceinline__ void flush_brick(const ViewDesc& vd, const Brick& br, const float* acc,
                                             float inv_qs) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  float* const org = vd.dV + (br.z0 * sz + br.y0 * sy + br.x0);
+  const bool narrow = brick_narrow(br, sz);
   for (int idx = threadIdx.x; idx < br.size; idx += NT) {
     const float g = FIX ? (float)reinterpret_cast<const int*>(acc)[idx] * inv_qs : acc[idx];
-    if (g != 0.0f) {
-      const int z = (int)(((float)idx + 0.5f) * br.inv_bxy);
-      const int rem = idx - z * br.bxy;
-      const int y = (int)(((float)rem + 0.5f) * br.inv_bx);
-      const int x = rem - y * br.bx;
-      atomicAdd(vd.dV + (br.z0 + z) * sz + (br.y0 + y) * sy + (br.x0 + x), g);
-    }
+    if (g != 0.0f)
+      gadd(org + (narrow ? brick_goff<true>(br, idx, sy, sz)
+                         : brick_goff<false>(br, idx, sy, sz)), g);
   }
 }
 
@@ -548,14 +581,14 @@ __device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, 
     if (s.gkey < 0) return;
     const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
     float* g = vd.dV + s.gkey;
-    atomicAdd(g, s.cg[0]);
-    atomicAdd(g + 1, s.cg[1]);
-    atomicAdd(g + sy, s.cg[2]);
-    atomicAdd(g + sy + 1, s.cg[3]);
-    atomicAdd(g + sz, s.cg[4]);
-    atomicAdd(g + sz + 1, s.cg[5]);
-    atomicAdd(g + sz + sy, s.cg[6]);
-    atomicAdd(g + sz + sy + 1, s.cg[7]);
+    gadd(g, s.cg[0]);
+    gadd(g + 1, s.cg[1]);
+    gadd(g + sy, s.cg[2]);
+    gadd(g + sy + 1, s.cg[3]);
+    gadd(g + sz, s.cg[4]);
+    gadd(g + sz + 1, s.cg[5]);
+    gadd(g + sz + sy, s.cg[6]);
+    gadd(g + sz + sy + 1, s.cg[7]);
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
@@ -698,14 +731,14 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     } else {
       const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
       float* g = vd.dV + (c.k[2] * sz + c.k[1] * sy + c.k[0]);
-      atomicAdd(g, w[0] * d_hat);
-      atomicAdd(g + 1, w[1] * d_hat);
-      atomicAdd(g + sy, w[2] * d_hat);
-      atomicAdd(g + sy + 1, w[3] * d_hat);
-      atomicAdd(g + sz, w[4] * d_hat);
-      atomicAdd(g + sz + 1, w[5] * d_hat);
-      atomicAdd(g + sz + sy, w[6] * d_hat);
-      atomicAdd(g + sz + sy + 1, w[7] * d_hat);
+      gadd(g, w[0] * d_hat);
+      gadd(g + 1, w[1] * d_hat);
+      gadd(g + sy, w[2] * d_hat);
+      gadd(g + sy + 1, w[3] * d_hat);
+      gadd(g + sz, w[4] * d_hat);
+      gadd(g + sz + 1, w[5] * d_hat);
+      gadd(g + sz + sy, w[6] * d_hat);
+      gadd(g + sz + sy + 1, w[7] * d_hat);
     }
   }
   if (need_xhat) {
@@ -1043,14 +1076,14 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     if (threadIdx.x == 0) {
       if (gmask & GRAD_CAM)
         for (int k = 0; k < 12; ++k)
-          if (cg[k] != 0.0f) atomicAdd(vd.dcam + k, cg[k]);
-      if ((gmask & GRAD_STEP) && cg[12] != 0.0f) atomicAdd(vd.dstep, cg[12]);
+          if (cg[k] != 0.0f) gadd(vd.dcam + k, cg[k]);
+      if ((gmask & GRAD_STEP) && cg[12] != 0.0f) gadd(vd.dstep, cg[12]);
     }
   }
   if (EA && (gmask & GRAD_TF)) {
     __syncthreads();
     for (int k = threadIdx.x; k < 4 * vd.R; k += NT)
-      if (dtf[k] != 0.0f) atomicAdd(vd.dTF + k, dtf[k]);
+      if (dtf[k] != 0.0f) gadd(vd.dTF + k, dtf[k]);
   }
 }
 
@@ -1171,8 +1204,8 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       float cg[13];
       camera_adjoint(vd, r, s, true, cg);
       if (gmask & GRAD_CAM)
-        for (int k = 0; k < 12; ++k) atomicAdd(vd.dcam + k, cg[k]);
-      if (gmask & GRAD_STEP) atomicAdd(vd.dstep, cg[12]);
+        for (int k = 0; k < 12; ++k) gadd(vd.dcam + k, cg[k]);
+      if (gmask & GRAD_STEP) gadd(vd.dstep, cg[12]);
     }
   }
 }
