@@ -154,8 +154,9 @@ struct Cell {
   float f[3];
 };
 
-__device__ __forceinline__ void locate(const RayG& r, int i, const ViewDesc& vd, Cell& c) {
-  const float fi = (float)i;
+// (sample indices stay below 2^22, so they are exact as floats and the march
+// loops count in float)
+__device__ __forceinline__ void locate(const RayG& r, float fi, const ViewDesc& vd, Cell& c) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float q = __builtin_amdgcn_fmed3f(fmaf(fi, r.dq[a], r.qo[a]), 0.0f, vd.qhi[a]);
@@ -214,6 +215,14 @@ __device__ __forceinline__ void fetch_lds(const float* st, const Brick& br, int 
   v[7] = reinterpret_cast<const float*>(p3)[1];
 }
 
+// float -> int32 rounding to nearest (halves up) in one instruction
+// (floor(x + 0.5)); fixed-point values here stay below 2^29 in magnitude.
+__device__ __forceinline__ int round_i32(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // Add 8 corner values to the LDS gradient brick: float atomics, or (FIX)
 // 32-bit integer atomics of values already in fixed-point units.
 template <bool FIX>
@@ -226,8 +235,8 @@ __device__ __forceinline__ void lds_add8(float* acc, const Brick& br, int base, 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (FIX) {
-      atomicAdd(reinterpret_cast<int*>(pc[k]), __float2int_rn(g[2 * k]));
-      atomicAdd(reinterpret_cast<int*>(pc[k]) + 1, __float2int_rn(g[2 * k + 1]));
+      atomicAdd(reinterpret_cast<int*>(pc[k]), round_i32(g[2 * k]));
+      atomicAdd(reinterpret_cast<int*>(pc[k]) + 1, round_i32(g[2 * k + 1]));
     } else {
       atomicAdd(reinterpret_cast<float*>(pc[k]), g[2 * k]);
       atomicAdd(reinterpret_cast<float*>(pc[k]) + 1, g[2 * k + 1]);
@@ -380,8 +389,8 @@ __device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, in
   int v[6];
   if (a < b) {
     Cell c0, c1;
-    locate(r, a, vd, c0);
-    locate(r, b - 1, vd, c1);
+    locate(r, (float)a, vd, c0);
+    locate(r, (float)(b - 1), vd, c1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       v[k] = -min(c0.k[k], c1.k[k]);
@@ -517,9 +526,10 @@ template <int MODEL, int DT, bool LDS>
 __device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int a, int b,
                                           const float* stage, const Brick& br,
                                           const float4* tfl, FwdState& s) {
-  for (int i = a; i < b; ++i) {
+  const float fb = (float)b;
+  for (float fi = (float)a; fi < fb; fi += 1.0f) {
     Cell c;
-    locate(r, i, vd, c);
+    locate(r, fi, vd, c);
     float v[8];
     if (LDS) fetch_lds(stage, br, brick_base(br, c), v);
     else fetch_global<DT>(vd, c, v);
@@ -611,7 +621,7 @@ __device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
 // recovered: 0 closed form (AO), 1 T-form inversion, 2 alpha-form inversion,
 // 3 caller supplies Ti (checkpoint).
 template <int MODEL, int DT, bool LDS, int MODE, bool XH>
-__device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, int i,
+__device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, float fi,
                                            const float* stage, float* acc, const Brick& br,
                                            const float4* tfl, float* dtf, int gmask,
                                            bool need_v, bool cell_acc, AdjState& s,
@@ -619,7 +629,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
   // the absorption-only closed form accumulates the LDS brick in fixed point
   constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
   Cell c;
-  locate(r, i, vd, c);
+  locate(r, fi, vd, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
   // registers the density-only kernels do not pay for)
   const bool need_xhat = XH && (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
@@ -745,7 +755,6 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, in
     float gd[3];
     trilerp_grad(v, c.f, gd);
     const float sc = d_hat * vd.inv_h;
-    const float fi = (float)i;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float xh = sc * gd[a];
@@ -760,8 +769,9 @@ __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int
                                           const float* stage, float* acc, const Brick& br,
                                           const float4* tfl, float* dtf, int gmask, bool need_v,
                                           bool cell_acc, AdjState& s) {
-  for (int i = b - 1; i >= a; --i)
-    adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, i, stage, acc, br, tfl, dtf, gmask, need_v,
+  const float fa = (float)a;
+  for (float fi = (float)(b - 1); fi >= fa; fi -= 1.0f)
+    adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, fi, stage, acc, br, tfl, dtf, gmask, need_v,
                                      cell_acc, s, 0.0f);
   constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
   if (cell_acc) cell_flush<LDS, FIX>(vd, br, acc, s);   // the brick changes with the slab
@@ -1156,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       for (int i = 0; i < N; ++i) {
         if (i % K == 0) ck[i / K] = T;
         Cell c;
-        locate(r, i, vd, c);
+        locate(r, (float)i, vd, c);
         float v[8];
         fetch_global<DT>(vd, c, v);
         const float d = trilerp(v, c.f);
@@ -1187,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
       tseg[0] = ck[sg];
       for (int i = i0; i < i1; ++i) {
         Cell c;
-        locate(r, i, vd, c);
+        locate(r, (float)i, vd, c);
         float v[8];
         fetch_global<DT>(vd, c, v);
         const float d = trilerp(v, c.f);
@@ -1196,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
         tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
       }
       for (int i = i1 - 1; i >= i0; --i)
-        adj_sample<MODEL, DT, false, 3, true>(vd, r, i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
+        adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
                                         true, false, s, tseg[i - i0]);
     }
     if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
