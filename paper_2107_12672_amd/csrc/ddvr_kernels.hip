@@ -307,16 +307,27 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Maximum over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (full-rate VALU, no LDS round trips): after the row_shr steps
+// lane 15 of each row holds the row maximum, row_bcast15/31 carry it into
+// lane 63, which is read back as a uniform value.  Lanes a DPP step does not
+// write keep INT_MIN, the identity.
+__device__ __forceinline__ int wave_max_i32(int x) {
+  constexpr int ID = -2147483647 - 1;
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x111, 0xf, 0xf, false));   // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x112, 0xf, 0xf, false));   // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x114, 0xf, 0xe, false));   // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x118, 0xf, 0xc, false));   // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x143, 0xc, 0xf, false));   // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
 template <int NT>
 __device__ __forceinline__ void wg_max_n(int* v, int n, int* scratch) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = 0; k < n; ++k) {
-    int x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
-    v[k] = x;
-  }
+  for (int k = 0; k < n; ++k) v[k] = wave_max_i32(v[k]);
   if (NW == 1) return;
   __syncthreads();
   if (lane == 0)
