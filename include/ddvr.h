@@ -135,7 +135,7 @@ typedef struct {
 /* Launch shape of the render kernels (process-wide default, captured by a
  * batch when it is created).
  *   waves      waves per workgroup: 1 (8x8-pixel tiles), 2 (16x8) or 4 (16x16)
- *   lds_cap    voxels per LDS brick (64..16384); the forward stages the grid
+ *   lds_cap    voxels per LDS brick (64..16384, default 7168); the forward stages the grid
  *              values of each slab's brick, the adjoint accumulates the density
  *              gradient of the brick before one global atomic per voxel
  *   slab_k     initial samples per ray in a slab (>= 4); the kernel halves it
@@ -144,8 +144,13 @@ typedef struct {
  *   cell_acc   1: keep a ray's density gradient for its current cell in
  *              registers and add it to the brick when the ray leaves the cell
  *              (Sec. 4.4, "on exit of the current cell"); 0: add every sample.
- *   lane_map   1: the lanes of a wave take every other pixel of the tile;
- *              0: a wave takes an 8x8 block of adjacent pixels.
+ *   lane_map   lane -> pixel map of the forward / adjoint passes: a wave
+ *              takes an 8x8 block of adjacent pixels ("compact") or an 8x8
+ *              lattice of every other pixel of the tile ("interleaved").
+ *              0 compact / compact, 1 interleaved / interleaved, 2 compact /
+ *              interleaved (the fused pass hands each ray's transmittance and
+ *              upstream gradient to the adjoint's lane through LDS), 3
+ *              interleaved / compact.
  *   schedule   batches only: 0 auto (2 when views differ in image size or grid,
  *              else 1), 1 one workgroup per tile with contiguous tile ranges
  *              per XCD, 2 persistent workgroups popping tiles from a queue

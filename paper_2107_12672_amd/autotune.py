@@ -81,8 +81,8 @@ def apply(key: str, path: Optional[str] = None) -> bool:
 
 def default_candidates() -> List[dict]:
     out = []
-    for waves, cap, k, lm in itertools.product((2, 4), (6144, 12288, 16384), (32, 64, 128),
-                                               (0, 1)):
+    for waves, cap, k, lm in itertools.product((2, 4), (5120, 6144, 7168, 8192, 12288),
+                                               (32, 64), (0, 1, 2)):
         out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
                     "cell_acc": 1, "lane_map": lm, "schedule": 0})
     return out

@@ -48,11 +48,11 @@ constexpr int kFallbackSlots = 65536;     // concurrent checkpoint slots
 // Launch shape of the render kernels (process-wide; see ddvr_set_tuning).
 struct Tuning {
   int waves = 4;        // waves per workgroup: 1 -> 8x8, 2 -> 16x8, 4 -> 16x16 pixel tiles
-  int lds_cap = 12288;  // voxels per LDS brick (clamped to the device's LDS per workgroup)
+  int lds_cap = 7168;   // voxels per LDS brick (clamped to the device's LDS per workgroup)
   int slab_k = 64;      // initial samples per slab
   int slab_kmax = 256;  // longest slab tried
   int cell_acc = 1;     // per-cell register accumulation of the density gradient
-  int lane_map = 1;     // interleaved lane -> pixel mapping
+  int lane_map = 2;     // lane -> pixel maps: compact forward, interleaved adjoint
   int schedule = 0;     // batches: 0 auto, 1 one workgroup per tile, 2 persistent queue
 };
 Tuning g_tuning;
@@ -504,8 +504,8 @@ int ddvr_set_tuning(const ddvr_tuning* t) {
     return fail(DDVR_ERR_VALUE, "lds_cap must be in [64, 16384] voxels");
   if (t->slab_k < 4 || t->slab_kmax < t->slab_k || t->slab_kmax > 4096)
     return fail(DDVR_ERR_VALUE, "need 4 <= slab_k <= slab_kmax <= 4096");
-  if ((t->cell_acc != 0 && t->cell_acc != 1) || (t->lane_map != 0 && t->lane_map != 1))
-    return fail(DDVR_ERR_VALUE, "cell_acc and lane_map are 0 or 1");
+  if (t->cell_acc != 0 && t->cell_acc != 1) return fail(DDVR_ERR_VALUE, "cell_acc is 0 or 1");
+  if (t->lane_map < 0 || t->lane_map > 3) return fail(DDVR_ERR_VALUE, "lane_map is 0..3");
   if (t->schedule < 0 || t->schedule > 2) return fail(DDVR_ERR_VALUE, "schedule is 0, 1 or 2");
   g_tuning.schedule = t->schedule;
   g_tuning.waves = t->waves;

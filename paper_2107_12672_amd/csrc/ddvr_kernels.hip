@@ -830,6 +830,22 @@ template <> struct TileShape<1> { static constexpr int BX = 1, BY = 1; };
 template <> struct TileShape<2> { static constexpr int BX = 2, BY = 1; };
 template <> struct TileShape<4> { static constexpr int BX = 2, BY = 2; };
 
+// Lane -> pixel inside a tile (local coordinates lx, ly): each wave an 8x8
+// block of adjacent pixels, or (interleaved) an 8x8 lattice of every other
+// pixel, so that the lanes of a wave are two pixels apart.  Both maps are
+// bijections of the tile.
+template <int WAVES>
+__device__ __forceinline__ void tile_pixel(bool interleaved, int wid, int lane, int& lx, int& ly) {
+  using TS = TileShape<WAVES>;
+  if (interleaved && WAVES > 1) {
+    lx = 2 * (lane & 7) + (wid % TS::BX);
+    ly = TS::BY == 2 ? 2 * (lane >> 3) + wid / 2 : (lane >> 3);
+  } else {
+    lx = (wid % TS::BX) * 8 + (lane & 7);
+    ly = (wid / TS::BX) * 8 + (lane >> 3);
+  }
+}
+
 // One tile of the render: forward, adjoint, or fused forward + L2 + adjoint.
 template <int MODEL, int DT, int WAVES, int PASS, bool XH>
 __device__ __forceinline__ void render_tile(const LaunchParams& p, const int item, float* smem) {
@@ -871,29 +887,28 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
 
   const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // lane -> pixel: each wave an 8x8 block of the tile, or (lane_map = 1) an
-  // 8x8 lattice of every other pixel, so that the lanes of a wave are two
-  // pixels apart and collide less on shared grid corners
-  int px, py;
-  if (p.lane_map && WAVES > 1) {
-    px = tx * TW + 2 * (lane & 7) + (wid % TileShape<WAVES>::BX);
-    py = ty * TH + (TileShape<WAVES>::BY == 2 ? 2 * (lane >> 3) + wid / 2 : (lane >> 3));
-  } else {
-    px = tx * TW + (wid % TileShape<WAVES>::BX) * 8 + (lane & 7);
-    py = ty * TH + (wid / TileShape<WAVES>::BX) * 8 + (lane >> 3);
-  }
-  const bool valid = px < vd.W && py < vd.H;
-  const int64_t pix = (int64_t)py * vd.W + px;
+  // lane -> pixel of each pass (lane_map: 0 compact, 1 interleaved, 2 compact
+  // forward + interleaved adjoint, 3 the reverse).  The forward gathers from
+  // the staged brick best with adjacent rays in a wave; the adjoint's LDS
+  // atomics collide less with rays two pixels apart.
+  const bool il_fwd = p.lane_map == 1 || p.lane_map == 3;
+  const bool il_adj = p.lane_map == 1 || p.lane_map == 2;
+  int lx, ly;
+  tile_pixel<WAVES>(PASS == PASS_ADJ ? il_adj : il_fwd, wid, lane, lx, ly);
+  int px = tx * TW + lx, py = ty * TH + ly;
+  bool valid = px < vd.W && py < vd.H;
+  int64_t pix = (int64_t)py * vd.W + px;
   RayG r;
   setup_ray(vd, px, py, valid, r);
-  const bool hit = r.N > 0;
+  bool hit = r.N > 0;
 
   // slab bookkeeping (shared by both passes): sample offsets relative to the
   // earliest entry point of the tile
   int off = 0, tile_end;
   const int kmax = cap > 0 ? max(p.slab_kmax, 4) : kMaxSamples + 1;
+  float tmin = 0.0f;
   if (cap > 0) {
-    const float tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
+    tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
     off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
   }
   {
@@ -959,6 +974,30 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     }
   }
   if (PASS == PASS_FWD) return;
+
+  // Fused pass with different lane maps: hand each ray's T_N and upstream
+  // gradient over to the lane that runs its adjoint, through the (now idle)
+  // staging region, and set that lane's ray up again.
+  if (PASS == PASS_FUSED && il_adj != il_fwd && cap >= (C + 1) * NT) {
+    __syncthreads();                       // the forward's last brick reads are done
+    const int lp = ly * TW + lx;
+    stage[lp] = TN;
+    for (int ch = 0; ch < C; ++ch) stage[(ch + 1) * NT + lp] = gimg[ch];
+    __syncthreads();
+    tile_pixel<WAVES>(il_adj, wid, lane, lx, ly);
+    const int lq = ly * TW + lx;
+    TN = stage[lq];
+    for (int ch = 0; ch < C; ++ch) gimg[ch] = stage[(ch + 1) * NT + lq];
+    px = tx * TW + lx;
+    py = ty * TH + ly;
+    valid = px < vd.W && py < vd.H;
+    pix = (int64_t)py * vd.W + px;
+    setup_ray(vd, px, py, valid, r);
+    hit = r.N > 0;
+    off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
+    // the staging region is next written after the adjoint's first brick
+    // reduction, whose barriers order it after these reads
+  }
 
   if (PASS == PASS_ADJ && valid) {
     TN = vd.trans[pix];

@@ -185,8 +185,8 @@ def camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, d_frame: Sequen
     return list(out)
 
 
-TUNING_DEFAULT = {"waves": 4, "lds_cap": 12288, "slab_k": 64, "slab_kmax": 256, "cell_acc": 1,
-                  "lane_map": 1, "schedule": 0}
+TUNING_DEFAULT = {"waves": 4, "lds_cap": 7168, "slab_k": 64, "slab_kmax": 256, "cell_acc": 1,
+                  "lane_map": 2, "schedule": 0}
 
 
 def set_tuning(**kw):

@@ -179,6 +179,7 @@ def test_tuning_roundtrip_and_validation():
                                   "cell_acc": 0, "lane_map": 0, "schedule": 2}
         for bad in ({"waves": 3}, {"lds_cap": 10}, {"lds_cap": 1 << 20}, {"slab_k": 2},
                     {"slab_k": 128, "slab_kmax": 64}, {"cell_acc": 2}, {"lane_map": -1},
+                    {"lane_map": 4},
                     {"schedule": 3}):
             with pytest.raises(d.DDVRError) as ei:
                 d.set_tuning(**bad)

@@ -284,12 +284,26 @@ def test_tiny_grid_and_two_knot_tf():
     assert_grad_close(got["dTF"], ref["dTF"], "tiny dTF")
 
 
-def test_fused_l2_equals_forward_then_adjoint():
-    import torch
+@pytest.mark.parametrize("lane_map", [0, 1, 2, 3])
+def test_fused_l2_equals_forward_then_adjoint(lane_map):
+    """The fused pass (forward, in-kernel L2 seed, adjoint) gives the forward's
+    images bitwise and the separate adjoint's gradients, for every pair of
+    lane maps (2 and 3 hand each ray over to another lane between the passes;
+    the ragged image leaves lanes without a pixel)."""
     from paper_2107_12672_amd import ddvr as d
+    old = d.get_tuning()
+    try:
+        d.set_tuning(lane_map=lane_map)
+        _fused_vs_separate(d)
+    finally:
+        d.set_tuning(**old)
+
+
+def _fused_vs_separate(d):
+    import torch
     from harness import device_volume, gpu_camera
-    for p in (ea_problem(W=48, H=48), c1_problem()[0]):
-        _say(f"fused model={p.model}")
+    for p in (ea_problem(W=56, H=44), c1_problem()[0]):
+        _say(f"fused model={p.model} lane_map={d.get_tuning()['lane_map']}")
         vol = device_volume(p)
         tf = torch.from_numpy(p.tf).cuda() if p.tf is not None else None
         cam = gpu_camera(p)
@@ -333,6 +347,8 @@ def test_fused_l2_equals_forward_then_adjoint():
     {"waves": 2, "lds_cap": 2048, "slab_k": 64, "cell_acc": 1, "lane_map": 1},
     {"waves": 4, "lds_cap": 512, "slab_k": 16, "cell_acc": 1, "lane_map": 0},
     {"waves": 4, "lds_cap": 8192, "slab_k": 128, "cell_acc": 0, "lane_map": 1},
+    {"waves": 4, "lds_cap": 7168, "slab_k": 64, "cell_acc": 1, "lane_map": 2},
+    {"waves": 2, "lds_cap": 3072, "slab_k": 32, "cell_acc": 1, "lane_map": 3},
 ])
 def test_results_do_not_depend_on_the_launch_shape(tuning):
     """Forward bitwise identical across tile shapes, brick sizes and slab
