@@ -97,6 +97,140 @@ def cpu_baseline(work, n_views_max, budget_s=12.0):
                       f"{samples} samples in {dt:.1f} s"}
 
 
+def _timed(fn, steps, warmup, stream, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def secondary(args):
+    """The other workloads, one JSON line each (not the headline figure):
+      c2  emission-absorption 128^3 f32, R=16, one 256x256 view, fused L2 with
+          gradients for density, TF, camera and step;
+      c4  uneven batch of 16 grids (edges 64-384, f16/f32, R 8-64, images
+          128-1024 px) in one persistent launch, forward + adjoint for camera
+          and step gradients (seeded upstream gradients);
+      c5  emission-absorption 512^3 f16 sparse noise, R=32, 32 views at
+          1024x1024, fused L2 with density, TF and step gradients: T-form
+          inversion (AUTO) and segment checkpointing (CHECKPOINT)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2107_12672_amd import ddvr as d
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def cams_of(views):
+        return [d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                     math.radians(v.fovy), v.width, v.height) for v in views]
+
+    def stored(vol_np, storage):
+        v32 = torch.from_numpy(np.ascontiguousarray(vol_np)).to(dev)
+        if storage == "f32":
+            return v32
+        out = torch.empty_like(v32, dtype=torch.float16 if storage == "f16" else torch.bfloat16)
+        d.cast_volume(v32, out)
+        return out
+
+    out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "unit": "ray-samples/s"}
+    if args.workload in ("c2", "c5"):
+        w = synth.make_c2() if args.workload == "c2" else synth.make_c5()
+        vol = stored(w.volume, w.storage)
+        tf = torch.from_numpy(w.tf).to(dev)
+        cams = cams_of(w.views)
+        nv = len(cams)
+        W = H = w.views[0].width
+        # targets: the same grid under a TF with seeded +-20% perturbations
+        tf_t = torch.from_numpy(w.tf * synth.rng_for(9, 1).uniform(0.8, 1.2, w.tf.shape)
+                                .astype(np.float32)).to(dev)
+        targets = torch.empty((nv, H, W, 4), device=dev)
+        tb = d.Batch([vol], [tf_t], [d.make_view(0, cams[i], w.step_world, targets[i],
+                                                 tf_index=0) for i in range(nv)],
+                     d.EMISSION_ABSORPTION)
+        tb.run(d.PASS_FORWARD)
+        torch.cuda.synchronize()
+        tb.close()
+        images = torch.empty_like(targets)
+        trans = torch.empty((nv, H, W), device=dev)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        dTF = torch.zeros_like(tf)
+        dstep = torch.zeros(nv, device=dev)
+        dcam = torch.zeros((nv, 12), device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        scale = 1.0 / images.numel()
+        res = {}
+        for mode, flags in (("auto", 0), ("checkpoint", 3)):
+            if args.workload == "c2" and flags:
+                continue
+            views = [d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
+                                 target=targets[i], d_step=dstep[i:i + 1], tf_index=0,
+                                 d_camera=dcam[i] if args.workload == "c2" else None)
+                     for i in range(nv)]
+            b = d.Batch([vol], [tf], views, d.EMISSION_ABSORPTION, flags=flags,
+                        d_volumes=[dV], d_tfs=[dTF])
+            ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+            S = b.sample_count()
+            ms = _timed(lambda: b.run(d.PASS_FUSED, scale, loss, workspace=ws, graph=True),
+                        args.steps, args.warmup, stream, torch)
+            res[mode] = {"ms_per_step": ms, "value": S / (ms * 1e-3), "samples_per_step": S}
+            log(f"{args.workload} {mode}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+            b.close()
+        out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
+                    "value": res["auto"]["value"], "ms_per_step": res["auto"]["ms_per_step"],
+                    "config": {"workload": w.name + (", gradients density+TF+camera+step"
+                                                     if args.workload == "c2" else
+                                                     ", gradients density+TF+step"),
+                               "samples_per_step": res["auto"]["samples_per_step"],
+                               "tuning": d.get_tuning()}})
+        if "checkpoint" in res:
+            out["checkpoint"] = res["checkpoint"]
+    else:   # c4
+        ws_ = synth.make_c4()
+        vols = [stored(w.volume, w.storage) for w in ws_]
+        tfs = [torch.from_numpy(w.tf).to(dev) for w in ws_]
+        rng = synth.rng_for(9, 4)
+        imgs, trs, gs, views = [], [], [], []
+        dcam = torch.zeros((len(ws_), 12), device=dev)
+        dstep = torch.zeros(len(ws_), device=dev)
+        for i, w in enumerate(ws_):
+            v = w.views[0]
+            imgs.append(torch.empty((v.height, v.width, 4), device=dev))
+            trs.append(torch.empty((v.height, v.width), device=dev))
+            gs.append(torch.from_numpy(rng.normal(size=(v.height, v.width, 4)).astype(np.float32)
+                                       / (v.width * v.height)).to(dev))
+            cam = cams_of([v])[0]
+            views.append(d.make_view(i, cam, w.step_world, imgs[i], transmittance=trs[i],
+                                     d_image=gs[i], d_camera=dcam[i], d_step=dstep[i:i + 1],
+                                     tf_index=i))
+        b = d.Batch(vols, tfs, views, d.EMISSION_ABSORPTION)
+        ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+        S = b.sample_count()
+
+        def step():
+            b.run(d.PASS_FORWARD, graph=True)
+            b.run(d.PASS_ADJOINT, workspace=ws, graph=True)
+
+        ms = _timed(step, args.steps, args.warmup, stream, torch)
+        log(f"c4: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s, {S} samples")
+        out.update({"metric": "fwd+adjoint ray-samples/s (forward, then adjoint)",
+                    "value": S / (ms * 1e-3), "ms_per_step": ms,
+                    "config": {"workload": "uneven batch: 16 grids (edges 64-384, f16/f32, "
+                                           "EA, R 8-64), one view each at 128-1024 px, "
+                                           "camera + step gradients, persistent launch",
+                               "samples_per_step": S, "tuning": d.get_tuning()}})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +240,9 @@ def main():
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
     ap.add_argument("--step-vox", type=float, default=0.2)
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5"),
+                    help="c3 (default) is the headline tomography step; the others print "
+                         "their own line")
     ap.add_argument("--burn-in", type=int, default=4,
                     help="untimed reconstruction iterations from the zero grid before warmup")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,6 +268,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
+    if args.workload != "c3":
+        secondary(args)
+        return
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4

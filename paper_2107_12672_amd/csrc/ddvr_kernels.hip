@@ -390,6 +390,23 @@ __device__ __forceinline__ void slab_range(int lo, int hi, int off, int N, int& 
   b = min(max(hi - off, 0), N);
 }
 
+// Sum over the workgroup, returned to every thread.
+template <int NT>
+__device__ __forceinline__ float wg_sum_all(float x, float* scratch) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  if (NW == 1) return x;
+  __syncthreads();
+  if (lane == 0) scratch[wid] = x;
+  __syncthreads();
+  float r = scratch[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r += scratch[w];
+  return r;
+}
+
 // Bounding box of the cells of every sample in the slab [lo, hi).
 // Returns false if no ray has a sample in it.
 template <int NT>
@@ -637,8 +654,9 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
                                            const float4* tfl, float* dtf, int gmask,
                                            bool need_v, bool cell_acc, AdjState& s,
                                            float Ti_given) {
-  // the absorption-only closed form accumulates the LDS brick in fixed point
-  constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
+  // the absorption-only closed form and the emission-absorption inversions
+  // accumulate the LDS brick in fixed point
+  constexpr bool FIX = LDS && (MODEL == DDVR_ABSORPTION ? MODE == 0 : (MODE == 1 || MODE == 2));
   Cell c;
   locate(r, fi, vd, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
@@ -715,7 +733,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
     // flushed on exit of the current cell); the fixed-point route accumulates
     // in fixed-point units.  Weights w_c * d_hat with d_hat folded into the x
     // factors.
-    const float dv = FIX ? s.dhq : d_hat;
+    const float dv = FIX ? (MODE == 0 ? s.dhq : d_hat * s.qs) : d_hat;
     const float gx = 1.0f - c.f[0], gy = 1.0f - c.f[1], gz = 1.0f - c.f[2];
     const float d0 = gx * dv, d1 = c.f[0] * dv;
     const float a00 = gy * gz, a10 = c.f[1] * gz, a01 = gy * c.f[2], a11 = c.f[1] * c.f[2];
@@ -744,7 +762,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
     float w[8];
     trilerp_weights(c.f, w);
     if (LDS) {
-      const float q = FIX ? s.dhq : d_hat;
+      const float q = FIX ? (MODE == 0 ? s.dhq : d_hat * s.qs) : d_hat;
       float g[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) g[k] = w[k] * q;
@@ -784,7 +802,7 @@ __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int
   for (float fi = (float)(b - 1); fi >= fa; fi -= 1.0f)
     adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, fi, stage, acc, br, tfl, dtf, gmask, need_v,
                                      cell_acc, s, 0.0f);
-  constexpr bool FIX = LDS && MODEL == DDVR_ABSORPTION && MODE == 0;
+  constexpr bool FIX = LDS && (MODEL == DDVR_ABSORPTION ? MODE == 0 : (MODE == 1 || MODE == 2));
   if (cell_acc) cell_flush<LDS, FIX>(vd, br, acc, s);   // the brick changes with the slab
 }
 
@@ -1050,31 +1068,75 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
 
-  // Fixed-point scale of the absorption-only closed form.  Every sample adds
-  // d_hat = dt*T_N*ahat (constant along the ray) times trilinear weights <= 1,
-  // and a straight ray has at most lmax samples in the 2x2x2 cells around a
-  // voxel (chord <= 2*sqrt(3) voxels), so no brick entry of the tile exceeds
-  // B = NT * max|d_hat| * lmax in magnitude; qs = 2^(29 - ceil(log2 B)) keeps
-  // every partial sum below 2^29.  A tile whose bound is not finite (NaN or
-  // Inf upstream gradients) takes the float32 T-form route without LDS
-  // bricks, which propagates them.
+  // Fixed-point scale of the LDS density-gradient brick.  A straight ray has
+  // at most lmax samples in the 2x2x2 cells around a voxel (chord <=
+  // 2*sqrt(3) voxels), and each adds w*d_hat with trilinear weight |w| <= 1.
+  // B bounds every brick entry by a sum over the tile's rays of per-ray
+  // bounds on their contributions to one voxel:
+  //  * absorption-only closed form: d_hat = dt*T_N*ahat exactly, so a ray
+  //    adds at most lmax*|d_hat|; B = NT * lmax * max|d_hat|;
+  //  * emission-absorption (T- or alpha-form inversion): d_hat = (R-1) *
+  //    (slope_rgb . alpha_i T^(i) Chat + slope_tau * tau_hat).  Along a ray
+  //    sum_i alpha_i T^(i) = 1 - T_N <= 1, so the colour part adds at most
+  //    (R-1) S_rgb |Chat|_1 in total; with P_i = T^(i) ahat^(i) the blend
+  //    adjoint gives P_(i+1) = T_N ahat_N - sum_(j>i) T^(j) alpha_j (rgb_j .
+  //    Chat), so e_i times the alpha adjoint is at most A = T_N |ahat_N| +
+  //    2 rgbmax |Chat|_1 and the opacity part adds at most lmax (R-1) S_tau
+  //    dt A (S: largest TF segment slopes, rgbmax: largest |colour|).
+  //    B = the sum of these per-ray bounds over the tile.
+  // qs = 2^(28 - ceil(log2 B)) keeps every partial sum below 2^28 (margin for
+  // float32 rounding of the recovered T^(i)).  A tile whose bound is not
+  // finite (NaN or Inf upstream gradients or TF) takes the float32 route
+  // without LDS bricks, which propagates them.
   const bool closed_form = !EA && mode == DDVR_ADJ_AUTO;
   s.qs = 1.0f;
   float inv_qs = 1.0f;
   bool fix_ok = true;
   {
-    const float m = (closed_form && want_dv && Nadj > 0) ? fabsf(vd.step * s.P) : 0.0f;
-    int v2[2] = {Nadj > 0 ? off + Nadj : 0, __float_as_int(m)};
-    wg_max_n<NT>(v2, 2, iscratch);
-    tile_end = v2[0];
+    const bool lane_dv = want_dv && Nadj > 0;
     const float lmax = floorf(3.4641017f / (vd.step * vd.inv_h)) + 2.0f;
-    const float B = __int_as_float(v2[1]) * (float)NT * lmax;
+    // per-lane maxima, reduced in one pass: tile end, then the bound's factors
+    constexpr int NV = EA ? 4 : 2;
+    int v[NV];
+    v[0] = Nadj > 0 ? off + Nadj : 0;
+    if (!EA) {
+      v[1] = __float_as_int((closed_form && lane_dv) ? fabsf(vd.step * s.P) : 0.0f);
+    } else {
+      float srgb = 0.0f, stau = 0.0f, rgbmax = 0.0f;
+      if (want_dv) {
+        for (int k = threadIdx.x; k < vd.R - 1; k += NT) {
+          const float4 a = tfl[k], b = tfl[k + 1];
+          srgb = fmaxf(srgb, fmaxf(fabsf(b.x - a.x), fmaxf(fabsf(b.y - a.y), fabsf(b.z - a.z))));
+          stau = fmaxf(stau, fabsf(b.w - a.w));
+          rgbmax = fmaxf(rgbmax, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fabsf(a.z)));
+          rgbmax = fmaxf(rgbmax, fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fabsf(b.z)));
+        }
+      }
+      v[1] = __float_as_int(srgb);
+      v[2] = __float_as_int(stau);
+      v[3] = __float_as_int(rgbmax);
+    }
+    wg_max_n<NT>(v, NV, iscratch);
+    tile_end = v[0];
+    float B;
+    if (!EA) {
+      B = __int_as_float(v[1]) * (float)NT * lmax;
+    } else {
+      float b = 0.0f;
+      if (lane_dv) {
+        const float c1 = fabsf(s.Chat[0]) + fabsf(s.Chat[1]) + fabsf(s.Chat[2]);
+        const float A = fabsf(TN * s.ahat) + 2.0f * __int_as_float(v[3]) * c1;
+        b = (float)(vd.R - 1) *
+            (__int_as_float(v[1]) * c1 + lmax * __int_as_float(v[2]) * vd.step * A);
+      }
+      B = wg_sum_all<NT>(b, fscratch) * 1.0001f;   // margin for the float32 sum
+    }
     if (!(B < INFINITY)) {
       fix_ok = false;
     } else if (B > 0.0f) {
       int ex;
       (void)frexpf(B, &ex);          // B < 2^ex
-      const int e = 29 - ex;
+      const int e = 28 - ex;
       if (e > 120) {
         fix_ok = false;              // subnormal-scale gradients: float32 route
       } else {
@@ -1084,6 +1146,9 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     }
   }
   const bool use_fix = closed_form && fix_ok;
+  // the brick holds fixed point on the closed form and on every
+  // emission-absorption route (the others add float32)
+  const bool lds_fix = (closed_form || EA) && fix_ok;
   s.dh = vd.step * s.P;
   s.dhq = s.dh * s.qs;
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || !use_fix;
@@ -1112,7 +1177,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
                                       p.cell_acc, s);
       __syncthreads();
       if (want_dv) {
-        if (use_fix) flush_brick<NT, true>(vd, br, acc, inv_qs);
+        if (lds_fix) flush_brick<NT, true>(vd, br, acc, inv_qs);
         else flush_brick<NT, false>(vd, br, acc, 1.0f);
       }
     } else {

@@ -200,7 +200,8 @@ def test_c5_full_size_sampled_parity_inversion_and_checkpoint():
         refT += a["dTF"]
         refS[vi] = a["dstep"]
     for mode, (gV, gT, gS) in results.items():
-        assert_dv_close(gV, refV, f"C5 dV mode {mode}")
+        e = assert_dv_close(gV, refV, f"C5 dV mode {mode}")
+        print(f"[result] C5 dV error mode {mode}: {e:.3g}", flush=True)
         assert_grad_close(gT, refT, f"C5 dTF mode {mode}")
         assert_grad_close([gS[vi] for vi in sel], [refS[vi] for vi in sel],
                           f"C5 dstep mode {mode}", rtol=2e-3)

@@ -115,6 +115,27 @@ def test_absorption_closed_form_density_gradient_is_accurate_at_any_scale(scale)
     assert_dv_close(got, ref, "closed-form dV", 2e-5)
 
 
+@pytest.mark.parametrize("flags,scale", [(0, 1.0), (0, 1e20), (1, 1.0), (2, 1.0)])
+def test_emission_absorption_density_gradient_fixed_point_accuracy(flags, scale):
+    """Emission-absorption density gradients add to the LDS brick in 32-bit
+    fixed point with a scale from a bound on every sample's d_hat (blend
+    adjoint invariant and TF slopes); the bound is loose, so this checks that
+    the result stays inside half the float32 tolerance (5e-4 norm-wise) on the
+    T-form (AUTO, INVERT_T) and alpha-form routes."""
+    p = ea_problem()
+    _say(f"EA fixed-point dV flags={flags} scale={scale:g}")
+    ora = oracle_forward(p)
+    ties = tie_mask(ora["ratio"])
+    rng = np.random.default_rng(17)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[ties] = 0.0
+    ref = oracle_adjoint(p, g)["dV"] * scale
+    got = gpu_adjoint(p, g * scale, flags=flags, want=("V",))["dV"]
+    assert np.isfinite(got).all()
+    e = assert_dv_close(got, ref, "EA dV", 5e-4)
+    print(f"[result] EA fixed-point dV error {e:.3g}", flush=True)
+
+
 def test_non_finite_upstream_gradient_propagates():
     """A NaN in d_image reaches the density gradient (the tile holding it takes
     the float route); every other voxel matches the oracle without that ray."""
