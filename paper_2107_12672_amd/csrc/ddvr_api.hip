@@ -43,7 +43,7 @@ bool finite3(const float* v) {
   return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
-constexpr int kFallbackSlots = 65536;     // concurrent checkpoint slots
+constexpr int kFallbackSlots = 1 << 19;   // concurrent checkpoint slots (8 workgroups per CU)
 
 // Launch shape of the render kernels (process-wide; see ddvr_set_tuning).
 struct Tuning {

@@ -1320,10 +1320,13 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
         if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
         tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
       }
+      // density gradient kept per cell in registers, one global atomic per
+      // corner when the ray leaves the cell
       for (int i = i1 - 1; i >= i0; --i)
-        adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, vd.dTF, gmask,
-                                        true, false, s, tseg[i - i0]);
+        adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, vd.dTF,
+                                              gmask, true, true, s, tseg[i - i0]);
     }
+    cell_flush<false, false>(vd, br, nullptr, s);
     if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
     if (gmask & (GRAD_CAM | GRAD_STEP)) {
       float cg[13];
