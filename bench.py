@@ -33,6 +33,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue roof: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-packed
+# operation per lane per clock (the 157.3 TFLOP/s fp32 figure counts packed
+# FMAs: 2 lanes x 2 flops)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
 ALG_BYTES_BF16 = 64      # per sample pair: 8 gathers x 2 B (fwd) + 8 x 2 B (adj) + 8 x 4 B scatter
 ALG_BYTES_F32 = 96
 KERNEL_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_kernels.hip",
@@ -63,6 +68,49 @@ def measured_traffic():
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def valu_counts():
+    """Per-sample VALU instruction counts of the fused kernel's loops (from
+    ``python -m paper_2107_12672_amd.isa_count --write``), if they were taken
+    on the current kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return t if t.get("kernel_source_sha") == kernel_source_hash() else None
+
+
+def cell_visits(work, cams, W, H):
+    """Grid cells entered by all rays of all views (each entry ends in one
+    cell-exit flush of the adjoint), from the rays' box entry and exit points:
+    a ray's cell index is monotone per axis, so it visits 1 + sum_a |k_a(exit)
+    - k_a(entry)| cells (up to simultaneous crossings)."""
+    import numpy as np
+    n = np.array(work.volume.shape[::-1], np.float64)          # nx, ny, nz
+    h = 2.0 / (n.max() - 1)
+    bmin, bmax = -0.5 * (n - 1) * h, 0.5 * (n - 1) * h
+    u = (2.0 * (np.arange(W) + 0.5) / W - 1.0)[None, :]
+    v = (1.0 - 2.0 * (np.arange(H) + 0.5) / H)[:, None]
+    total = 0
+    for c in cams:
+        cam = np.array(c.frame(), np.float64)                 # the library's camera frame
+        e, f, r, up = cam[0:3], cam[3:6], cam[6:9], cam[9:12]
+        w = f[None, None, :] + u[..., None] * r + v[..., None] * up
+        om = w / np.linalg.norm(w, axis=-1, keepdims=True)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ta = (bmin - e) / om
+            tb = (bmax - e) / om
+        t0 = np.maximum(np.nanmax(np.minimum(ta, tb), axis=-1), 0.0)
+        t1 = np.nanmin(np.maximum(ta, tb), axis=-1)
+        hit = t1 > t0
+        q0 = (e + t0[..., None] * om - bmin) / h
+        q1 = (e + t1[..., None] * om - bmin) / h
+        k0 = np.clip(np.floor(q0), 0, n - 2)
+        k1 = np.clip(np.floor(q1), 0, n - 2)
+        total += int((1 + np.abs(k1 - k0).sum(-1))[hit].sum())
+    return total
 
 
 def cpu_baseline(work, n_views_max, budget_s=12.0):
@@ -359,12 +407,37 @@ def main():
     seeded = float((images != targets).float().mean())
     log(f"pixels with a non-zero residual: {seeded:.4f}, loss {float(loss):.4g}")
 
-    achieved = S * ALG_BYTES_BF16 / (k_ms * 1e-3) / 1e9
+    # The fused kernel is bound by VALU issue (rocprofv3: VALU busy on ~98% of
+    # SIMD cycles, DRAM traffic ~5% of peak), so its roofline is the ALU one:
+    # per-sample VALU operations of the forward and adjoint loops (counted in
+    # the kernel's assembly) plus one cell-exit flush per grid cell a ray
+    # enters, per launch, over the kernel's event-timed duration.
+    achieved_gbs = S * ALG_BYTES_BF16 / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
-                "kernel_ms": round(k_ms, 4), "alg_bytes_per_launch": S * ALG_BYTES_BF16}
+    vc = valu_counts()
+    cells = cell_visits(work, cams, W, H)
+    if vc:
+        ops = S * (vc["forward_valu_per_sample"] + vc["adjoint_valu_per_sample"]) + \
+            cells * vc["adjoint_cell_exit_flush_valu"]
+        a_tops = ops / (k_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(a_tops, 3), "peak": VALU_PEAK_TOPS,
+                    "unit": "TOP/s", "frac": round(a_tops / VALU_PEAK_TOPS, 4),
+                    "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
+                    "kernel_ms": round(k_ms, 4), "ops_per_launch": ops,
+                    "ops": "VALU lane-operations: per sample forward %d + adjoint %d, "
+                           "%d per cell exit (%d cell entries)" % (
+                               vc["forward_valu_per_sample"], vc["adjoint_valu_per_sample"],
+                               vc["adjoint_cell_exit_flush_valu"], cells)}
+    else:
+        roofline = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": None, "traffic": traffic,
+                    "note": "VALU counts missing or taken on another kernel source: run "
+                            "python -m paper_2107_12672_amd.isa_count --write"}
+    roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "alg_bytes_per_launch": S * ALG_BYTES_BF16,
+                    "note": "algorithmic bytes (16 s_V + 32 per sample pair): LDS bricks "
+                            "serve the gathers and scatters, so this exceeds the HBM roof"}
 
     result = {
         "metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
@@ -382,6 +455,7 @@ def main():
                    "pixels_with_nonzero_residual": round(seeded, 4),
                    "tuning": d.get_tuning(), "tuning_source": "autotuned" if tuned else "default"},
         "roofline": roofline,
+        "roofline_hbm_algorithmic": roofline_hbm,
     }
 
     if not args.no_plain:

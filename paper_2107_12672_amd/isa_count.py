@@ -1,0 +1,140 @@
+"""Per-sample VALU instruction counts of the render kernels' inner loops, read
+from the gfx950 assembly of the current source (the ALU-roofline figure of
+the benchmark).
+
+    python -m paper_2107_12672_amd.isa_count [--write]
+
+Compiles ``csrc/ddvr_kernels.hip`` with the library's flags to device
+assembly and counts, for the absorption-only bf16 4-wave kernels:
+  * forward: every VALU instruction of the innermost loop that gathers the
+    8 corners from the LDS brick (four ds_read2_b32) -- one sample;
+  * adjoint (closed form, fixed-point brick): every VALU instruction of the
+    innermost loop that adds to the LDS brick (ds_add_u32), except the basic
+    blocks that do the adding (the cell-exit flush, taken only when a ray
+    leaves its cell) -- one sample, plus the flush block counted separately.
+``--write`` stores the counts with the source hash in
+``profiles/valu_per_sample_c3.json``, which the benchmark reads.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import re
+import subprocess
+import sys
+import tempfile
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+OUT = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
+KERNEL_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_kernels.hip",
+                  "paper_2107_12672_amd/csrc/ddvr_internal.h"]
+FWD = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi0ELb0EEEvNS_12LaunchParamsE"
+FUSED = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi2ELb0EEEvNS_12LaunchParamsE"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def assembly() -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in _build.HIPCC_FLAGS if f != "-fPIC"]
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "k.s")
+        subprocess.check_call([hipcc] + flags + ["--cuda-device-only", "-S", "-o", out,
+                                                 os.path.join(_build.CSRC, "ddvr_kernels.hip")],
+                              stderr=subprocess.DEVNULL)
+        with open(out) as f:
+            return f.read()
+
+
+def _kernel(asm: str, sym: str):
+    lines = asm.split("\n")
+    start = next(i for i, l in enumerate(lines) if l.startswith(sym + ":"))
+    end = next(i for i in range(start, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    return lines[start:end]
+
+
+def _loops(lines):
+    """Innermost loops: {header: [(block header line, [mnemonics]), ...]},
+    from the compiler's loop annotations on block labels ("in Loop:
+    Header=BBx" on member blocks, "This Inner Loop Header" on the header)."""
+    loops, cur, members = {}, None, None
+    for i, l in enumerate(lines):
+        is_label = re.match(r"^(\.LBB\S+):", l) or l.startswith("; %bb.")
+        if is_label:
+            cur = None
+            m = re.match(r"^\.L(BB\S+):", l)
+            nxt = lines[i + 1] if i + 1 < len(lines) else ""
+            if m and "Inner Loop Header" in nxt:
+                cur = m.group(1)
+            else:
+                h = re.search(r"in Loop: Header=(BB\S+)", l)
+                if h:
+                    cur = h.group(1)
+            if cur is not None:
+                members = []
+                loops.setdefault(cur, []).append((l, members))
+            continue
+        t = l.strip()
+        if cur is not None and l.startswith("\t") and t and not t.startswith((".", ";")):
+            members.append(t.split()[0])
+    return loops
+
+
+def _inner(lines):
+    """Innermost loops only: headers whose own label carries the inner-loop mark."""
+    marked = set()
+    for i, l in enumerate(lines):
+        m = re.match(r"^\.L(BB\S+):", l)
+        if m and i + 1 < len(lines) and "Inner Loop Header" in lines[i + 1]:
+            marked.add(m.group(1))
+    return {h: b for h, b in _loops(lines).items() if h in marked}
+
+
+def count(asm: str) -> dict:
+    fwd = None
+    for blocks in _inner(_kernel(asm, FWD)).values():
+        ins = [x for _, blk in blocks for x in blk]
+        if ins.count("ds_read2_b32") == 4:
+            fwd = sum(1 for x in ins if x.startswith("v_"))
+            break
+    adj = flush = None
+    for blocks in _inner(_kernel(asm, FUSED)).values():
+        adders = [blk for _, blk in blocks if "ds_add_u32" in blk]
+        if not adders:
+            continue
+        common = [x for _, blk in blocks if "ds_add_u32" not in blk for x in blk]
+        adj = sum(1 for x in common if x.startswith("v_"))
+        # the cell-exit flush is the smaller adding block (the per-sample
+        # variant, not taken with per-cell accumulation, computes weights too)
+        flush = min(sum(1 for x in blk if x.startswith("v_")) for blk in adders)
+        break
+    if fwd is None or adj is None:
+        raise RuntimeError("inner loops not found in the assembly")
+    return {"forward_valu_per_sample": fwd, "adjoint_valu_per_sample": adj,
+            "adjoint_cell_exit_flush_valu": flush}
+
+
+def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    res = count(assembly())
+    res["kernel_source_sha"] = source_hash()
+    res["kernels"] = {"forward": FWD, "fused": FUSED}
+    print(json.dumps(res, indent=1))
+    if "--write" in argv:
+        os.makedirs(os.path.dirname(OUT), exist_ok=True)
+        with open(OUT, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
