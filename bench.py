@@ -33,10 +33,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue roof: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-packed
-# operation per lane per clock (the 157.3 TFLOP/s fp32 figure counts packed
-# FMAs: 2 lanes x 2 flops)
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU roof in lane-operations: MI355X's published fp32 vector rate, 157.3
+# TFLOP/s = 256 CUs x 128 FMA lanes x 2 flops x 2.4 GHz, i.e. 78.6 T
+# lane-operations/s with one VALU operation in each FMA slot
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
 ALG_BYTES_BF16 = 64      # per sample pair: 8 gathers x 2 B (fwd) + 8 x 2 B (adj) + 8 x 4 B scatter
 ALG_BYTES_F32 = 96
