@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define DDVR_ABI_VERSION 1
+#define DDVR_ABI_VERSION 2
 
 typedef enum {
   DDVR_OK = 0,
@@ -236,6 +236,47 @@ int ddvr_render_fused_l2(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
                          float* image, float* transmittance, const ddvr_grads* grads,
                          int32_t flags, void* workspace, size_t workspace_bytes,
                          int32_t* n_fallback_rays, double* loss_out, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Forward-mode derivatives (Sec. 4.2, forward differentiation with forward
+ * variables; Sec. 5.1 compares "forward-immediate" and "forward-delayed").
+ * ------------------------------------------------------------------------ */
+#define DDVR_MAX_DIRECTIONS 4
+/* A direction in (camera frame, step) space: d_frame in the layout of
+ * ddvr_grads.d_camera (eye, fwd, right, up), d_step per world unit. */
+typedef struct {
+  float d_frame[12];
+  float d_step;
+} ddvr_direction;
+
+/* Forward pass of one view carrying, for every sample, the derivatives of
+ * its state along ndir (1..DDVR_MAX_DIRECTIONS) directions -- the paper's
+ * forward variables with p = ndir parameters (Sec. 4.2).  Cost grows with
+ * ndir; it suits the few camera / step parameters of viewpoint optimisation.
+ * The sample count N is piecewise constant in the camera and the step and is
+ * not differentiated (as in the adjoint).
+ *   dirs        (host) [ndir] directions.
+ *   image       layout of render_forward's image, written; may be NULL.
+ *   image_dot   [ndir][H][W][C] float32, d image / d direction_k, written
+ *               ("forward-immediate": the caller contracts later); may be NULL.
+ *   d_image, d_dir  "forward-delayed": d_dir[k] (device, ndir floats) +=
+ *               sum over pixels and channels of d_image * image_dot_k, reduced
+ *               in the same pass; both NULL, or both given.
+ *   flags       0 or DDVR_LAUNCH_PLAIN.
+ * At least one of image, image_dot, d_dir must be given.  The tangent
+ * launch always uses 16x16-pixel tiles (4 waves); the brick capacity and slab
+ * lengths follow the tuning. */
+int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, const ddvr_direction* dirs,
+                        int32_t ndir, float* image, float* image_dot, const float* d_image,
+                        float* d_dir, int32_t flags, void* hip_stream);
+
+/* Directions of the sphere camera's parameters: d_frame[k*12 + j] (host,
+ * [4][12]) = d frame_j / d (yaw, pitch, dist, fovy)_k, angles in radians --
+ * the tangent inputs that make render_tangent differentiate w.r.t. the
+ * viewpoint (the transpose of ddvr_camera_grad_to_sphere). */
+int ddvr_camera_sphere_tangents(float yaw, float pitch, float dist, float fovy, int32_t width,
+                                int32_t height, float* d_frame);
 
 /* ------------------------------------------------------------------------
  * Batches: many views of one or several grids in ONE launch.

@@ -496,6 +496,66 @@ int ddvr_camera_grad_to_sphere(float yaw, float pitch, float dist, float fovy, i
   return DDVR_OK;
 }
 
+int ddvr_camera_sphere_tangents(float yaw, float pitch, float dist, float fovy, int32_t width,
+                                int32_t height, float* d_frame) {
+  if (!d_frame) return fail(DDVR_ERR_NULL, "output pointer is NULL");
+  int rc = validate_sphere(yaw, pitch, dist, fovy, width, height);
+  if (rc) return rc;
+  D4 f[12];
+  sphere_frame(yaw, pitch, dist, fovy, width, height, f);
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 12; ++j) d_frame[k * 12 + j] = (float)f[j].d[k];
+  return DDVR_OK;
+}
+
+int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
+                        float step_world, int32_t model, const ddvr_direction* dirs, int32_t ndir,
+                        float* image, float* image_dot, const float* d_image, float* d_dir,
+                        int32_t flags, void* hip_stream) {
+  int rc;
+  if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
+      (rc = validate_camera(cam)) || (rc = validate_step(vol, step_world)))
+    return rc;
+  if (flags & ~DDVR_LAUNCH_PLAIN) return fail(DDVR_ERR_VALUE, "tangent flags: only DDVR_LAUNCH_PLAIN");
+  if (!dirs) return fail(DDVR_ERR_NULL, "dirs is NULL");
+  if (ndir < 1 || ndir > DDVR_MAX_DIRECTIONS)
+    return fail(DDVR_ERR_VALUE, "ndir must be 1..%d", DDVR_MAX_DIRECTIONS);
+  for (int k = 0; k < ndir; ++k) {
+    for (int j = 0; j < 12; ++j)
+      if (!std::isfinite(dirs[k].d_frame[j])) return fail(DDVR_ERR_VALUE, "direction %d is not finite", k);
+    if (!std::isfinite(dirs[k].d_step)) return fail(DDVR_ERR_VALUE, "direction %d is not finite", k);
+  }
+  if (!image && !image_dot && !d_dir)
+    return fail(DDVR_ERR_NULL, "nothing to write: image, image_dot and d_dir are NULL");
+  if (d_dir && !d_image) return fail(DDVR_ERR_NULL, "d_dir needs d_image");
+  if ((rc = check_pending())) return rc;
+
+  const int cap = (flags & DDVR_LAUNCH_PLAIN) ? 0 : g_tuning.lds_cap;
+  TangentParams p;
+  std::memset(&p, 0, sizeof(p));
+  // tangent kernels run 16x16-pixel tiles of 4 waves whatever the tuning says
+  fill_view(p.one, vol, tf, cam, step_world, model, cap);
+  p.one.tiles_x = (cam->width + 15) / 16;
+  p.one.tiles_y = (cam->height + 15) / 16;
+  p.one.image = image;
+  p.one.d_image = d_image;
+  if ((rc = fit_cap(cap, 0, model, p.one.R, &p.lds_cap))) return rc;
+  p.slab_kmax = g_tuning.slab_kmax;
+  p.ndir = ndir;
+  for (int k = 0; k < ndir; ++k) {
+    for (int j = 0; j < 12; ++j) p.dir[k][j] = dirs[k].d_frame[j];
+    p.dir[k][12] = dirs[k].d_step;
+  }
+  p.image_dot = image_dot;
+  p.d_dir = d_dir;
+  const size_t lds = lds_bytes(p.lds_cap, 0, model, p.one.R);
+  if ((rc = check_lds(lds))) return rc;
+  const hipError_t e = (hipError_t)launch_tangent(p, model, vol->dtype,
+                                                   p.one.tiles_x * p.one.tiles_y, lds, hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "tangent launch");
+  return DDVR_OK;
+}
+
 int ddvr_set_tuning(const ddvr_tuning* t) {
   if (!t) return fail(DDVR_ERR_NULL, "tuning is NULL");
   if (t->waves != 1 && t->waves != 2 && t->waves != 4)

@@ -65,6 +65,19 @@ struct LaunchParams {
   int32_t fb_slot_floats; // floats per slot
 };
 
+// Forward-mode (tangent) launch: derivatives of the image along up to
+// kMaxDirections directions in (camera frame, step) space.
+constexpr int kMaxDirections = 4;
+struct TangentParams {
+  ViewDesc one;           // the view (image / trans / d_image pointers inside)
+  int32_t lds_cap;        // voxels per LDS brick (0 = never stage)
+  int32_t slab_kmax;
+  int32_t ndir;           // 1..kMaxDirections
+  float dir[kMaxDirections][13];   // d frame (12: eye, fwd, right, up) and d step
+  float* image_dot;       // [ndir][H][W][C] or null (forward-immediate)
+  float* d_dir;           // [ndir] += <d_image, image_dot_k> or null (forward-delayed)
+};
+
 enum GradBits { GRAD_V = 1, GRAD_TF = 2, GRAD_CAM = 4, GRAD_STEP = 8 };
 
 enum Pass { PASS_FWD = 0, PASS_ADJ = 1, PASS_FUSED = 2 };
@@ -74,6 +87,8 @@ int launch_render(const LaunchParams& p, int pass, int model, int dtype, int wav
                   size_t lds_bytes, void* stream);
 int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void* stream);
 int launch_zero_i32(int32_t* ptr, int n, void* stream);
+int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, size_t lds_bytes,
+                   void* stream);
 int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
 
 constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persistent launch

@@ -568,7 +568,8 @@ __device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int
       TFv t;
       tf_eval(tfl, vd.R, d, t);
       const float e = __expf(-vd.step * t.tau);
-      const float w = s.T * (1.0f - e);
+      // explicitly rounded (no contraction), shared bit for bit with march_tan
+      const float w = __fmul_rn(s.T, __fsub_rn(1.0f, e));
       s.C[0] = fmaf(w, t.r, s.C[0]);
       s.C[1] = fmaf(w, t.g, s.C[1]);
       s.C[2] = fmaf(w, t.b, s.C[2]);
@@ -1238,6 +1239,235 @@ __global__ __launch_bounds__(WAVES * 64) void k_render(const LaunchParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// forward-mode derivatives (Sec. 4.2, forward differentiation)
+// ---------------------------------------------------------------------------
+// Every quantity of the forward march carries its derivatives along P
+// directions in (camera frame, step) space, as the dual numbers of Sec. 4.2
+// do.  The sample count N is piecewise constant in the camera and the step and
+// is not differentiated (the same reading as the adjoint).
+
+// Tangents of the ray's grid-unit positions: q_i' = qo' + i*dq'.
+template <int P>
+struct RayTan {
+  float qo[P][3];
+  float dq[P][3];
+};
+
+template <int P>
+__device__ __forceinline__ void setup_tangent(const ViewDesc& vd, const RayG& r,
+                                              const float (*dir)[13], RayTan<P>& t) {
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const float* de = dir[k];
+    const float* dfw = dir[k] + 3;
+    const float* drt = dir[k] + 6;
+    const float* dup = dir[k] + 9;
+    const float dstep = dir[k][12];
+    // w = fwd + u right + v up, omega = w/|w|: omega' = (w' - omega (omega . w'))/|w|
+    float wd[3], od = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      wd[a] = dfw[a] + r.u * drt[a] + r.v * dup[a];
+      od = fmaf(r.om[a], wd[a], od);
+    }
+    float omd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) omd[a] = (wd[a] - r.om[a] * od) / r.wlen;
+    // entry distance t0 = (b - e_a)/omega_a on the entry plane a
+    float t0d = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a == r.axis) t0d = -(de[a] + r.t0 * omd[a]) / r.om[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      t.qo[k][a] = (de[a] + t0d * r.om[a] + r.t0 * omd[a]) * vd.inv_h;
+      t.dq[k][a] = (dstep * r.om[a] + vd.step * omd[a]) * vd.inv_h;
+    }
+  }
+}
+
+template <int P>
+struct TanState {
+  float C[3], T, sigma;           // primal (as FwdState)
+  float Cd[P][3], Td[P], sigd[P]; // derivatives
+};
+
+template <int MODEL, int DT, bool LDS, int P>
+__device__ __forceinline__ void march_tan(const ViewDesc& vd, const RayG& r, const RayTan<P>& t,
+                                          const float (*dir)[13], int a, int b,
+                                          const float* stage, const Brick& br,
+                                          const float4* tfl, TanState<P>& s) {
+  const float fb = (float)b;
+  for (float fi = (float)a; fi < fb; fi += 1.0f) {
+    Cell c;
+    locate(r, fi, vd, c);
+    float v[8];
+    if (LDS) fetch_lds(stage, br, brick_base(br, c), v);
+    else fetch_global<DT>(vd, c, v);
+    float g[3];
+    trilerp_grad(v, c.f, g);            // d density / d q (grid units)
+    const float d = trilerp(v, c.f);
+    float dd[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      float x = 0.0f;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) x = fmaf(g[ax], fmaf(fi, t.dq[k][ax], t.qo[k][ax]), x);
+      dd[k] = x;
+    }
+    if (MODEL == DDVR_ABSORPTION) {
+      s.sigma += d;
+#pragma unroll
+      for (int k = 0; k < P; ++k) s.sigd[k] += dd[k];
+    } else {
+      TFv tv;
+      tf_eval(tfl, vd.R, d, tv);
+      const float4 ta = tfl[tv.j], tb = tfl[tv.j + 1];
+      const float sc = tv.inside ? (float)(vd.R - 1) : 0.0f;   // d u / d density
+      const float sr = sc * (tb.x - ta.x), sg = sc * (tb.y - ta.y), sb = sc * (tb.z - ta.z),
+                  st = sc * (tb.w - ta.w);
+      const float e = __expf(-vd.step * tv.tau);
+      const float alpha = __fsub_rn(1.0f, e);
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        // c = alpha rgb: c' = alpha' rgb + alpha rgb'; C' += T' c + T c'; T' = T' e + T e'
+        const float taud = st * dd[k];
+        const float ed = -e * fmaf(dir[k][12], tv.tau, vd.step * taud);
+        const float ad = -ed;
+        const float ta = s.Td[k] * alpha;
+        const float cd0 = fmaf(ad, tv.r, alpha * sr * dd[k]);
+        const float cd1 = fmaf(ad, tv.g, alpha * sg * dd[k]);
+        const float cd2 = fmaf(ad, tv.b, alpha * sb * dd[k]);
+        s.Cd[k][0] = fmaf(ta, tv.r, fmaf(s.T, cd0, s.Cd[k][0]));
+        s.Cd[k][1] = fmaf(ta, tv.g, fmaf(s.T, cd1, s.Cd[k][1]));
+        s.Cd[k][2] = fmaf(ta, tv.b, fmaf(s.T, cd2, s.Cd[k][2]));
+        s.Td[k] = fmaf(s.Td[k], e, s.T * ed);
+      }
+      // primal exactly as march_fwd (bitwise the same image)
+      const float w = __fmul_rn(s.T, alpha);
+      s.C[0] = fmaf(w, tv.r, s.C[0]);
+      s.C[1] = fmaf(w, tv.g, s.C[1]);
+      s.C[2] = fmaf(w, tv.b, s.C[2]);
+      s.T *= e;
+    }
+  }
+}
+
+// One 16x16 tile per workgroup (4 waves, compact lane map), slab-synchronous
+// LDS staging as in the forward of k_render.
+template <int MODEL, int DT, int P>
+__global__ __launch_bounds__(256) void k_tangent(const TangentParams p) {
+  constexpr int WAVES = 4, NT = 256, TW = 16, TH = 16;
+  constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
+  extern __shared__ __align__(16) float smem[];
+  const ViewDesc& vd = p.one;
+  const int cap = p.lds_cap;
+  float* stage = smem;
+  float4* tfl = reinterpret_cast<float4*>(smem + cap);
+  int* iscratch = reinterpret_cast<int*>(reinterpret_cast<float*>(tfl) + (EA ? 4 * vd.R : 0));
+  float* fscratch = reinterpret_cast<float*>(iscratch);
+  if (EA)
+    for (int k = threadIdx.x; k < 4 * vd.R; k += NT) reinterpret_cast<float*>(tfl)[k] = vd.tf[k];
+
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int lx, ly;
+  tile_pixel<WAVES>(false, wid, lane, lx, ly);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool valid = px < vd.W && py < vd.H;
+  const int64_t pix = (int64_t)py * vd.W + px;
+  RayG r;
+  setup_ray(vd, px, py, valid, r);
+  const bool hit = r.N > 0;
+  RayTan<P> t;
+  setup_tangent<P>(vd, r, p.dir, t);
+
+  int off = 0, tile_end;
+  const int kmax = cap > 0 ? max(p.slab_kmax, 4) : kMaxSamples + 1;
+  if (cap > 0) {
+    const float tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
+    off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
+  }
+  {
+    int e = hit ? off + r.N : 0;
+    wg_max_n<NT>(&e, 1, iscratch);
+    tile_end = e;
+  }
+  __syncthreads();   // TF table visible
+
+  TanState<P> s;
+  s.C[0] = s.C[1] = s.C[2] = 0.0f;
+  s.T = 1.0f;
+  s.sigma = 0.0f;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    s.Cd[k][0] = s.Cd[k][1] = s.Cd[k][2] = 0.0f;
+    s.Td[k] = 0.0f;
+    s.sigd[k] = 0.0f;
+  }
+  int K = min(vd.slab_k, kmax);
+  for (int pos = 0; pos < tile_end;) {
+    int lo, hi;
+    Brick br;
+    const int st = pick_slab<NT>(vd, r, off, r.N, pos, +1, tile_end, cap, K, kmax, lo, hi,
+                                 iscratch, br);
+    int a, b;
+    slab_range(lo, hi, off, r.N, a, b);
+    if (st == 1) {
+      stage_brick<NT, DT>(vd, br, stage, nullptr);
+      __syncthreads();
+      march_tan<MODEL, DT, true, P>(vd, r, t, p.dir, a, b, stage, br, tfl, s);
+    } else if (st == 2) {
+      march_tan<MODEL, DT, false, P>(vd, r, t, p.dir, a, b, stage, br, tfl, s);
+    }
+    pos = hi;
+  }
+
+  constexpr int C = EA ? 4 : 1;
+  float out[4], outd[P][4];
+  if (EA) {
+    out[0] = s.C[0]; out[1] = s.C[1]; out[2] = s.C[2]; out[3] = 1.0f - s.T;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      outd[k][0] = s.Cd[k][0]; outd[k][1] = s.Cd[k][1]; outd[k][2] = s.Cd[k][2];
+      outd[k][3] = -s.Td[k];
+    }
+  } else {
+    // alpha = 1 - exp(-dt sigma): alpha' = T_N (dt' sigma + dt sigma')
+    const float TN = __expf(-vd.step * s.sigma);
+    out[0] = 1.0f - TN;
+#pragma unroll
+    for (int k = 0; k < P; ++k) outd[k][0] = TN * fmaf(p.dir[k][12], s.sigma, vd.step * s.sigd[k]);
+  }
+  if (valid) {
+    if (vd.image)
+      for (int ch = 0; ch < C; ++ch) vd.image[pix * C + ch] = out[ch];
+    if (p.image_dot) {
+      const int64_t plane = (int64_t)vd.W * vd.H * C;
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+        for (int ch = 0; ch < C; ++ch) p.image_dot[k * plane + pix * C + ch] = outd[k][ch];
+    }
+  }
+  if (p.d_dir) {
+    // forward-delayed: contract with the upstream gradient in the same pass
+    float dk[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      float x = 0.0f;
+      if (valid)
+        for (int ch = 0; ch < C; ++ch) x = fmaf(vd.d_image[pix * C + ch], outd[k][ch], x);
+      dk[k] = x;
+    }
+    wg_sum_n<NT>(dk, P, fscratch);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < P; ++k)
+        if (dk[k] != 0.0f) gadd(p.d_dir + k, dk[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // segment-checkpoint fallback (one ray per thread, queued by the main kernel)
 // ---------------------------------------------------------------------------
 template <int MODEL, int DT, int FUSED>
@@ -1477,6 +1707,35 @@ static hipError_t launch_fb1(const LaunchParams& p, int dtype, int fused, int bl
     case DT_DYN: return launch_fb2<MODEL, DT_DYN>(p, fused, blocks, s);
     default: return launch_fb2<MODEL, DDVR_F32>(p, fused, blocks, s);
   }
+}
+
+template <int MODEL, int DT>
+static hipError_t launch_tan2(const TangentParams& p, int n_blocks, size_t lds, hipStream_t s) {
+  switch (p.ndir) {
+    case 1: hipLaunchKernelGGL((k_tangent<MODEL, DT, 1>), dim3(n_blocks), dim3(256), lds, s, p); break;
+    case 2: hipLaunchKernelGGL((k_tangent<MODEL, DT, 2>), dim3(n_blocks), dim3(256), lds, s, p); break;
+    case 3: hipLaunchKernelGGL((k_tangent<MODEL, DT, 3>), dim3(n_blocks), dim3(256), lds, s, p); break;
+    default: hipLaunchKernelGGL((k_tangent<MODEL, DT, 4>), dim3(n_blocks), dim3(256), lds, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODEL>
+static hipError_t launch_tan1(const TangentParams& p, int dtype, int n_blocks, size_t lds,
+                              hipStream_t s) {
+  switch (dtype) {
+    case DDVR_F16: return launch_tan2<MODEL, DDVR_F16>(p, n_blocks, lds, s);
+    case DDVR_BF16: return launch_tan2<MODEL, DDVR_BF16>(p, n_blocks, lds, s);
+    default: return launch_tan2<MODEL, DDVR_F32>(p, n_blocks, lds, s);
+  }
+}
+
+int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, size_t lds_bytes,
+                   void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  return (int)(model == DDVR_EMISSION_ABSORPTION
+                   ? launch_tan1<DDVR_EMISSION_ABSORPTION>(p, dtype, n_blocks, lds_bytes, s)
+                   : launch_tan1<DDVR_ABSORPTION>(p, dtype, n_blocks, lds_bytes, s));
 }
 
 int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void* stream) {

@@ -30,7 +30,9 @@ EXPORTED = [
     "ddvr_render_adjoint", "ddvr_render_fused_l2", "ddvr_batch_create", "ddvr_batch_destroy",
     "ddvr_batch_workspace_size", "ddvr_batch_run", "ddvr_batch_run_graph",
     "ddvr_batch_sample_count", "ddvr_cast_volume", "ddvr_set_tuning", "ddvr_get_tuning",
+    "ddvr_render_tangent", "ddvr_camera_sphere_tangents",
 ]
+MAX_DIRECTIONS = 4
 
 
 class DDVRError(RuntimeError):
@@ -109,6 +111,8 @@ def lib():
         "ddvr_cast_volume": ([P, P, I32, ctypes.c_int64, P], ctypes.c_int),
         "ddvr_set_tuning": ([P], ctypes.c_int),
         "ddvr_get_tuning": ([P], ctypes.c_int),
+        "ddvr_render_tangent": ([P, P, P, F, I32, P, I32, P, P, P, P, I32, P], ctypes.c_int),
+        "ddvr_camera_sphere_tangents": ([F, F, F, F, I32, I32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -163,6 +167,34 @@ def tf_desc(tf) -> TF:
 
 def grads_desc(d_volume=None, d_tf=None, d_camera=None, d_step=None) -> Grads:
     return Grads(_ptr(d_volume), _ptr(d_tf), _ptr(d_camera), _ptr(d_step))
+
+
+class Direction(ctypes.Structure):
+    _fields_ = [("d_frame", ctypes.c_float * 12), ("d_step", ctypes.c_float)]
+
+
+def render_tangent(volume, tf, cam: Camera, step: float, model: int, dirs, image=None,
+                   image_dot=None, d_image=None, d_dir=None, flags: int = 0, stream=None):
+    """Forward-mode derivatives along up to 4 directions; dirs is a sequence of
+    13 numbers each (d frame[12], d step) -- see include/ddvr.h."""
+    dirs = [list(map(float, x)) for x in dirs]
+    arr = (Direction * max(len(dirs), 1))()
+    for k, x in enumerate(dirs):
+        if len(x) != 13:
+            raise ValueError("a direction has 13 components (frame[12], step)")
+        arr[k].d_frame[:] = x[:12]
+        arr[k].d_step = x[12]
+    v, t = volume_desc(volume), tf_desc(tf)
+    _check(lib().ddvr_render_tangent(ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step,
+                                     model, arr, len(dirs), _ptr(image), _ptr(image_dot),
+                                     _ptr(d_image), _ptr(d_dir), flags, _stream(stream)))
+
+
+def camera_sphere_tangents(yaw, pitch, dist, fovy, width, height):
+    """[4][12]: d frame / d (yaw, pitch, dist, fovy), angles in radians."""
+    out = (ctypes.c_float * 48)()
+    _check(lib().ddvr_camera_sphere_tangents(yaw, pitch, dist, fovy, width, height, out))
+    return [list(out[12 * k:12 * k + 12]) for k in range(4)]
 
 
 def abi_version() -> int:

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     d = _ddvr()
-    assert d.abi_version() == 1
+    assert d.abi_version() == 2
     assert isinstance(d.last_error(), str)
 
 
@@ -188,3 +188,41 @@ def test_tuning_roundtrip_and_validation():
     finally:
         d.set_tuning(**old)
     assert d.get_tuning() == old
+
+
+def test_tangent_rejects_bad_arguments_before_launch():
+    d = _ddvr()
+    L = d.lib()
+    vol, tf, cam = _descs(d)
+    B = ctypes.byref
+    tan = L.ddvr_render_tangent
+    dirs = (d.Direction * 4)()
+    dirs[0].d_step = 1.0
+    img, dot, g, dd = 0x3000, 0x4000, 0x5000, 0x6000
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, None, 1, img, None, None, None, 0, None) == d.ERR_NULL
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, dirs, 0, img, None, None, None, 0, None) == d.ERR_VALUE
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, dirs, 5, img, None, None, None, 0, None) == d.ERR_VALUE
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, dirs, 1, None, None, None, None, 0, None) == d.ERR_NULL
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, dirs, 1, img, None, None, dd, 0, None) == d.ERR_NULL
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, dirs, 1, img, dot, g, dd, 1, None) == d.ERR_VALUE
+    bad = (d.Direction * 1)()
+    bad[0].d_frame[3] = float("nan")
+    assert tan(B(vol), B(tf), B(cam), 0.1, 1, bad, 1, img, dot, None, None, 0, None) == d.ERR_VALUE
+    assert tan(B(vol), B(tf), B(cam), 0.0, 1, dirs, 1, img, dot, None, None, 0, None) == d.ERR_VALUE
+    assert tan(B(vol), B(d.TF(None, 4)), B(cam), 0.1, 1, dirs, 1, img, dot, None, None, 0,
+               None) == d.ERR_NULL
+
+
+def test_camera_sphere_tangents_match_oracle_jacobian():
+    d = _ddvr()
+    args = (40.0, 25.0, 2.7, 55.0, 96, 64)
+    got = np.array(d.camera_sphere_tangents(math.radians(40), math.radians(25), 2.7,
+                                            math.radians(55), 96, 64))
+    ref = oracle.camera_jacobian(*args)
+    assert got.shape == (4, 12)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-6)
+    # the transpose of the gradient chain rule
+    g = np.random.default_rng(5).normal(size=12)
+    back = d.camera_grad_to_sphere(math.radians(40), math.radians(25), 2.7, math.radians(55), 96,
+                                   64, g)
+    assert np.allclose(back, got @ g, rtol=1e-5, atol=1e-5)

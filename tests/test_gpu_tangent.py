@@ -1,0 +1,143 @@
+"""Forward-mode derivatives on the GPU (Sec. 4.2 forward variables along camera
+and step directions) against the FP64 oracle's dual-number forward pass, on
+the same seeded inputs.
+
+Tolerances (per pixel, rays that are ties or pass within float32 position
+error of a kink excluded, as for the adjoint's camera gradients in
+harness.py): the tangent images within 1e-3 relative of max(|oracle|, 1e-2 x
+the image's scale), on pixels whose FP64 tangent itself is stable to that
+level under a 1e-7 relative perturbation of the camera frame (float32
+rounding of the input; a per-pixel derivative of a long emission-absorption
+ray is a sum with cancellation and can be ill-conditioned); the
+forward-delayed contraction within 1e-3 of the oracle's adjoint dotted with
+the direction (the paper's claim that both modes give the same derivative);
+the image bitwise the forward pass's.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from harness import (Problem, assert_grad_close, device_volume, gpu_camera, gpu_forward,
+                     kink_mask, oracle_adjoint, oracle_camera, oracle_forward, tie_mask,
+                     dequantized)
+from test_gpu_parity import c1_problem, ea_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _directions(p: Problem, rng):
+    """yaw, pitch, dist (the sphere camera's tangents), the step, and a random
+    frame direction."""
+    from paper_2107_12672_amd import ddvr as d
+    J = d.camera_sphere_tangents(math.radians(p.yaw), math.radians(p.pitch), p.dist,
+                                 math.radians(p.fovy), p.W, p.H)
+    rnd = list(rng.normal(size=12) * 0.05)
+    return [J[0] + [0.0], J[1] + [0.0], J[2] + [0.0], [0.0] * 12 + [p.step], rnd + [0.0]]
+
+
+def _gpu_tangent(p: Problem, dirs, flags=0, d_image=None):
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    vol = device_volume(p)
+    tf = torch.from_numpy(p.tf).cuda() if p.tf is not None else None
+    n = p.H * p.W * p.C
+    img = torch.full((n,), float("nan"), device="cuda")
+    dot = torch.full((len(dirs), n), float("nan"), device="cuda")
+    g = None if d_image is None else torch.from_numpy(
+        np.ascontiguousarray(d_image, dtype=np.float32)).cuda()
+    dd = None if d_image is None else torch.zeros(len(dirs), device="cuda")
+    d.render_tangent(vol, tf, gpu_camera(p), p.step, p.model, dirs, image=img, image_dot=dot,
+                     d_image=g, d_dir=dd, flags=flags)
+    torch.cuda.synchronize()
+    return (img.view(p.H * p.W, p.C).cpu().numpy(),
+            dot.view(len(dirs), p.H * p.W, p.C).cpu().numpy(),
+            None if dd is None else dd.cpu().double().numpy())
+
+
+def _oracle_dot(p: Problem, direction):
+    V = dequantized(p)
+    return oracle.render_dual(V, p.tf, oracle_camera(p), p.W, p.H, p.step, p.model,
+                              cam_dir=np.asarray(direction[:12], np.float64),
+                              step_dir=float(direction[12]))["image_dot"]
+
+
+def _unstable(p: Problem, direction, ref, rel=1e-7, trials=3, seed=3):
+    """Pixels whose oracle tangent moves by more than the tolerance when the
+    camera frame is perturbed by `rel` relative."""
+    V = dequantized(p)
+    cam = oracle_camera(p)
+    rng = np.random.default_rng(seed)
+    scale = float(np.abs(ref).max())
+    bound = 1e-3 * np.maximum(np.abs(ref), 1e-2 * scale)
+    out = np.zeros(ref.shape[0], dtype=bool)
+    for _ in range(trials):
+        a = oracle.render_dual(V, p.tf, cam * (1.0 + rel * rng.normal(size=12)), p.W, p.H,
+                               p.step, p.model, cam_dir=np.asarray(direction[:12], np.float64),
+                               step_dir=float(direction[12]))["image_dot"]
+        out |= (np.abs(a - ref) > 0.5 * bound).any(axis=1)
+    return out
+
+
+def _problems():
+    return {"ao": c1_problem()[0], "ea": ea_problem(W=56, H=44)}
+
+
+@pytest.mark.parametrize("which", ["ao", "ea"])
+@pytest.mark.parametrize("flags", [0, 0x10])
+def test_tangent_images_match_oracle_dual_numbers(which, flags):
+    p = _problems()[which]
+    rng = np.random.default_rng(21)
+    _say(f"tangent images {which} flags={flags}")
+    dirs = _directions(p, rng)
+    keep = ~(tie_mask(oracle_forward(p)["ratio"]) | kink_mask(p))
+    for chunk in (dirs[:4], dirs[4:]):          # 4 directions, then 1 (two instantiations)
+        img, dot, _ = _gpu_tangent(p, chunk, flags)
+        fwd, _ = gpu_forward(p, flags)
+        assert np.array_equal(img, fwd), "the tangent pass must render the forward's image"
+        for k, direction in enumerate(chunk):
+            ref = _oracle_dot(p, direction)
+            ok = keep & ~_unstable(p, direction, ref)
+            assert ok.sum() >= 0.95 * keep.sum()       # the screen drops few rays
+            assert_grad_close(dot[k][ok], ref[ok], f"{which} image_dot dir {k}")
+
+
+@pytest.mark.parametrize("which", ["ao", "ea"])
+def test_forward_delayed_equals_the_adjoint_contraction(which):
+    """d_dir[k] = <d_image, d image / d direction_k> from the forward pass
+    equals the oracle's adjoint gradient dotted with the direction, and the
+    forward-immediate tangent images contracted on the host."""
+    p = _problems()[which]
+    rng = np.random.default_rng(22)
+    _say(f"forward-delayed {which}")
+    dirs = _directions(p, rng)[:4]
+    ora = oracle_forward(p)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[tie_mask(ora["ratio"]) | kink_mask(p)] = 0.0
+    _, dot, dd = _gpu_tangent(p, dirs, d_image=g)
+    adj = oracle_adjoint(p, g)
+    ref = np.array([np.dot(adj["dcam"], np.asarray(x[:12], np.float64)) + adj["dstep"] * x[12]
+                    for x in dirs])
+    assert_grad_close(dd, ref, f"{which} forward-delayed")
+    host = np.einsum("kpc,pc->k", dot.astype(np.float64), g)
+    assert np.allclose(dd, host, rtol=1e-4, atol=1e-6 * np.abs(host).max())
+
+
+def test_tangent_low_precision_storage():
+    p = ea_problem(W=40, H=40, storage="bf16", seed=9)
+    rng = np.random.default_rng(23)
+    _say("tangent bf16")
+    dirs = _directions(p, rng)[:2]
+    keep = ~(tie_mask(oracle_forward(p)["ratio"]) | kink_mask(p))
+    _, dot, _ = _gpu_tangent(p, dirs)
+    for k, direction in enumerate(dirs):
+        ref = _oracle_dot(p, direction)
+        ok = keep & ~_unstable(p, direction, ref)
+        assert_grad_close(dot[k][ok], ref[ok], f"bf16 dir {k}")
