@@ -168,7 +168,9 @@ def secondary(args):
           and step gradients (seeded upstream gradients);
       c5  emission-absorption 512^3 f16 sparse noise, R=32, 32 views at
           1024x1024, fused L2 with density, TF and step gradients: T-form
-          inversion (AUTO) and segment checkpointing (CHECKPOINT)."""
+          inversion (AUTO) and segment checkpointing (CHECKPOINT);
+      viewpoint  the C5 grid and views, gradient w.r.t. (yaw, pitch, dist) of
+          every view by forward-mode (delayed / immediate) and by the adjoint."""
     import numpy as np
     import torch
     import synth
@@ -242,6 +244,64 @@ def secondary(args):
                                "tuning": d.get_tuning()}})
         if "checkpoint" in res:
             out["checkpoint"] = res["checkpoint"]
+    elif args.workload == "viewpoint":
+        # viewpoint gradients (yaw, pitch, dist) of every view of the C5 grid:
+        # forward-delayed (one tangent pass per view), forward-immediate
+        # (tangent images written), and the adjoint (batched forward + adjoint
+        # with camera gradients) -- the comparison of Sec. 5.1
+        w = synth.make_c5()
+        vol = stored(w.volume, w.storage)
+        tf = torch.from_numpy(w.tf).to(dev)
+        cams = cams_of(w.views)
+        nv = len(cams)
+        W = H = w.views[0].width
+        rng = synth.rng_for(9, 5)
+        gs = torch.from_numpy(rng.normal(size=(nv, H, W, 4)).astype(np.float32)
+                              / (H * W)).to(dev)
+        dirs = []
+        for v in w.views:
+            J = d.camera_sphere_tangents(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                         math.radians(v.fovy), W, H)
+            dirs.append([J[0] + [0.0], J[1] + [0.0], J[2] + [0.0]])
+        images = torch.empty((nv, H, W, 4), device=dev)
+        dots = torch.empty((3, H, W, 4), device=dev)
+        d_dir = torch.zeros((nv, 3), device=dev)
+
+        def delayed():
+            for i in range(nv):
+                d.render_tangent(vol, tf, cams[i], w.step_world, d.EMISSION_ABSORPTION, dirs[i],
+                                 image=images[i], d_image=gs[i], d_dir=d_dir[i])
+
+        def immediate():
+            for i in range(nv):
+                d.render_tangent(vol, tf, cams[i], w.step_world, d.EMISSION_ABSORPTION, dirs[i],
+                                 image=images[i], image_dot=dots)
+
+        trans = torch.empty((nv, H, W), device=dev)
+        dcam = torch.zeros((nv, 12), device=dev)
+        views = [d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
+                             d_image=gs[i], d_camera=dcam[i], tf_index=0) for i in range(nv)]
+        b = d.Batch([vol], [tf], views, d.EMISSION_ABSORPTION)
+        ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+        S = b.sample_count()
+
+        def adjoint():
+            b.run(d.PASS_FORWARD, graph=True)
+            b.run(d.PASS_ADJOINT, workspace=ws, graph=True)
+
+        res = {}
+        for name, fn in (("forward_delayed", delayed), ("forward_immediate", immediate),
+                         ("adjoint", adjoint)):
+            ms = _timed(fn, args.steps, args.warmup, stream, torch)
+            res[name] = {"ms_per_step": ms, "value": S / (ms * 1e-3)}
+            log(f"viewpoint {name}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+        out.update({"metric": "ray-samples/s of the viewpoint (yaw, pitch, dist) gradient",
+                    "value": res["forward_delayed"]["value"],
+                    "ms_per_step": res["forward_delayed"]["ms_per_step"],
+                    "config": {"workload": w.name + ", gradient w.r.t. yaw, pitch, dist of "
+                                                    "every view (seeded upstream gradients)",
+                               "samples_per_step": S},
+                    "routes": res})
     else:   # c4
         ws_ = synth.make_c4()
         vols = [stored(w.volume, w.storage) for w in ws_]
@@ -288,7 +348,7 @@ def main():
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
     ap.add_argument("--step-vox", type=float, default=0.2)
-    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5"),
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint"),
                     help="c3 (default) is the headline tomography step; the others print "
                          "their own line")
     ap.add_argument("--burn-in", type=int, default=4,
