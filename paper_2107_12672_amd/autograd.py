@@ -9,6 +9,12 @@ a PyTorch custom operation with a backward pass, Sec. 4.4 last paragraph).
   ``ddvr_cast_volume``); backward = ``ddvr_render_adjoint`` in AUTO mode, i.e.
   the inversion trick with the segment-checkpoint fallback for nearly opaque
   rays.  Gradients are returned in float32 for the master grid.
+* :class:`ViewpointFunction` -- the same render with the camera given as its
+  sphere pose; the gradients of the pose and the step come from forward-mode
+  derivatives (``ddvr_render_tangent``, "forward-delayed" of Sec. 5.1: the
+  backward re-traces the rays with the forward variables and contracts them
+  with the upstream gradient in the kernel), those of the grid and the TF from
+  the adjoint.
 
 All arithmetic runs in the HIP library; these classes only allocate outputs
 and pass pointers.
@@ -113,6 +119,94 @@ class DDVRFunction(torch.autograd.Function):
         g_frame = dcam.to(ctx.frame_device) if dcam is not None else None
         g_step = dstep.reshape(()).to(ctx.step_device) if dstep is not None else None
         return dV, dTF, g_frame, g_step, None, None, None, None, None
+
+
+def _stored(volume, storage):
+    if not volume.is_cuda:
+        raise ValueError("volume must be a device tensor")
+    volume = volume.contiguous()
+    if volume.dtype != torch.float32:
+        raise ValueError("the master grid is float32; choose the stored form with `storage`")
+    if storage == torch.float32:
+        return volume
+    out = torch.empty_like(volume, dtype=storage)
+    _d.cast_volume(volume, out)
+    return out
+
+
+class ViewpointFunction(torch.autograd.Function):
+    """image = render(volume, tf, camera on the sphere (yaw, pitch, dist, fovy;
+    radians), step); pose and step gradients by forward mode."""
+
+    @staticmethod
+    def forward(ctx, volume, tf, yaw, pitch, dist, fovy, step, model: int, width: int,
+                height: int, storage: torch.dtype = torch.float32):
+        stored = _stored(volume, storage)
+        if model == _d.EMISSION_ABSORPTION:
+            if tf is None:
+                raise ValueError("emission-absorption needs a transfer function")
+            tf = tf.contiguous()
+        pose = [float(t) for t in (yaw, pitch, dist, fovy)]
+        cam = _d.camera_from_sphere(*pose, width, height)
+        C = 4 if model == _d.EMISSION_ABSORPTION else 1
+        image = torch.empty((height, width, C) if C == 4 else (height, width),
+                            device=volume.device, dtype=torch.float32)
+        trans = torch.empty((height, width), device=volume.device, dtype=torch.float32)
+        s = float(step)
+        _d.render_forward(stored, tf, cam, s, model, image, trans)
+        ctx.save_for_backward(stored, tf if tf is not None else torch.empty(0), image, trans)
+        ctx.has_tf = tf is not None
+        ctx.cam, ctx.pose, ctx.step, ctx.model, ctx.wh = cam, pose, s, model, (width, height)
+        return image
+
+    @staticmethod
+    def backward(ctx, g_image):
+        stored, tf, image, trans = ctx.saved_tensors
+        tf = tf if ctx.has_tf else None
+        need = ctx.needs_input_grad
+        dev = stored.device
+        g = g_image.contiguous().to(torch.float32)
+        # forward mode for the pose (yaw, pitch, dist, fovy) and the step
+        J = _d.camera_sphere_tangents(*ctx.pose, *ctx.wh)
+        dirs, slots = [], []
+        for k in range(4):
+            if need[2 + k]:
+                dirs.append(J[k] + [0.0])
+                slots.append(2 + k)
+        if need[6]:
+            dirs.append([0.0] * 12 + [1.0])
+            slots.append(6)
+        grads = [None] * 11
+        if dirs:
+            d_dir = torch.zeros(len(dirs), device=dev, dtype=torch.float32)
+            for c in range(0, len(dirs), _d.MAX_DIRECTIONS):
+                _d.render_tangent(stored, tf, ctx.cam, ctx.step, ctx.model,
+                                  dirs[c:c + _d.MAX_DIRECTIONS], d_image=g,
+                                  d_dir=d_dir[c:c + _d.MAX_DIRECTIONS])
+            vals = d_dir.to("cpu")
+            for j, slot in enumerate(slots):
+                grads[slot] = vals[j].clone()
+        # the adjoint for the grid and the TF
+        if need[0] or (need[1] and tf is not None):
+            dV = torch.zeros(stored.shape, device=dev, dtype=torch.float32) if need[0] else None
+            dTF = torch.zeros_like(tf) if (need[1] and tf is not None) else None
+            n = _d.adjoint_workspace_size(stored, ctx.cam, ctx.step, ctx.model, 0)
+            ws = torch.empty((n + 3) // 4, device=dev, dtype=torch.int32) if n else None
+            _d.render_adjoint(stored, tf, ctx.cam, ctx.step, ctx.model, image, trans, g,
+                              _d.grads_desc(dV, dTF), workspace=ws)
+            grads[0], grads[1] = dV, dTF
+        return tuple(grads)
+
+
+def render_viewpoint(volume: torch.Tensor, tf: Optional[torch.Tensor], yaw, pitch, dist, fovy,
+                     step, model: int, width: int, height: int,
+                     storage: torch.dtype = torch.float32) -> torch.Tensor:
+    """Differentiable render from a sphere pose; pose/step gradients by forward
+    mode (see ViewpointFunction)."""
+    t = [x if isinstance(x, torch.Tensor) else torch.tensor(float(x))
+         for x in (yaw, pitch, dist, fovy, step)]
+    return ViewpointFunction.apply(volume, tf, t[0], t[1], t[2], t[3], t[4], model, width,
+                                   height, storage)
 
 
 def camera_frame(yaw, pitch, dist, fovy, width: int, height: int) -> torch.Tensor:

@@ -105,3 +105,34 @@ def test_directional_derivative_against_oracle_finite_difference_c2():
     eps = 1e-4
     fd = (loss(eps) - loss(-eps)) / (2 * eps)
     assert abs(fd - lin) <= 2e-3 * abs(fd) + 1e-6, (fd, lin)
+
+
+def test_viewpoint_autograd_forward_mode_matches_oracle():
+    """render_viewpoint: pose (yaw, pitch, dist, fovy) and step gradients by
+    forward mode, grid and TF gradients by the adjoint, all against the
+    oracle's adjoint chained to the sphere pose."""
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    p = _ea("f32")
+    _say("viewpoint autograd (forward mode)")
+    ora = oracle_forward(p)
+    mask = tie_mask(ora["ratio"]) | kink_mask(p)
+    rng = np.random.default_rng(24)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[mask] = 0.0
+    dev = torch.device("cuda")
+    V = torch.from_numpy(p.volume).to(dev).requires_grad_(True)
+    T = torch.from_numpy(p.tf).to(dev).requires_grad_(True)
+    pose = [torch.tensor(x, requires_grad=True) for x in
+            (math.radians(p.yaw), math.radians(p.pitch), p.dist, math.radians(p.fovy))]
+    step = torch.tensor(p.step, requires_grad=True)
+    img = ag.render_viewpoint(V, T, *pose, step, d.EMISSION_ABSORPTION, p.W, p.H)
+    gt = torch.from_numpy(g.reshape(p.H, p.W, 4).astype(np.float32)).to(dev)
+    (img * gt).sum().backward()
+    ref = oracle_adjoint(p, g)
+    sph = oracle.sphere_grad(ref["dcam"], p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H)
+    got = np.array([t.grad.item() for t in pose])
+    assert_grad_close(got, sph, "forward-mode yaw/pitch/dist/fovy", rtol=2e-3)
+    assert_grad_close([step.grad.item()], [ref["dstep"]], "forward-mode step")
+    assert_dv_close(V.grad.double().cpu().numpy(), ref["dV"], "viewpoint dV")
+    assert_grad_close(T.grad.double().cpu().numpy(), ref["dTF"], "viewpoint dTF")
