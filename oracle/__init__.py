@@ -25,7 +25,7 @@ _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "libddvr_oracle.so")
 
 TAPE, INV_T, INV_ALPHA, CHECKPOINT, RESIDUAL = 0, 1, 2, 3, 4
-AO, EA = 0, 1
+AO, EA, COLOR = 0, 1, 2     # COLOR: pre-shaded colour volume [nz][ny][nx][4] = (r, g, b, tau)
 
 _lib = None
 
@@ -120,13 +120,13 @@ def _pix(pix):
 def render(volume, tf, cam, W, H, step, model, pix=None):
     """Returns dict(image [npix,C], trans [npix], nsamp [npix], ratio [npix])."""
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     T = _f64(tf) if model == EA else None
     R = 0 if T is None else T.shape[0]
     cam = _f64(cam)
     p, npix = _pix(pix)
     n = npix if p is not None else W * H
-    C = 4 if model == EA else 1
+    C = 1 if model == AO else 4
     image = np.zeros((n, C), np.float64)
     trans = np.zeros(n, np.float64)
     nsamp = np.zeros(n, np.int32)
@@ -141,7 +141,7 @@ def adjoint(volume, tf, cam, W, H, step, model, d_image, variant=TAPE, pix=None,
             want_dV=True):
     """Gradients of <d_image, image> -> dict(dV, dTF, dcam, dstep)."""
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     T = _f64(tf) if model == EA else None
     R = 0 if T is None else T.shape[0]
     cam = _f64(cam)
@@ -162,13 +162,13 @@ def render_dual(volume, tf, cam, W, H, step, model, V_dir=None, tf_dir=None, cam
                 step_dir=0.0, pix=None):
     """Forward mode along one direction -> dict(image, image_dot, trans, trans_dot)."""
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     T = _f64(tf) if model == EA else None
     R = 0 if T is None else T.shape[0]
     cam = _f64(cam)
     p, npix = _pix(pix)
     n = npix if p is not None else W * H
-    C = 4 if model == EA else 1
+    C = 1 if model == AO else 4
     image = np.zeros((n, C)); image_dot = np.zeros((n, C))
     trans = np.zeros(n); trans_dot = np.zeros(n)
     _check(_load().oracle_render_dual(
@@ -180,7 +180,7 @@ def render_dual(volume, tf, cam, W, H, step, model, V_dir=None, tf_dir=None, cam
 
 def trilinear(volume, x) -> float:
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     xx = _f64(x)
     out = np.zeros(1)
     _check(_load().oracle_trilinear(_ptr(V), nx, ny, nz, _ptr(xx), _ptr(out)), "trilinear")
@@ -214,7 +214,7 @@ def sphere_grad(dcam, yaw_deg, pitch_deg, dist, fovy_deg, W, H) -> np.ndarray:
 def trace_ray(volume, tf, cam, W, H, px, py, step, model, cap=100000):
     """Per-sample (d, tau, T_before, x) of one pixel's ray."""
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     T = _f64(tf) if model == EA else None
     R = 0 if T is None else T.shape[0]
     d = np.zeros(cap); tau = np.zeros(cap); Tb = np.zeros(cap); x = np.zeros(3 * cap)
@@ -232,7 +232,7 @@ def kinks(volume, tf, cam, W, H, step, model, pix=None, with_entry=False):
     min distance of d*(R-1) to a TF knot [EA]) and, with_entry, t0/|omega_a|
     of the entry plane a."""
     V = _f64(volume)
-    nz, ny, nx = V.shape
+    nz, ny, nx = V.shape[:3]
     T = _f64(tf) if model == EA else None
     R = 0 if T is None else T.shape[0]
     p, npix = _pix(pix)

@@ -41,6 +41,12 @@
 //   - camera: pinhole, up = +y, pixel centres, frame (eye, fwd, right*s_x,
 //     up*s_y) with s_y = tan(fovy/2), s_x = s_y * W/H.
 //   - AO (absorption-only) model: tau(d) = d per world unit, no clamp, rgb=0.
+//   - pre-shaded colour volume (Sec. 5.4: the colour volume stores rgb
+//     emission and absorption per voxel instead of a density mapped by a TF):
+//     grid [nz][ny][nx][4] of (r, g, b, tau), each channel interpolated
+//     trilinearly, then the same Beer-Lambert segment and blend as the
+//     emission-absorption model.  In the code it is the emission model
+//     without a TF (T == nullptr).
 
 #include <cmath>
 #include <cstdint>
@@ -225,6 +231,20 @@ S trilinear(const Grid& g, const VS* V, const Cell<S>& c) {
   return d;
 }
 
+// Channel ch of a grid of 4-vectors [nz][ny][nx][4] (the colour volume).
+template <class S, class VS>
+S trilinear_ch(const Grid& g, const VS* V4, const Cell<S>& c, int ch) {
+  S d = S(0.0);
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        S w = (cx ? c.f[0] : S(1.0) - c.f[0]) * (cy ? c.f[1] : S(1.0) - c.f[1]) *
+              (cz ? c.f[2] : S(1.0) - c.f[2]);
+        d = d + w * S(V4[4 * vidx(g, c.k[0] + cx, c.k[1] + cy, c.k[2] + cz) + ch]);
+      }
+  return d;
+}
+
 // --------------------------------------------------------------------------
 // G6: piecewise-linear TF (f_TF), R regularly spaced knots at k/(R-1).
 // --------------------------------------------------------------------------
@@ -274,10 +294,16 @@ Sample<S> eval_sample(const Grid& g, const VS* V, const TS* T, int R, bool ea,
   Sample<S> s;
   for (int a = 0; a < 3; ++a) s.x[a] = r.xo[a] + S(double(i)) * dt * r.omega[a];
   s.cell = locate(g, s.x);
-  s.d = trilinear(g, V, s.cell);
-  if (ea) {
+  if (ea && !T) {
+    // colour volume: (r, g, b, tau) interpolated per channel, no TF
+    for (int ch = 0; ch < 3; ++ch) s.tf.rgb[ch] = trilinear_ch(g, V, s.cell, ch);
+    s.tf.tau = trilinear_ch(g, V, s.cell, 3);
+    s.d = s.tf.tau;
+  } else if (ea) {
+    s.d = trilinear(g, V, s.cell);
     s.tf = tf_lookup(s.d, T, R);
   } else {
+    s.d = trilinear(g, V, s.cell);
     s.tf.rgb[0] = s.tf.rgb[1] = s.tf.rgb[2] = S(0.0);
     s.tf.tau = s.d;
   }
@@ -327,6 +353,36 @@ void adjoint_below_blend(const Grid& g, const double* V, const double* T, int R,
                          const Ray<double>& r, double dt, int i, const Sample<double>& s,
                          double tau_hat, const double* rgb_hat, GradAcc& acc,
                          double* xo_hat, double* om_hat) {
+  if (ea && !T) {
+    // colour volume: every channel's value adjoint goes to its own grid
+    const double g4[4] = {rgb_hat[0], rgb_hat[1], rgb_hat[2], tau_hat};
+    const Cell<double>& c = s.cell;
+    double dd_df[3] = {0.0, 0.0, 0.0};
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          double wx = cx ? c.f[0] : 1.0 - c.f[0];
+          double wy = cy ? c.f[1] : 1.0 - c.f[1];
+          double wz = cz ? c.f[2] : 1.0 - c.f[2];
+          int64_t id = vidx(g, c.k[0] + cx, c.k[1] + cy, c.k[2] + cz);
+          for (int ch = 0; ch < 4; ++ch) {
+            if (acc.want_dV) acc.dV[4 * id + ch] += wx * wy * wz * g4[ch];
+            double v = g4[ch] * V[4 * id + ch];
+            dd_df[0] += (cx ? 1.0 : -1.0) * wy * wz * v;
+            dd_df[1] += wx * (cy ? 1.0 : -1.0) * wz * v;
+            dd_df[2] += wx * wy * (cz ? 1.0 : -1.0) * v;
+          }
+        }
+    double om_dot = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double xh = dd_df[a] / g.h;
+      xo_hat[a] += xh;
+      om_hat[a] += double(i) * dt * xh;
+      om_dot += r.omega[a] * xh;
+    }
+    acc.dstep += double(i) * om_dot;
+    return;
+  }
   // f_TF adjoint
   double d_hat;
   if (ea) {
@@ -579,9 +635,11 @@ int oracle_render(const double* V, int nx, int ny, int nz, const double* tf, int
                   const double* cam, int W, int H, double step, int model,
                   const int32_t* pix, int64_t npix, double* image, double* trans,
                   int32_t* nsamp, double* ratio) {
-  const bool ea = model == 1;
-  if (!V || !cam || (ea && !tf)) return -1;
-  if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
+  if (model < 0 || model > 2) return -3;
+  const bool ea = model >= 1;                 // emission: TF model or colour volume
+  if (model == 2) tf = nullptr;
+  if (!V || !cam || (model == 1 && !tf)) return -1;
+  if (!check_common(nx, ny, nz, R, model == 1, W, H, step)) return -2;
   const Grid g = make_grid(nx, ny, nz);
   const int64_t n = pix ? npix : int64_t(W) * H;
   const int C = ea ? 4 : 1;
@@ -614,15 +672,17 @@ int oracle_adjoint(const double* V, int nx, int ny, int nz, const double* tf, in
                    const double* cam, int W, int H, double step, int model,
                    const int32_t* pix, int64_t npix, const double* d_image, int variant,
                    int ck_K, double* dV, double* dTF, double* dcam, double* dstep) {
-  const bool ea = model == 1;
-  if (!V || !cam || !d_image || (ea && !tf)) return -1;
-  if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
+  if (model < 0 || model > 2) return -3;
+  const bool ea = model >= 1;
+  if (model == 2) { tf = nullptr; dTF = nullptr; }
+  if (!V || !cam || !d_image || (model == 1 && !tf)) return -1;
+  if (!check_common(nx, ny, nz, R, model == 1, W, H, step)) return -2;
   if (variant < 0 || variant > 4) return -3;
   const Grid g = make_grid(nx, ny, nz);
   const int64_t n = pix ? npix : int64_t(W) * H;
   const int C = ea ? 4 : 1;
-  const size_t nv = size_t(nx) * ny * nz;
-  const size_t ntf = ea ? size_t(R) * 4 : 0;
+  const size_t nv = size_t(nx) * ny * nz * (model == 2 ? 4 : 1);
+  const size_t ntf = model == 1 ? size_t(R) * 4 : 0;
   // one float64 gradient copy per thread; bound their total to ~2 GiB so that
   // sparse pixel sets on large grids stay cheap
   int nt = nthreads_max();
@@ -659,12 +719,14 @@ int oracle_render_dual(const double* V, const double* V_dir, int nx, int ny, int
                        const double* cam_dir, int W, int H, double step, double step_dir,
                        int model, const int32_t* pix, int64_t npix, double* image,
                        double* image_dot, double* trans, double* trans_dot) {
-  const bool ea = model == 1;
-  if (!V || !cam || (ea && !tf)) return -1;
-  if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
+  if (model < 0 || model > 2) return -3;
+  const bool ea = model >= 1;
+  if (model == 2) { tf = nullptr; tf_dir = nullptr; }
+  if (!V || !cam || (model == 1 && !tf)) return -1;
+  if (!check_common(nx, ny, nz, R, model == 1, W, H, step)) return -2;
   const Grid g = make_grid(nx, ny, nz);
-  const size_t nv = size_t(nx) * ny * nz;
-  std::vector<Dual> Vd(nv), Td(ea ? size_t(R) * 4 : 0);
+  const size_t nv = size_t(nx) * ny * nz * (model == 2 ? 4 : 1);
+  std::vector<Dual> Vd(nv), Td(model == 1 ? size_t(R) * 4 : 0);
   for (size_t k = 0; k < nv; ++k) Vd[k] = Dual(V[k], V_dir ? V_dir[k] : 0.0);
   for (size_t k = 0; k < Td.size(); ++k) Td[k] = Dual(tf[k], tf_dir ? tf_dir[k] : 0.0);
   Dual camd[12];
@@ -677,7 +739,9 @@ int oracle_render_dual(const double* V, const double* V_dir, int nx, int ny, int
     const int px = int(p % W), py = int(p / W);
     Ray<Dual> r = make_ray<Dual>(camd, px, py, W, H, g, dt);
     Dual Cc[3] = {Dual(0), Dual(0), Dual(0)}, Tr(1.0);
-    if (r.hit) march(g, Vd.data(), Td.data(), R, ea, r, dt, Cc, Tr);
+    if (r.hit)
+      march(g, Vd.data(), model == 2 ? static_cast<const Dual*>(nullptr) : Td.data(), R, ea, r,
+            dt, Cc, Tr);
     if (ea) {
       for (int ch = 0; ch < 3; ++ch) {
         if (image) image[q * 4 + ch] = Cc[ch].v;
@@ -759,9 +823,11 @@ int oracle_trace_ray(const double* V, int nx, int ny, int nz, const double* tf, 
 int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int R,
                  const double* cam, int W, int H, double step, int model,
                  const int32_t* pix, int64_t npix, double* face, double* knot, double* entry) {
-  const bool ea = model == 1;
-  if (!V || !cam || !face || !knot || (ea && !tf)) return -1;
-  if (!check_common(nx, ny, nz, R, ea, W, H, step)) return -2;
+  if (model < 0 || model > 2) return -3;
+  const bool ea = model >= 1;
+  if (model == 2) tf = nullptr;               // no TF knots in a colour volume
+  if (!V || !cam || !face || !knot || (model == 1 && !tf)) return -1;
+  if (!check_common(nx, ny, nz, R, model == 1, W, H, step)) return -2;
   const Grid g = make_grid(nx, ny, nz);
   const int64_t n = pix ? npix : int64_t(W) * H;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -776,7 +842,7 @@ int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int 
         const double k = std::round(qa);
         if (k >= 1.0 && k <= double(g.n[a] - 2)) fmin = std::min(fmin, std::fabs(qa - k));
       }
-      if (ea) {
+      if (ea && tf) {
         const double u = s.d * double(R - 1);
         const double k = std::round(u);
         if (k >= 0.0 && k <= double(R - 1)) kmin = std::min(kmin, std::fabs(u - k));

@@ -423,3 +423,89 @@ def test_alpha_form_inversion_degrades_when_nearly_opaque():
     # the T-form inversion stays accurate while T_N is representable
     it = oracle.adjoint(V, None, cam, W, W, step, AO, g, variant=oracle.INV_T, pix=pix)
     assert np.abs(it["dV"] - ref["dV"]).max() <= 1e-10 * scale
+
+
+# ---------------------------------------------------------------------------
+# pre-shaded colour volume (Sec. 5.4): (r, g, b, tau) per voxel, interpolated
+# per channel, same Beer-Lambert segment and blend
+# ---------------------------------------------------------------------------
+COLOR = oracle.COLOR
+
+
+def _shaded(V, tf2):
+    """Colour volume of a density grid under an affine (two-knot) TF: shading
+    commutes with trilinear interpolation when every density is in [0, 1]."""
+    a, b = tf2[0], tf2[1]
+    return a[None, None, None, :] + V[..., None] * (b - a)[None, None, None, :]
+
+
+def _color_problem(seed=31, n=(7, 6, 8), W=10, H=9):
+    rng = np.random.default_rng(seed)
+    V = rng.uniform(0.0, 1.0, n[::-1])
+    tf2 = np.array([[0.9, 0.2, 0.1, 0.5], [0.1, 0.7, 0.8, 6.0]])
+    cam = oracle.camera_from_sphere(35, 22, 2.3, 60, W, H)
+    step = 0.4 * 2 / (max(n) - 1)
+    return rng, V, tf2, cam, W, H, step
+
+
+def test_colour_volume_of_an_affine_tf_renders_like_the_tf():
+    rng, V, tf2, cam, W, H, step = _color_problem()
+    CV = _shaded(V, tf2)
+    a = oracle.render(V, tf2, cam, W, H, step, EA)
+    b = oracle.render(CV, None, cam, W, H, step, COLOR)
+    assert (a["nsamp"] > 0).sum() > 20
+    assert np.abs(a["image"] - b["image"]).max() < 1e-13
+    assert np.array_equal(a["nsamp"], b["nsamp"])
+    # the chain rule through the shading: dL/dV = sum_c dL/dCV_c * (b - a)_c,
+    # camera and step gradients identical
+    g = rng.normal(size=a["image"].shape)
+    ga = oracle.adjoint(V, tf2, cam, W, H, step, EA, g)
+    gb = oracle.adjoint(CV, None, cam, W, H, step, COLOR, g)
+    assert gb["dV"].shape == CV.shape
+    chained = (gb["dV"] * (tf2[1] - tf2[0])[None, None, None, :]).sum(-1)
+    assert np.abs(chained - ga["dV"]).max() <= 1e-12 * np.abs(ga["dV"]).max()
+    assert np.allclose(gb["dcam"], ga["dcam"], rtol=1e-11, atol=1e-14)
+    assert gb["dstep"] == pytest.approx(ga["dstep"], rel=1e-11)
+
+
+def test_colour_volume_homogeneous_slab_closed_form():
+    n, W = 9, 5
+    rgbt = np.array([0.3, 0.6, 0.9, 2.5])
+    CV = np.broadcast_to(rgbt, (n, n, n, 4)).copy()
+    cam = oracle.camera_from_sphere(0, 0, 2.5, 40, W, W)
+    step = 0.07
+    out = oracle.render(CV, None, cam, W, W, step, COLOR)
+    hit = out["nsamp"] > 0
+    N = out["nsamp"][hit]
+    a = 1.0 - np.exp(-N * step * rgbt[3])
+    assert np.allclose(out["image"][hit, 3], a, rtol=1e-13)
+    for c in range(3):
+        assert np.allclose(out["image"][hit, c], rgbt[c] * a, rtol=1e-13)
+
+
+def test_colour_volume_adjoint_variants_dual_numbers_and_finite_differences():
+    rng, V, tf2, cam, W, H, step = _color_problem(seed=32)
+    CV = rng.uniform(0.0, 1.0, V.shape + (4,)) * np.array([1.0, 1.0, 1.0, 8.0])
+    g = rng.normal(size=(W * H, 4))
+    ref = oracle.adjoint(CV, None, cam, W, H, step, COLOR, g, variant=oracle.TAPE)
+    for var in (oracle.INV_T, oracle.INV_ALPHA, oracle.CHECKPOINT, oracle.RESIDUAL):
+        got = oracle.adjoint(CV, None, cam, W, H, step, COLOR, g, variant=var)
+        assert np.abs(got["dV"] - ref["dV"]).max() <= 1e-11 * np.abs(ref["dV"]).max(), var
+        assert np.allclose(got["dcam"], ref["dcam"], rtol=1e-11, atol=1e-14), var
+    # dual numbers along a joint direction
+    Vd = rng.normal(size=CV.shape)
+    cd = rng.normal(size=12)
+    sd = float(rng.normal())
+    dual = oracle.render_dual(CV, None, cam, W, H, step, COLOR, Vd, None, cd, sd)
+    lhs = float((g * dual["image_dot"]).sum())
+    rhs = float((ref["dV"] * Vd).sum() + (ref["dcam"] * cd).sum() + ref["dstep"] * sd)
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+    # central finite differences
+
+    def loss(C, camx, sx):
+        return float((g * oracle.render(C, None, camx, W, H, sx, COLOR)["image"]).sum())
+
+    eps = 1e-6
+    fd = (loss(CV + eps * Vd, cam + eps * cd, step + eps * sd) -
+          loss(CV - eps * Vd, cam - eps * cd, step - eps * sd)) / (2 * eps)
+    assert fd == pytest.approx(rhs, rel=1e-6)
