@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define DDVR_ABI_VERSION 2
+#define DDVR_ABI_VERSION 3
 
 typedef enum {
   DDVR_OK = 0,
@@ -73,7 +73,24 @@ typedef enum {
 
 typedef enum { DDVR_F32 = 0, DDVR_F16 = 1, DDVR_BF16 = 2 } ddvr_dtype;
 
-typedef enum { DDVR_ABSORPTION = 0, DDVR_EMISSION_ABSORPTION = 1 } ddvr_model;
+/* Models.
+ *   ABSORPTION              tau(d) = d, image = alpha only.
+ *   EMISSION_ABSORPTION     scalar density through the transfer function.
+ *   COLOR                   pre-shaded colour volume: every vertex holds
+ *                           (r, g, b, tau), data -> [nz][ny][nx][4] of the
+ *                           volume's dtype (16-byte aligned for f32, 8-byte for
+ *                           f16/bf16), each channel interpolated trilinearly,
+ *                           then the emission-absorption segment and blend;
+ *                           no TF (tf may be NULL), d_volume is
+ *                           [nz][ny][nx][4] float32, images as
+ *                           emission-absorption.  Single views only (forward,
+ *                           adjoint, fused L2); batches and render_tangent
+ *                           return DDVR_ERR_UNSUPPORTED. */
+typedef enum {
+  DDVR_ABSORPTION = 0,
+  DDVR_EMISSION_ABSORPTION = 1,
+  DDVR_COLOR = 2
+} ddvr_model;
 
 /* Adjoint mode (low bits of `flags`).
  *   AUTO       absorption-only: the inversion of Sec. 4.4 carried out in closed
@@ -86,16 +103,25 @@ typedef enum { DDVR_ABSORPTION = 0, DDVR_EMISSION_ABSORPTION = 1 } ddvr_model;
  *              recovered T^(i) carries a relative error ~ 2^-24 / T_N, so rays
  *              with T_N < 2^-10 take the checkpoint fallback (needs workspace).
  *   CHECKPOINT segment checkpointing for every ray (the stored-state
- *              alternative; needs workspace). */
+ *              alternative; needs workspace).
+ *   RESIDUAL   colour model only: every ray runs its adjoint in forward order
+ *              with alpha_hat^(i+1) T^(i+1) = g_alpha T_N - (C_N - C^(i+1)).C_hat
+ *              (no division, no workspace).
+ * The colour model takes AUTO (T-form inversion; rays with T_N < 2^-100 use
+ * the RESIDUAL form in the same launch, no workspace), INVERT_T or RESIDUAL;
+ * the other models reject RESIDUAL, the colour model INVERT_ALPHA and
+ * CHECKPOINT (DDVR_ERR_UNSUPPORTED). */
 #define DDVR_ADJ_AUTO 0
 #define DDVR_ADJ_INVERT_T 1
 #define DDVR_ADJ_INVERT_ALPHA 2
 #define DDVR_ADJ_CHECKPOINT 3
+#define DDVR_ADJ_RESIDUAL 4
 #define DDVR_ADJ_MODE_MASK 0xF
 /* Launch strategy (bit flags, OR-ed into `flags`).
  *   PLAIN      one thread per ray with direct global gathers and global atomics
  *              for the density gradient (no LDS staging).  Same results up to
- *              float rounding; kept as the straightforward baseline. */
+ *              float rounding; kept as the straightforward baseline.  (The
+ *              colour model always gathers directly; it ignores PLAIN.) */
 #define DDVR_LAUNCH_PLAIN 0x10
 
 /* A scalar grid: data -> [nz][ny][nx] values of `dtype` (device). */

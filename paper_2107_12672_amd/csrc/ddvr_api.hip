@@ -111,7 +111,7 @@ int validate_volume(const ddvr_volume* v) {
 }
 
 int validate_tf(const ddvr_tf* tf, int model) {
-  if (model == DDVR_ABSORPTION) return DDVR_OK;
+  if (model == DDVR_ABSORPTION || model == DDVR_COLOR) return DDVR_OK;
   if (!tf) return fail(DDVR_ERR_NULL, "transfer function descriptor is NULL");
   if (!tf->rgba_tau) return fail(DDVR_ERR_NULL, "transfer function table is NULL");
   if (tf->R < 2 || tf->R > 4096) return fail(DDVR_ERR_SHAPE, "TF size R=%d not in [2, 4096]", tf->R);
@@ -119,8 +119,26 @@ int validate_tf(const ddvr_tf* tf, int model) {
 }
 
 int validate_model(int model) {
-  if (model != DDVR_ABSORPTION && model != DDVR_EMISSION_ABSORPTION)
+  if (model != DDVR_ABSORPTION && model != DDVR_EMISSION_ABSORPTION && model != DDVR_COLOR)
     return fail(DDVR_ERR_VALUE, "unknown model %d", model);
+  return DDVR_OK;
+}
+
+// The adjoint modes a model takes (flags already validated).
+int validate_mode(int model, int flags) {
+  const int mode = flags & DDVR_ADJ_MODE_MASK;
+  if (model == DDVR_COLOR && (mode == DDVR_ADJ_INVERT_ALPHA || mode == DDVR_ADJ_CHECKPOINT))
+    return fail(DDVR_ERR_UNSUPPORTED, "the colour model takes AUTO, INVERT_T or RESIDUAL");
+  if (model != DDVR_COLOR && mode == DDVR_ADJ_RESIDUAL)
+    return fail(DDVR_ERR_UNSUPPORTED, "the RESIDUAL adjoint mode is for the colour model");
+  return DDVR_OK;
+}
+
+// Colour volumes are read one vertex (4 values) per load.
+int validate_color_volume(const ddvr_volume* v) {
+  const uintptr_t align = v->dtype == DDVR_F32 ? 16 : 8;
+  if (reinterpret_cast<uintptr_t>(v->data) % align)
+    return fail(DDVR_ERR_VALUE, "colour volume data must be %d-byte aligned", (int)align);
   return DDVR_OK;
 }
 
@@ -222,6 +240,7 @@ FbLayout fallback_layout(int64_t rays, int64_t nmax_samples) {
 }
 
 bool needs_fallback(int model, int flags) {
+  if (model == DDVR_COLOR) return false;
   const int mode = flags & DDVR_ADJ_MODE_MASK;
   return mode == DDVR_ADJ_CHECKPOINT || mode == DDVR_ADJ_INVERT_ALPHA ||
          (model == DDVR_EMISSION_ABSORPTION && mode == DDVR_ADJ_AUTO);
@@ -229,7 +248,7 @@ bool needs_fallback(int model, int flags) {
 
 int validate_flags(int flags) {
   const int mode = flags & DDVR_ADJ_MODE_MASK;
-  if (mode > DDVR_ADJ_CHECKPOINT) return fail(DDVR_ERR_VALUE, "unknown adjoint mode %d", mode);
+  if (mode > DDVR_ADJ_RESIDUAL) return fail(DDVR_ERR_VALUE, "unknown adjoint mode %d", mode);
   if (flags & ~(DDVR_ADJ_MODE_MASK | DDVR_LAUNCH_PLAIN))
     return fail(DDVR_ERR_VALUE, "unknown flag bits 0x%x", flags);
   return DDVR_OK;
@@ -267,8 +286,10 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
                void* ws, size_t ws_bytes, int32_t* n_fb, double* loss_out, void* stream) {
   int rc;
   if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
-      (rc = validate_camera(cam)) || (rc = validate_step(vol, step)) || (rc = validate_flags(flags)))
+      (rc = validate_camera(cam)) || (rc = validate_step(vol, step)) || (rc = validate_flags(flags)) ||
+      (rc = validate_mode(model, flags)))
     return rc;
+  if (model == DDVR_COLOR && (rc = validate_color_volume(vol))) return rc;
   if (!image) return fail(DDVR_ERR_NULL, "image is NULL");
   if (pass == PASS_ADJ) {
     if (!trans) return fail(DDVR_ERR_NULL, "transmittance is NULL (the adjoint needs T_N)");
@@ -320,9 +341,19 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, flags);
 
+  hipError_t e;
+  if (model == DDVR_COLOR) {
+    // own kernel: 16x16-pixel tiles, direct gathers, no workspace
+    p.one.tiles_x = (cam->width + 15) / 16;
+    p.one.tiles_y = (cam->height + 15) / 16;
+    p.n_items = p.one.tiles_x * p.one.tiles_y;
+    e = (hipError_t)launch_color(p, pass, vol->dtype, stream);
+    if (e != hipSuccess) return hip_fail(e, "colour render launch");
+    if (n_fb) *n_fb = 0;
+    return DDVR_OK;
+  }
   const size_t lds = lds_bytes(p.lds_cap, p.lds_two, model, p.one.R);
   if ((rc = check_lds(lds))) return rc;
-  hipError_t e;
   if (fb && (e = (hipError_t)launch_zero_i32(p.fb_count, 1, stream)) != hipSuccess)
     return hip_fail(e, "zeroing the fallback queue");
   e = (hipError_t)launch_render(p, pass, model, vol->dtype, g_tuning.waves, p.n_items, lds,
@@ -516,6 +547,7 @@ int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
   if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
       (rc = validate_camera(cam)) || (rc = validate_step(vol, step_world)))
     return rc;
+  if (model == DDVR_COLOR) return fail(DDVR_ERR_UNSUPPORTED, "render_tangent: colour model");
   if (flags & ~DDVR_LAUNCH_PLAIN) return fail(DDVR_ERR_VALUE, "tangent flags: only DDVR_LAUNCH_PLAIN");
   if (!dirs) return fail(DDVR_ERR_NULL, "dirs is NULL");
   if (ndir < 1 || ndir > DDVR_MAX_DIRECTIONS)
@@ -615,7 +647,8 @@ int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, 
   int rc;
   if (!bytes) return fail(DDVR_ERR_NULL, "bytes is NULL");
   if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_camera(cam)) ||
-      (rc = validate_step(vol, step_world)) || (rc = validate_flags(flags)))
+      (rc = validate_step(vol, step_world)) || (rc = validate_flags(flags)) ||
+      (rc = validate_mode(model, flags)))
     return rc;
   *bytes = needs_fallback(model, flags)
                ? fallback_layout((int64_t)cam->width * cam->height, max_samples(vol, step_world)).bytes
@@ -657,7 +690,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
   if (!vols || !views) return fail(DDVR_ERR_NULL, "volumes or views is NULL");
   if (nvol <= 0 || nview <= 0 || nview >= 2048)
     return fail(DDVR_ERR_SHAPE, "need 1..2047 views and >= 1 volume");
-  if ((rc = validate_model(model)) || (rc = validate_flags(flags))) return rc;
+  if ((rc = validate_model(model)) || (rc = validate_flags(flags)) ||
+      (rc = validate_mode(model, flags)))
+    return rc;
+  if (model == DDVR_COLOR) return fail(DDVR_ERR_UNSUPPORTED, "batches: colour model");
   if (model == DDVR_EMISSION_ABSORPTION && (!tfs || ntf <= 0))
     return fail(DDVR_ERR_NULL, "emission-absorption batch without transfer functions");
   for (int i = 0; i < nvol; ++i)

@@ -1568,6 +1568,258 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// pre-shaded colour volume: (r, g, b, tau) at every vertex, each channel
+// interpolated trilinearly, then the same Beer-Lambert segment and
+// front-to-back blend as the emission-absorption model (Sec. 3.1; the volume
+// Sec. 5.4 reconstructs when it optimises colours directly).  No transfer
+// function; the density gradient becomes a 4-channel gradient.
+//
+// One ray per lane, 16x16-pixel tiles, direct gathers of the 8 corners (one
+// 16-byte or 8-byte load per corner), the 4x8 corner gradients of the ray's
+// current cell kept in registers and added to global memory when the ray
+// leaves the cell.  The adjoint recovers T^(i) by the T-form inversion
+// T^(i) = T^(i+1)/e_i (Sec. 4.4); a ray whose T_N is below 2^-100, where that
+// inversion loses float32 range, runs instead in forward order with the
+// identity alpha_hat^(i+1) T^(i+1) = g_alpha T_N - (C_N - C^(i+1)) . C_hat
+// (no division; C_N, T_N from the forward).
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <int DT> struct Vox4;
+template <> struct Vox4<DDVR_F32> {
+  static __device__ __forceinline__ float4 ld(const void* p, int64_t i) {
+    const f32x4 x = gmem<f32x4>(p)[i];
+    return make_float4(x.x, x.y, x.z, x.w);
+  }
+};
+template <> struct Vox4<DDVR_F16> {
+  static __device__ __forceinline__ float4 ld(const void* p, int64_t i) {
+    const u32x2 u = gmem<u32x2>(p)[i];
+    return make_float4(__half2float(__ushort_as_half((unsigned short)(u.x & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(u.x >> 16))),
+                       __half2float(__ushort_as_half((unsigned short)(u.y & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(u.y >> 16))));
+  }
+};
+template <> struct Vox4<DDVR_BF16> {
+  static __device__ __forceinline__ float4 ld(const void* p, int64_t i) {
+    const u32x2 u = gmem<u32x2>(p)[i];
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  }
+};
+
+// corner values v[ch][cx + 2cy + 4cz]; b = vertex index of corner 0
+template <int DT>
+__device__ __forceinline__ void fetch_color(const ViewDesc& vd, int64_t b, float (*v)[8]) {
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  const int64_t off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 x = Vox4<DT>::ld(vd.vol, b + off[k]);
+    v[0][k] = x.x; v[1][k] = x.y; v[2][k] = x.z; v[3][k] = x.w;
+  }
+}
+
+__device__ __forceinline__ int64_t cell_index(const ViewDesc& vd, const Cell& c) {
+  return ((int64_t)c.k[2] * vd.ny + c.k[1]) * vd.nx + c.k[0];
+}
+
+// per-ray colour adjoint state
+struct ColorAdj {
+  float Chat[3];
+  float ahat;       // inversion: alpha_hat^(i+1)
+  float Tn;         // inversion: T^(i+1)
+  float Cr[3], Tr;  // forward order: C^(i), T^(i)
+  float CN[3];      // forward order: C_N
+  float gaTN;       // forward order: g_alpha * T_N
+  int64_t gkey;     // vertex index of the current cell's corner 0, -1: none
+  float cg[4][8];   // gradient of the current cell's corners, per channel
+};
+
+__device__ __forceinline__ void color_flush(const ViewDesc& vd, ColorAdj& s) {
+  if (s.gkey < 0) return;
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  const int64_t off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+  float* g = vd.dV + 4 * s.gkey;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      gadd(g + 4 * off[k] + ch, s.cg[ch][k]);
+      s.cg[ch][k] = 0.0f;
+    }
+  s.gkey = -1;
+}
+
+template <int DT, int PASS, bool XH>
+__global__ __launch_bounds__(256) void k_color(const LaunchParams p) {
+  constexpr int NT = 256, TW = 16, TH = 16;
+  __shared__ float fscratch[64];
+  const ViewDesc& vd = p.one;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int lx, ly;
+  tile_pixel<4>(false, wid, lane, lx, ly);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool valid = px < vd.W && py < vd.H;
+  const int64_t pix = (int64_t)py * vd.W + px;
+  RayG r;
+  setup_ray(vd, px, py, valid, r);
+  const int N = r.N;
+
+  float CN[3] = {0.0f, 0.0f, 0.0f}, TN = 1.0f;
+  float gimg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (PASS != PASS_ADJ) {
+    // forward (Alg. 1 with per-channel interpolation in place of the TF)
+    for (float fi = 0.0f; fi < (float)N; fi += 1.0f) {
+      Cell c;
+      locate(r, fi, vd, c);
+      float v[4][8];
+      fetch_color<DT>(vd, cell_index(vd, c), v);
+      float q[4];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
+      const float e = __expf(-vd.step * q[3]);
+      const float w = __fmul_rn(TN, __fsub_rn(1.0f, e));
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) CN[ch] = fmaf(w, q[ch], CN[ch]);
+      TN *= e;
+    }
+    if (valid) {
+      reinterpret_cast<float4*>(vd.image)[pix] = make_float4(CN[0], CN[1], CN[2], 1.0f - TN);
+      if (vd.trans) vd.trans[pix] = TN;
+    }
+    if (PASS == PASS_FWD) return;
+    float loss = 0.0f;
+    if (valid) {
+      const float out[4] = {CN[0], CN[1], CN[2], 1.0f - TN};
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const float dlt = out[ch] - vd.target[pix * 4 + ch];
+        loss = fmaf(dlt, dlt, loss);
+        gimg[ch] = 2.0f * p.loss_scale * dlt;
+      }
+    }
+    if (p.loss_out) {
+      float l = loss * p.loss_scale;
+      wg_sum_n<NT>(&l, 1, fscratch);
+      if (threadIdx.x == 0 && l != 0.0f) atomicAdd(p.loss_out, (double)l);
+    }
+  } else if (valid) {
+    const float4 im = reinterpret_cast<const float4*>(vd.image)[pix];
+    CN[0] = im.x; CN[1] = im.y; CN[2] = im.z;
+    TN = vd.trans[pix];
+    const float4 g = reinterpret_cast<const float4*>(vd.d_image)[pix];
+    gimg[0] = g.x; gimg[1] = g.y; gimg[2] = g.z; gimg[3] = g.w;
+  }
+
+  // adjoint (Alg. 2)
+  int gmask = p.grad_mask;
+  if (!vd.dV) gmask &= ~GRAD_V;
+  if (!vd.dcam) gmask &= ~GRAD_CAM;
+  if (!vd.dstep) gmask &= ~GRAD_STEP;
+  const bool need_xhat = XH && (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
+  const int mode = p.flags & DDVR_ADJ_MODE_MASK;
+  const bool fwd_order =
+      mode == DDVR_ADJ_RESIDUAL || (mode == DDVR_ADJ_AUTO && !(TN >= kFallbackTmin));
+  ColorAdj s;
+  s.Chat[0] = gimg[0]; s.Chat[1] = gimg[1]; s.Chat[2] = gimg[2];
+  s.ahat = gimg[3];
+  s.Tn = TN;
+  s.Cr[0] = s.Cr[1] = s.Cr[2] = 0.0f;
+  s.Tr = 1.0f;
+  s.CN[0] = CN[0]; s.CN[1] = CN[1]; s.CN[2] = CN[2];
+  s.gaTN = gimg[3] * TN;
+  s.gkey = -1;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s.cg[ch][k] = 0.0f;
+  AdjState x;   // camera / step ray sums
+  x.xo_hat[0] = x.xo_hat[1] = x.xo_hat[2] = 0.0;
+  x.si[0] = x.si[1] = x.si[2] = 0.0;
+  x.dstep = 0.0;
+
+  const float lastf = (float)(N - 1);
+  for (float kf = 0.0f; kf < (float)N; kf += 1.0f) {
+    const float fi = fwd_order ? kf : lastf - kf;
+    Cell c;
+    locate(r, fi, vd, c);
+    const int64_t key = cell_index(vd, c);
+    float v[4][8];
+    fetch_color<DT>(vd, key, v);
+    float q[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
+    const float e = __expf(-vd.step * q[3]);
+    const float alpha = 1.0f - e;
+    const float rc = q[0] * s.Chat[0] + q[1] * s.Chat[1] + q[2] * s.Chat[2];
+    float Ti, ase;   // T^(i), and alpha_hat_i * e_i = T^(i+1) (alpha_hat^(i+1) + rgb . C_hat)
+    if (fwd_order) {
+      Ti = s.Tr;
+      const float w = __fmul_rn(Ti, __fsub_rn(1.0f, e));
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) s.Cr[ch] = fmaf(w, q[ch], s.Cr[ch]);
+      s.Tr = Ti * e;
+      const float res = s.gaTN - ((s.CN[0] - s.Cr[0]) * s.Chat[0] +
+                                  (s.CN[1] - s.Cr[1]) * s.Chat[1] +
+                                  (s.CN[2] - s.Cr[2]) * s.Chat[2]);
+      ase = fmaf(s.Tr, rc, res);
+    } else {
+      Ti = s.Tn * __builtin_amdgcn_rcpf(e);
+      ase = s.Tn * (s.ahat + rc);
+      s.ahat = fmaf(e, s.ahat, -alpha * rc);
+      s.Tn = Ti;
+    }
+    const float wgt = alpha * Ti;
+    const float g4[4] = {wgt * s.Chat[0], wgt * s.Chat[1], wgt * s.Chat[2], ase * vd.step};
+    if (XH) x.dstep += (double)(ase * q[3]);
+    if (gmask & GRAD_V) {
+      if (key != s.gkey) {
+        color_flush(vd, s);
+        s.gkey = key;
+      }
+      float w8[8];
+      trilerp_weights(c.f, w8);
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s.cg[ch][k] = fmaf(w8[k], g4[ch], s.cg[ch][k]);
+    }
+    if (need_xhat) {
+      float gp[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        float gd[3];
+        trilerp_grad(v[ch], c.f, gd);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gp[a] = fmaf(g4[ch], gd[a], gp[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float xh = gp[a] * vd.inv_h;
+        x.xo_hat[a] += (double)xh;
+        x.si[a] += (double)fi * (double)xh;
+      }
+    }
+  }
+  if (gmask & GRAD_V) color_flush(vd, s);
+  if (XH && (gmask & (GRAD_CAM | GRAD_STEP))) {
+    float cg[13];
+    camera_adjoint(vd, r, x, N > 0, cg);
+    wg_sum_n<NT>(cg, 13, fscratch);
+    if (threadIdx.x == 0) {
+      if (gmask & GRAD_CAM)
+        for (int k = 0; k < 12; ++k)
+          if (cg[k] != 0.0f) gadd(vd.dcam + k, cg[k]);
+      if ((gmask & GRAD_STEP) && cg[12] != 0.0f) gadd(vd.dstep, cg[12]);
+    }
+  }
+}
+
 // float32 master -> storage copy (round to nearest even), 4 values per lane
 __global__ void k_cast(const float* __restrict__ src, void* __restrict__ dst, int dtype,
                        int64_t n) {
@@ -1746,6 +1998,29 @@ int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void
       ? launch_fb1<DDVR_EMISSION_ABSORPTION>(p, dtype, fused, blocks, s)
       : launch_fb1<DDVR_ABSORPTION>(p, dtype, fused, blocks, s);
   return (int)e;
+}
+
+template <int DT>
+static hipError_t launch_color2(const LaunchParams& p, int pass, bool xh, int blocks,
+                                hipStream_t s) {
+  const dim3 g(blocks), b(256);
+  if (pass == PASS_FWD) hipLaunchKernelGGL((k_color<DT, PASS_FWD, false>), g, b, 0, s, p);
+  else if (pass == PASS_ADJ && xh) hipLaunchKernelGGL((k_color<DT, PASS_ADJ, true>), g, b, 0, s, p);
+  else if (pass == PASS_ADJ) hipLaunchKernelGGL((k_color<DT, PASS_ADJ, false>), g, b, 0, s, p);
+  else if (xh) hipLaunchKernelGGL((k_color<DT, PASS_FUSED, true>), g, b, 0, s, p);
+  else hipLaunchKernelGGL((k_color<DT, PASS_FUSED, false>), g, b, 0, s, p);
+  return hipGetLastError();
+}
+
+int launch_color(const LaunchParams& p, int pass, int dtype, void* stream) {
+  if (p.n_items <= 0) return 0;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool xh = (p.grad_mask & (GRAD_CAM | GRAD_STEP)) != 0;
+  switch (dtype) {
+    case DDVR_F16: return (int)launch_color2<DDVR_F16>(p, pass, xh, p.n_items, s);
+    case DDVR_BF16: return (int)launch_color2<DDVR_BF16>(p, pass, xh, p.n_items, s);
+    default: return (int)launch_color2<DDVR_F32>(p, pass, xh, p.n_items, s);
+  }
 }
 
 int launch_zero_i32(int32_t* ptr, int n, void* stream) {

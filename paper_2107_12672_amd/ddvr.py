@@ -19,8 +19,8 @@ OK = 0
 ERR_NULL, ERR_SHAPE, ERR_DTYPE, ERR_VALUE, ERR_HIP, ERR_UNSUPPORTED, ERR_WORKSPACE = \
     -1, -2, -3, -4, -5, -6, -7
 F32, F16, BF16 = 0, 1, 2
-ABSORPTION, EMISSION_ABSORPTION = 0, 1
-ADJ_AUTO, ADJ_INVERT_T, ADJ_INVERT_ALPHA, ADJ_CHECKPOINT = 0, 1, 2, 3
+ABSORPTION, EMISSION_ABSORPTION, COLOR = 0, 1, 2
+ADJ_AUTO, ADJ_INVERT_T, ADJ_INVERT_ALPHA, ADJ_CHECKPOINT, ADJ_RESIDUAL = 0, 1, 2, 3, 4
 LAUNCH_PLAIN = 0x10
 PASS_FORWARD, PASS_ADJOINT, PASS_FUSED = 0, 1, 2
 
@@ -152,9 +152,10 @@ def dtype_code(t) -> int:
 
 
 def volume_desc(vol) -> Volume:
-    """Descriptor of a contiguous [nz][ny][nx] device tensor."""
-    assert vol.is_contiguous() and vol.dim() == 3
-    nz, ny, nx = vol.shape
+    """Descriptor of a contiguous [nz][ny][nx] device tensor, or of a colour
+    volume [nz][ny][nx][4] (r, g, b, tau per vertex)."""
+    assert vol.is_contiguous() and (vol.dim() == 3 or (vol.dim() == 4 and vol.shape[3] == 4))
+    nz, ny, nx = vol.shape[:3]
     return Volume(vol.data_ptr(), dtype_code(vol), nx, ny, nz)
 
 

@@ -193,8 +193,8 @@ class View:
 class Workload:
     """One seeded problem instance (inputs only)."""
     name: str
-    model: str                      # "ao" or "ea"
-    volume: np.ndarray              # float32 [nz][ny][nx]
+    model: str                      # "ao", "ea" or "color"
+    volume: np.ndarray              # float32 [nz][ny][nx] (colour: [nz][ny][nx][4])
     storage: str                    # "f32" | "f16" | "bf16"
     tf: Optional[np.ndarray]        # float32 [R][4] or None for AO
     views: List[View]
@@ -208,7 +208,7 @@ class Workload:
 
     @property
     def step_world(self) -> float:
-        n = max(self.volume.shape)
+        n = max(self.volume.shape[:3])
         return float(self.step_vox * 2.0 / (n - 1))
 
 
@@ -289,6 +289,37 @@ def make_c5(n: int = 512, n_views: int = 32, image: int = 1024, R: int = 32,
     views = [View(y, p, 2.5, image, image) for (y, p) in fibonacci_sphere(n_views)]
     return Workload(f"C5: EA {n}^3 f16 sparse noise, R={R}, {n_views} views {image}^2, "
                     f"step {step_vox} vox", "ea", vol, "f16", tf, views, step_vox)
+
+
+def color_volume(shape_zyx, rng: np.random.Generator, tau_max: float, n_blobs: int = 6,
+                 noise: float = 0.02) -> np.ndarray:
+    """[nz][ny][nx][4] pre-shaded colour volume (r, g, b, tau) per vertex:
+    three independent blob fields clipped to [0, 1] for the emission and a
+    fourth, scaled to [0, tau_max], for the extinction (the four-channel
+    volume Sec. 5.4 reconstructs in place of a density + TF)."""
+    out = np.empty(tuple(shape_zyx) + (4,), dtype=np.float32)
+    for ch in range(4):
+        f = blob_volume(shape_zyx, n_blobs, rng, sigma_world=(0.1, 0.3), amplitude=0.6,
+                        noise=noise)
+        out[..., ch] = np.clip(f, 0.0, 1.0) * (tau_max if ch == 3 else 1.0)
+    return out
+
+
+# Extinction scale of the colour-volume workload: median transmittance of the
+# rays that hit the grid in [0.1, 0.5] at 256^3 (frozen constant).
+COLOR_TAU_MAX = 48.0
+
+
+def make_color(n: int = 256, n_views: int = 64, image: int = 512,
+               step_vox: float = 0.2, storage: str = "bf16") -> Workload:
+    """Colour-volume reconstruction (Sec. 5.4 first stage): the C3 setting
+    (grid, views, step) with a four-channel volume; the volume is a
+    mid-optimisation state, the targets are drawn per view by the caller."""
+    rng = rng_for(6, 0)
+    vol = color_volume((n, n, n), rng, COLOR_TAU_MAX)
+    views = [View(y, p, 2.5, image, image) for (y, p) in fibonacci_sphere(n_views)]
+    return Workload(f"colour volume {n}^3x4 {storage}, {n_views} views {image}^2, "
+                    f"step {step_vox} vox", "color", vol, storage, None, views, step_vox)
 
 
 def image_target(rng: np.random.Generator, n_pix: int, channels: int) -> np.ndarray:

@@ -51,8 +51,8 @@ def ddvr_mod():
 
 @dataclass
 class Problem:
-    model: int                 # 0 AO, 1 EA
-    volume: np.ndarray         # float32 [nz][ny][nx] (master)
+    model: int                 # 0 AO, 1 EA, 2 colour volume
+    volume: np.ndarray         # float32 [nz][ny][nx] (colour: [nz][ny][nx][4]), master
     storage: str               # f32 / f16 / bf16
     tf: Optional[np.ndarray]   # float32 [R][4]
     yaw: float
@@ -65,7 +65,7 @@ class Problem:
 
     @property
     def C(self):
-        return 4 if self.model == 1 else 1
+        return 1 if self.model == 0 else 4
 
 
 def storage_dtype(storage):
@@ -159,7 +159,7 @@ def kink_mask(p: Problem, pix=None) -> np.ndarray:
     V = dequantized(p)
     face, knot, entry = oracle.kinks(V, p.tf, oracle_camera(p), p.W, p.H, p.step, p.model,
                                      pix=pix, with_entry=True)
-    nmax = max(p.volume.shape)
+    nmax = max(p.volume.shape[:3])
     # the entry point x_o = e + t0*omega inherits direction errors amplified by
     # t0/|omega_a| (entry plane a): grazing entries move all samples further
     face_tol = 1e-6 * nmax + 1e-4 + 4e-7 * 0.5 * (nmax - 1) * entry

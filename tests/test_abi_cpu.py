@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     d = _ddvr()
-    assert d.abi_version() == 2
+    assert d.abi_version() == 3
     assert isinstance(d.last_error(), str)
 
 
@@ -226,3 +226,44 @@ def test_camera_sphere_tangents_match_oracle_jacobian():
     back = d.camera_grad_to_sphere(math.radians(40), math.radians(25), 2.7, math.radians(55), 96,
                                    64, g)
     assert np.allclose(back, got @ g, rtol=1e-5, atol=1e-5)
+
+
+def test_colour_model_validation():
+    """The colour-volume model: its adjoint modes, alignment of its 4-channel
+    data, no workspace, and the entry points that do not take it."""
+    d = _ddvr()
+    L = d.lib()
+    vol, tf, cam = _descs(d)
+    B = ctypes.byref
+    C = d.COLOR
+    g = d.Grads(0x5000, None, None, None)
+    adj = L.ddvr_render_adjoint
+    for mode in (d.ADJ_INVERT_ALPHA, d.ADJ_CHECKPOINT):
+        assert adj(B(vol), None, B(cam), 0.1, C, 0x3000, 0x3100, 0x4000, B(g), mode, None, 0,
+                   None, None) == d.ERR_UNSUPPORTED
+    # the residual form is the colour model's own
+    assert adj(B(vol), B(tf), B(cam), 0.1, 1, 0x3000, 0x3100, 0x4000, B(g), d.ADJ_RESIDUAL, None,
+               0, None, None) == d.ERR_UNSUPPORTED
+    assert adj(B(vol), None, B(cam), 0.1, C, 0x3000, 0x3100, 0x4000, B(g), 5, None, 0, None,
+               None) == d.ERR_VALUE
+    # 4 values per load: f32 data 16-byte aligned, f16 / bf16 8-byte aligned
+    fwd = L.ddvr_render_forward
+    assert fwd(B(d.Volume(0x1008, d.F32, 8, 8, 8)), None, B(cam), 0.1, C, 0x3000, None, 0,
+               None) == d.ERR_VALUE
+    assert "aligned" in d.last_error()
+    assert fwd(B(d.Volume(0x1004, d.BF16, 8, 8, 8)), None, B(cam), 0.1, C, 0x3000, None, 0,
+               None) == d.ERR_VALUE
+    n = ctypes.c_size_t(7)
+    for mode in (d.ADJ_AUTO, d.ADJ_INVERT_T, d.ADJ_RESIDUAL):
+        assert L.ddvr_adjoint_workspace_size(B(vol), B(cam), 0.05, C, mode, B(n)) == 0
+        assert n.value == 0
+    assert L.ddvr_adjoint_workspace_size(B(vol), B(cam), 0.05, C, d.ADJ_CHECKPOINT,
+                                         B(n)) == d.ERR_UNSUPPORTED
+    dirs = (d.Direction * 1)()
+    assert L.ddvr_render_tangent(B(vol), None, B(cam), 0.1, C, dirs, 1, 0x3000, None, None, None,
+                                 0, None) == d.ERR_UNSUPPORTED
+    h = ctypes.c_void_p()
+    views = (d.View * 1)(d.View(0, -1, cam, 0.1, 0x3000, None, None, None, None, None))
+    vols = (d.Volume * 1)(vol)
+    assert L.ddvr_batch_create(vols, 1, None, 0, views, 1, C, 0, None, None, None,
+                               B(h)) == d.ERR_UNSUPPORTED
