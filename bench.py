@@ -170,7 +170,10 @@ def secondary(args):
           1024x1024, fused L2 with density, TF and step gradients: T-form
           inversion (AUTO) and segment checkpointing (CHECKPOINT);
       viewpoint  the C5 grid and views, gradient w.r.t. (yaw, pitch, dist) of
-          every view by forward-mode (delayed / immediate) and by the adjoint."""
+          every view by forward-mode (delayed / immediate) and by the adjoint;
+      color  pre-shaded colour volume 256^3 x (r, g, b, tau) bf16, the C3 views
+          (64 at 512x512, step 0.2 voxel), fused L2 with the colour-volume
+          gradient, one launch per view."""
     import numpy as np
     import torch
     import synth
@@ -244,6 +247,51 @@ def secondary(args):
                                "tuning": d.get_tuning()}})
         if "checkpoint" in res:
             out["checkpoint"] = res["checkpoint"]
+    elif args.workload == "color":
+        w = synth.make_color()
+        vol = stored(w.volume, w.storage)
+        cams = cams_of(w.views)
+        nv = len(cams)
+        W = H = w.views[0].width
+        rng = synth.rng_for(9, 6)
+        targets = torch.from_numpy(rng.uniform(0.0, 1.0, (nv, H, W, 4)).astype(np.float32)).to(dev)
+        images = torch.empty_like(targets)
+        trans = torch.empty((nv, H, W), device=dev)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        scale = 1.0 / images.numel()
+        grads = d.grads_desc(dV)
+        # samples per step: the sample count depends only on the geometry, so
+        # an absorption-only batch over a scalar grid of the same size counts it
+        geo = torch.empty(w.volume.shape[:3], dtype=torch.bfloat16, device=dev)
+        cb = d.Batch([geo], None, [d.make_view(0, cams[i], w.step_world, images[i, :, :, 0])
+                                   for i in range(nv)], d.ABSORPTION)
+        S = cb.sample_count()
+        cb.close()
+        del geo
+
+        def step():
+            for i in range(nv):
+                d.render_fused_l2(vol, None, cams[i], w.step_world, d.COLOR, targets[i], scale,
+                                  images[i], trans[i], grads, loss_out=loss)
+
+        res = {}
+        for mode, flags in (("auto", d.ADJ_AUTO), ("residual", d.ADJ_RESIDUAL)):
+            fn = step if flags == 0 else (lambda: [d.render_fused_l2(
+                vol, None, cams[i], w.step_world, d.COLOR, targets[i], scale, images[i], trans[i],
+                grads, flags=flags, loss_out=loss) for i in range(nv)])
+            ms = _timed(fn, args.steps, args.warmup, stream, torch)
+            res[mode] = {"ms_per_step": ms, "value": S / (ms * 1e-3)}
+            log(f"color {mode}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+        fwd_ms = _timed(lambda: [d.render_forward(vol, None, cams[i], w.step_world, d.COLOR,
+                                                  images[i], trans[i]) for i in range(nv)],
+                        args.steps, args.warmup, stream, torch)
+        log(f"color forward only: {fwd_ms:.3f} ms")
+        out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
+                    "value": res["auto"]["value"], "ms_per_step": res["auto"]["ms_per_step"],
+                    "config": {"workload": w.name + ", fused L2, colour-volume gradient",
+                               "samples_per_step": S},
+                    "residual_form": res["residual"], "forward_ms": fwd_ms})
     elif args.workload == "viewpoint":
         # viewpoint gradients (yaw, pitch, dist) of every view of the C5 grid:
         # forward-delayed (one tangent pass per view), forward-immediate
@@ -348,7 +396,7 @@ def main():
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
     ap.add_argument("--step-vox", type=float, default=0.2)
-    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint"),
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint", "color"),
                     help="c3 (default) is the headline tomography step; the others print "
                          "their own line")
     ap.add_argument("--burn-in", type=int, default=4,

@@ -343,11 +343,17 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
 
   hipError_t e;
   if (model == DDVR_COLOR) {
-    // own kernel: 16x16-pixel tiles, direct gathers, no workspace
+    // own kernels, 16x16-pixel tiles, no workspace: the slab-synchronous
+    // route (the tuning's brick bytes hold lds_cap/4 vertices of 4 channels)
+    // or, with PLAIN or the RESIDUAL mode, the direct route
     p.one.tiles_x = (cam->width + 15) / 16;
     p.one.tiles_y = (cam->height + 15) / 16;
     p.n_items = p.one.tiles_x * p.one.tiles_y;
-    e = (hipError_t)launch_color(p, pass, vol->dtype, stream);
+    const int slab = cap > 0 && (flags & DDVR_ADJ_MODE_MASK) != DDVR_ADJ_RESIDUAL;
+    p.lds_cap = slab ? std::max(cap / 4, 16) : 0;
+    const size_t lds = slab ? (size_t)p.lds_cap * 4 * sizeof(float) + 64 * sizeof(int) : 0;
+    if (slab && (rc = check_lds(lds))) return rc;
+    e = (hipError_t)launch_color(p, pass, vol->dtype, slab, lds, stream);
     if (e != hipSuccess) return hip_fail(e, "colour render launch");
     if (n_fb) *n_fb = 0;
     return DDVR_OK;

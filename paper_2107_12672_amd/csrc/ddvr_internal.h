@@ -89,8 +89,11 @@ int launch_fallback(const LaunchParams& p, int model, int dtype, int fused, void
 int launch_zero_i32(int32_t* ptr, int n, void* stream);
 int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, size_t lds_bytes,
                    void* stream);
-// pre-shaded colour volume (one tile of 16x16 pixels per workgroup, p.n_items tiles)
-int launch_color(const LaunchParams& p, int pass, int dtype, void* stream);
+// pre-shaded colour volume (one tile of 16x16 pixels per workgroup, p.n_items tiles):
+// slab = 1 the slab-synchronous route (p.lds_cap vertices per brick, lds_bytes of
+// dynamic LDS), 0 the direct route (one ray per lane, global atomics)
+int launch_color(const LaunchParams& p, int pass, int dtype, int slab, size_t lds_bytes,
+                 void* stream);
 int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
 
 constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persistent launch

@@ -409,11 +409,10 @@ __device__ __forceinline__ float wg_sum_all(float x, float* scratch) {
 
 // Bounding box of the cells of every sample in the slab [lo, hi).
 // Returns false if no ray has a sample in it.
+// Bounding box of the cells of every lane's samples [a, b).
 template <int NT>
-__device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, int off, int N,
-                                           int lo, int hi, int* iscratch, Brick& br) {
-  int a, b;
-  slab_range(lo, hi, off, N, a, b);
+__device__ __forceinline__ bool range_brick(const ViewDesc& vd, const RayG& r, int a, int b,
+                                            int* iscratch, Brick& br) {
   int v[6];
   if (a < b) {
     Cell c0, c1;
@@ -441,6 +440,14 @@ __device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, in
   br.inv_bx = 1.0f / (float)bx;
   br.inv_bxy = 1.0f / (float)br.bxy;
   return true;
+}
+
+template <int NT>
+__device__ __forceinline__ bool slab_brick(const ViewDesc& vd, const RayG& r, int off, int N,
+                                           int lo, int hi, int* iscratch, Brick& br) {
+  int a, b;
+  slab_range(lo, hi, off, N, a, b);
+  return range_brick<NT>(vd, r, a, b, iscratch, br);
 }
 
 // Choose the next slab of the march: starting at `pos` and running forward
@@ -1626,6 +1633,64 @@ __device__ __forceinline__ int64_t cell_index(const ViewDesc& vd, const Cell& c)
   return ((int64_t)c.k[2] * vd.ny + c.k[1]) * vd.nx + c.k[0];
 }
 
+// Start of the slab-synchronous route's inversion.  A ray whose T_N is at least 2^-100 is inverted
+// from its last sample.  Any other ray is inverted from sample K-1, K one
+// past the last sample entered with T^(i) >= 2^-100: the samples after it
+// carry T^(i) < 2^-100, and with non-negative extinction their share of every
+// gradient is below 2^-100 of the upstream gradient.  Sample K-1 is adjoined
+// with P = T^(i+1) alpha_hat^(i+1) = g_alpha T_N - (C_N - C^(i+1)) . C_hat
+// (no division by the possibly underflowed T^(K)); alpha_hat^(K-1) =
+// P^(K-1) / T^(K-1) then starts the T-form inversion with T^(K-1) >= 2^-100.
+// ---------------------------------------------------------------------------
+struct ColorCut {
+  int K;        // samples the adjoint covers
+  float TK1;    // T^(K-1)
+  float CK[3];  // C^(K)
+  // factors of the fixed-point bound (see k_color_lds): max |w_i|,
+  // sum |w_i| m_i, max T^(i+1), max m_i; w_i = alpha_i T^(i), m_i = max |rgb_i|
+  float maxw, swm, tmax, mmax;
+};
+
+template <int DT, bool TRACK>
+__device__ __forceinline__ void color_march_fwd(const ViewDesc& vd, const RayG& r, int n,
+                                                float* C, float& T, ColorCut& cut) {
+  C[0] = C[1] = C[2] = 0.0f;
+  T = 1.0f;
+  cut.K = 0;
+  cut.TK1 = 1.0f;
+  cut.CK[0] = cut.CK[1] = cut.CK[2] = 0.0f;
+  cut.maxw = cut.swm = cut.tmax = cut.mmax = 0.0f;
+  for (float fi = 0.0f; fi < (float)n; fi += 1.0f) {
+    Cell c;
+    locate(r, fi, vd, c);
+    float v[4][8];
+    fetch_color<DT>(vd, cell_index(vd, c), v);
+    float q[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
+    const float e = __expf(-vd.step * q[3]);
+    const float Ti = T;
+    // explicitly rounded (no contraction): every route renders the same image
+    const float w = __fmul_rn(T, __fsub_rn(1.0f, e));
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, q[ch], C[ch]);
+    T *= e;
+    if (TRACK) {
+      if (Ti >= kFallbackTmin) {
+        cut.K = (int)fi + 1;
+        cut.TK1 = Ti;
+        cut.CK[0] = C[0]; cut.CK[1] = C[1]; cut.CK[2] = C[2];
+      }
+      const float m = fmaxf(fabsf(q[0]), fmaxf(fabsf(q[1]), fabsf(q[2])));
+      const float aw = fabsf(w);
+      cut.maxw = fmaxf(cut.maxw, aw);
+      cut.swm = fmaf(aw, m, cut.swm);
+      cut.tmax = fmaxf(cut.tmax, T);
+      cut.mmax = fmaxf(cut.mmax, m);
+    }
+  }
+}
+
 // per-ray colour adjoint state
 struct ColorAdj {
   float Chat[3];
@@ -1674,20 +1739,8 @@ __global__ __launch_bounds__(256) void k_color(const LaunchParams p) {
   float gimg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if (PASS != PASS_ADJ) {
     // forward (Alg. 1 with per-channel interpolation in place of the TF)
-    for (float fi = 0.0f; fi < (float)N; fi += 1.0f) {
-      Cell c;
-      locate(r, fi, vd, c);
-      float v[4][8];
-      fetch_color<DT>(vd, cell_index(vd, c), v);
-      float q[4];
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
-      const float e = __expf(-vd.step * q[3]);
-      const float w = __fmul_rn(TN, __fsub_rn(1.0f, e));
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) CN[ch] = fmaf(w, q[ch], CN[ch]);
-      TN *= e;
-    }
+    ColorCut cut;
+    color_march_fwd<DT, false>(vd, r, N, CN, TN, cut);
     if (valid) {
       reinterpret_cast<float4*>(vd.image)[pix] = make_float4(CN[0], CN[1], CN[2], 1.0f - TN);
       if (vd.trans) vd.trans[pix] = TN;
@@ -1810,6 +1863,410 @@ __global__ __launch_bounds__(256) void k_color(const LaunchParams p) {
   if (XH && (gmask & (GRAD_CAM | GRAD_STEP))) {
     float cg[13];
     camera_adjoint(vd, r, x, N > 0, cg);
+    wg_sum_n<NT>(cg, 13, fscratch);
+    if (threadIdx.x == 0) {
+      if (gmask & GRAD_CAM)
+        for (int k = 0; k < 12; ++k)
+          if (cg[k] != 0.0f) gadd(vd.dcam + k, cg[k]);
+      if ((gmask & GRAD_STEP) && cg[12] != 0.0f) gadd(vd.dstep, cg[12]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// colour volume, slab-synchronous route: the tile's adjoint marches slab by
+// slab back to front (as the scalar kernel does) and accumulates the
+// 4-channel gradient of each slab's brick of vertices in LDS, flushed with
+// one global atomic per touched vertex and channel.  The grid values are
+// gathered directly (the forward's 8 corner loads per sample, from L2).
+// ---------------------------------------------------------------------------
+// per-ray state of the slab-synchronous colour adjoint
+struct ColorAdjL {
+  float Chat[3];
+  float ahat;       // alpha_hat^(i+1)
+  float Tn;         // T^(i+1)
+  float P;          // first sample of a cut ray: T^(K) alpha_hat^(K)
+  float fK1;        // index of that sample (-1: the ray is not cut)
+  float TK1;        // T^(K-1)
+  int ckey;         // LDS byte offset of the current cell's corner 0 (-1: none)
+  int64_t gkey;     // vertex index of the current cell's corner 0 (direct slabs)
+  float cg[4][8];   // gradient of the current cell's corners, per channel
+};
+
+// Add the registered cell gradient to the LDS brick ([vertex][4] floats) or
+// to global memory, then clear it.
+// FIX: the brick holds 32-bit fixed point, channel ch scaled by qs[ch] (LDS
+// integer atomics run at the rate of plain stores, float ones serialise).
+template <bool LDS, bool FIX>
+__device__ __forceinline__ void color_cell_flush(const ViewDesc& vd, const Brick& br, float* acc,
+                                                 ColorAdjL& s, const float* qs) {
+  if (LDS) {
+    if (s.ckey < 0) return;
+    char* p0 = reinterpret_cast<char*>(acc) + s.ckey;
+    const int sy = 4 * br.bx4, sz = 4 * br.bxy4;
+    const int off[8] = {0, 16, sy, sy + 16, sz, sz + 16, sz + sy, sz + sy + 16};
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        if (FIX)
+          atomicAdd(reinterpret_cast<int*>(p0 + off[k]) + ch, round_i32(s.cg[ch][k] * qs[ch]));
+        else
+          atomicAdd(reinterpret_cast<float*>(p0 + off[k]) + ch, s.cg[ch][k]);
+        s.cg[ch][k] = 0.0f;
+      }
+    s.ckey = -1;
+  } else {
+    if (s.gkey < 0) return;
+    const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+    const int64_t off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+    float* g = vd.dV + 4 * s.gkey;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        gadd(g + 4 * off[k] + ch, s.cg[ch][k]);
+        s.cg[ch][k] = 0.0f;
+      }
+    s.gkey = -1;
+  }
+}
+
+template <int DT, bool LDS, bool FIX, bool XH>
+__device__ __forceinline__ void color_adj_sample(const ViewDesc& vd, const RayG& r, float fi,
+                                                 float* acc, const Brick& br, int gmask,
+                                                 bool need_xhat, ColorAdjL& s, AdjState& x,
+                                                 const float* qs) {
+  Cell c;
+  locate(r, fi, vd, c);
+  const int64_t vidx = cell_index(vd, c);
+  float v[4][8];
+  fetch_color<DT>(vd, vidx, v);
+  float q[4];
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
+  const float e = __expf(-vd.step * q[3]);
+  const float alpha = 1.0f - e;
+  const float rc = q[0] * s.Chat[0] + q[1] * s.Chat[1] + q[2] * s.Chat[2];
+  float Ti, ase;   // T^(i), and e_i times the adjoint of alpha_i
+  if (fi == s.fK1) {
+    Ti = s.TK1;
+    ase = fmaf(s.TK1 * e, rc, s.P);
+    s.ahat = (s.P - alpha * Ti * rc) / Ti;
+  } else {
+    Ti = s.Tn * __builtin_amdgcn_rcpf(e);
+    ase = s.Tn * (s.ahat + rc);
+    s.ahat = fmaf(e, s.ahat, -alpha * rc);
+  }
+  s.Tn = Ti;
+  const float wgt = alpha * Ti;
+  const float g4[4] = {wgt * s.Chat[0], wgt * s.Chat[1], wgt * s.Chat[2], ase * vd.step};
+  if (XH) x.dstep += (double)(ase * q[3]);
+  if (gmask & GRAD_V) {
+    if (LDS) {
+      const int key = 4 * brick_base(br, c);
+      if (key != s.ckey) {
+        color_cell_flush<true, FIX>(vd, br, acc, s, qs);
+        s.ckey = key;
+      }
+    } else if (vidx != s.gkey) {
+      color_cell_flush<false, false>(vd, br, acc, s, qs);
+      s.gkey = vidx;
+    }
+    float w8[8];
+    trilerp_weights(c.f, w8);
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s.cg[ch][k] = fmaf(w8[k], g4[ch], s.cg[ch][k]);
+  }
+  if (need_xhat) {
+    float gp[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      float gd[3];
+      trilerp_grad(v[ch], c.f, gd);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gp[a] = fmaf(g4[ch], gd[a], gp[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float xh = gp[a] * vd.inv_h;
+      x.xo_hat[a] += (double)xh;
+      x.si[a] += (double)fi * (double)xh;
+    }
+  }
+}
+
+// Zero the brick's 4-channel accumulator / add it to the gradient in global
+// memory (one atomic per touched vertex and channel).
+template <int NT>
+__device__ __forceinline__ void color_brick_zero(const Brick& br, float* acc) {
+  float4* a4 = reinterpret_cast<float4*>(acc);
+  for (int idx = threadIdx.x; idx < br.size; idx += NT) a4[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+template <int NT, bool FIX>
+__device__ __forceinline__ void color_brick_flush(const ViewDesc& vd, const Brick& br,
+                                                  const float* acc, const float* inv_qs) {
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  float* const org = vd.dV + 4 * (br.z0 * sz + br.y0 * sy + br.x0);
+  const bool narrow = brick_narrow(br, sz);
+  const float4* a4 = reinterpret_cast<const float4*>(acc);
+  const int4* i4 = reinterpret_cast<const int4*>(acc);
+  for (int idx = threadIdx.x; idx < br.size; idx += NT) {
+    float4 g;
+    if (FIX) {
+      const int4 u = i4[idx];
+      g = make_float4((float)u.x * inv_qs[0], (float)u.y * inv_qs[1], (float)u.z * inv_qs[2],
+                      (float)u.w * inv_qs[3]);
+    } else {
+      g = a4[idx];
+    }
+    if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f && g.w == 0.0f) continue;
+    float* dst = org + 4 * (narrow ? brick_goff<true>(br, idx, sy, sz)
+                                   : brick_goff<false>(br, idx, sy, sz));
+    if (g.x != 0.0f) gadd(dst, g.x);
+    if (g.y != 0.0f) gadd(dst + 1, g.y);
+    if (g.z != 0.0f) gadd(dst + 2, g.z);
+    if (g.w != 0.0f) gadd(dst + 3, g.w);
+  }
+}
+
+// The back-to-front slab march of a tile's colour adjoint.
+template <int DT, bool FIX, bool XH>
+__device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const RayG& r, int tx,
+                                                    int ty, int Nadj, float* acc, int* iscratch,
+                                                    int vcap, int gmask,
+                                                    bool need_xhat, bool want_dv, ColorAdjL& s,
+                                                    AdjState& x, const float* qs,
+                                                    const float* inv_qs) {
+  constexpr int NT = 256, TW = 16, TH = 16;
+  // Slabs between planes q_ax = const of the grid axis ax closest to the
+  // tile's centre ray, in march order (t = sgn * q_ax grows along every ray):
+  // an axis-aligned slab has a tight bounding box at any view angle, where a
+  // shell of constant distance from the eye cut obliquely through the grid
+  // spans a box many times its volume (the 4-channel brick holds a quarter
+  // of the scalar brick's vertices).  Each ray's samples between two planes
+  // form one index range; consecutive slabs share their boundary plane, so
+  // the ranges partition the ray.
+  int ax;
+  float sgn;
+  {
+    const float uc = 2.0f * ((float)(tx * TW) + 0.5f * TW) / (float)vd.W - 1.0f;
+    const float vc = 1.0f - 2.0f * ((float)(ty * TH) + 0.5f * TH) / (float)vd.H;
+    float wc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wc[k] = vd.fwd[k] + uc * vd.right[k] + vc * vd.up[k];
+    ax = fabsf(wc[0]) >= fabsf(wc[1]) ? (fabsf(wc[0]) >= fabsf(wc[2]) ? 0 : 2)
+                                       : (fabsf(wc[1]) >= fabsf(wc[2]) ? 1 : 2);
+    sgn = wc[ax] >= 0.0f ? 1.0f : -1.0f;
+  }
+  const float t0 = sgn * r.qo[ax], dt_ax = sgn * r.dq[ax];
+  int tlo, thi;
+  {
+    // every ray with work must advance along the axis (else the tile runs
+    // its rays whole on the direct path)
+    const bool bad = Nadj > 0 && !(dt_ax > 0.0f);
+    int v[3] = {Nadj > 0 ? -(int)floorf(t0) : -0x3fffffff,
+                Nadj > 0 ? (int)ceilf(fmaf((float)(Nadj - 1), dt_ax, t0)) + 1 : -0x3fffffff,
+                bad ? 1 : 0};
+    wg_max_n<NT>(v, 3, iscratch);
+    tlo = -v[0];
+    thi = v[1];
+    if (v[2]) {
+      const Brick none{};
+      for (float fi = (float)(Nadj - 1); fi >= 0.0f; fi -= 1.0f)
+        color_adj_sample<DT, false, false, XH>(vd, r, fi, acc, none, gmask, need_xhat, s, x, qs);
+      if (want_dv) color_cell_flush<false, false>(vd, none, acc, s, qs);
+      tlo = thi = 0;
+    }
+  }
+  const int acap = want_dv ? vcap : 0;
+  float dz = 4.0f;
+  for (float th = (float)thi; th > (float)tlo;) {
+    int st, a = 0, b = 0;
+    float tl;
+    Brick br;
+    for (;;) {
+      tl = fmaxf(th - dz, (float)tlo);
+      a = (int)fminf(fmaxf(ceilf((tl - t0) / dt_ax), 0.0f), (float)Nadj);
+      b = (int)fminf(fmaxf(ceilf((th - t0) / dt_ax), 0.0f), (float)Nadj);
+      if (Nadj <= 0) a = b = 0;
+      if (!range_brick<NT>(vd, r, a, b, iscratch, br)) { st = 0; dz = fminf(2.0f * dz, 64.0f); break; }
+      if (acap > 0 && br.size <= acap) {
+        if (4 * br.size < acap) dz = fminf(2.0f * dz, 64.0f);
+        st = 1;
+        break;
+      }
+      if (acap <= 0 || dz <= 0.25f) { st = 2; break; }
+      dz *= 0.5f;
+    }
+    th = tl;
+    if (st == 0) continue;
+    const float fa = (float)a;
+    if (st == 1) {
+      color_brick_zero<NT>(br, acc);
+      __syncthreads();
+      for (float fi = (float)(b - 1); fi >= fa; fi -= 1.0f)
+        color_adj_sample<DT, true, FIX, XH>(vd, r, fi, acc, br, gmask, need_xhat, s, x, qs);
+      if (want_dv) color_cell_flush<true, FIX>(vd, br, acc, s, qs);
+      __syncthreads();
+      color_brick_flush<NT, FIX>(vd, br, acc, inv_qs);
+    } else {
+      for (float fi = (float)(b - 1); fi >= fa; fi -= 1.0f)
+        color_adj_sample<DT, false, false, XH>(vd, r, fi, acc, br, gmask, need_xhat, s, x, qs);
+      if (want_dv) color_cell_flush<false, false>(vd, br, acc, s, qs);
+    }
+  }
+}
+
+template <int DT, int PASS, bool XH>
+__global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
+  constexpr int NT = 256, TW = 16, TH = 16;
+  extern __shared__ __align__(16) float smem[];
+  const ViewDesc& vd = p.one;
+  const int vcap = p.lds_cap;          // vertices per brick (4 floats each)
+  float* acc = smem;
+  int* iscratch = reinterpret_cast<int*>(smem + 4 * vcap);
+  float* fscratch = reinterpret_cast<float*>(iscratch);
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int lx, ly;
+  tile_pixel<4>(false, wid, lane, lx, ly);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool valid = px < vd.W && py < vd.H;
+  const int64_t pix = (int64_t)py * vd.W + px;
+  RayG r;
+  setup_ray(vd, px, py, valid, r);
+  const int N = r.N;
+  const bool hit = N > 0;
+  const int mode = p.flags & DDVR_ADJ_MODE_MASK;
+
+  float CN[3] = {0.0f, 0.0f, 0.0f}, TN = 1.0f;
+  float gimg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // The forward runs in every pass: the adjoint pass re-marches it for the
+  // start of each ray's inversion and the bound of the fixed-point brick
+  // (reproducing the image and T_N the forward pass wrote, bit for bit).
+  ColorCut cut;
+  color_march_fwd<DT, PASS != PASS_FWD>(vd, r, N, CN, TN, cut);
+  if (PASS != PASS_ADJ) {
+    if (valid) {
+      reinterpret_cast<float4*>(vd.image)[pix] = make_float4(CN[0], CN[1], CN[2], 1.0f - TN);
+      if (vd.trans) vd.trans[pix] = TN;
+    }
+    if (PASS == PASS_FWD) return;
+    float loss = 0.0f;
+    if (valid) {
+      const float out[4] = {CN[0], CN[1], CN[2], 1.0f - TN};
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const float dlt = out[ch] - vd.target[pix * 4 + ch];
+        loss = fmaf(dlt, dlt, loss);
+        gimg[ch] = 2.0f * p.loss_scale * dlt;
+      }
+    }
+    if (p.loss_out) {
+      float l = loss * p.loss_scale;
+      wg_sum_n<NT>(&l, 1, fscratch);
+      if (threadIdx.x == 0 && l != 0.0f) atomicAdd(p.loss_out, (double)l);
+    }
+  } else if (valid) {
+    const float4 g = reinterpret_cast<const float4*>(vd.d_image)[pix];
+    gimg[0] = g.x; gimg[1] = g.y; gimg[2] = g.z; gimg[3] = g.w;
+  }
+  const bool seeded = gimg[0] != 0.0f || gimg[1] != 0.0f || gimg[2] != 0.0f || gimg[3] != 0.0f;
+  // where the inversion starts (INVERT_T: always at the last sample)
+  const bool cutting = hit && seeded && mode == DDVR_ADJ_AUTO && !(TN >= kFallbackTmin);
+  if (!cutting) cut.K = N;
+
+  int gmask = p.grad_mask;
+  if (!vd.dV) gmask &= ~GRAD_V;
+  if (!vd.dcam) gmask &= ~GRAD_CAM;
+  if (!vd.dstep) gmask &= ~GRAD_STEP;
+  const bool need_xhat = XH && (gmask & (GRAD_CAM | GRAD_STEP)) != 0;
+  const bool want_dv = (gmask & GRAD_V) != 0;
+  const int Nadj = seeded ? cut.K : 0;
+
+  ColorAdjL s;
+  s.Chat[0] = gimg[0]; s.Chat[1] = gimg[1]; s.Chat[2] = gimg[2];
+  s.ahat = gimg[3];
+  s.Tn = TN;
+  s.fK1 = -1.0f;
+  s.TK1 = cut.TK1;
+  s.P = 0.0f;
+  if (cutting && Nadj > 0) {
+    s.fK1 = (float)(Nadj - 1);
+    s.P = gimg[3] * TN - ((CN[0] - cut.CK[0]) * gimg[0] + (CN[1] - cut.CK[1]) * gimg[1] +
+                          (CN[2] - cut.CK[2]) * gimg[2]);
+  }
+  s.ckey = -1;
+  s.gkey = -1;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s.cg[ch][k] = 0.0f;
+  AdjState x;
+  x.xo_hat[0] = x.xo_hat[1] = x.xo_hat[2] = 0.0;
+  x.si[0] = x.si[1] = x.si[2] = 0.0;
+  x.dstep = 0.0;
+
+  // Fixed-point scales of the brick, one per channel.  A vertex takes at
+  // most lmax samples of a straight ray (its 2x2x2 cells: chord <= 2 sqrt 3
+  // voxels), each adding a trilinear weight <= 1 times the sample's gradient:
+  //  * colour channel c: alpha_i T^(i) C_hat_c, at most maxw |C_hat_c|;
+  //  * extinction: dt times e_i alpha_hat_i = P^(i+1) + T^(i+1) rgb_i . C_hat
+  //    with P^(i+1) = T^(i+1) alpha_hat^(i+1) = g_alpha T_N - sum_(j>i) w_j
+  //    rgb_j . C_hat, at most |g_alpha| T_N + |C_hat|_1 (sum |w_j| m_j +
+  //    max T * max m).
+  // B_c sums these per-ray bounds over the tile; qs_c = 2^(28 - ceil(log2
+  // B_c)) keeps every partial sum below 2^28 (margin for the float32 drift of
+  // the recovered T^(i)).  A tile with a non-finite or subnormal-scale bound
+  // accumulates float32 instead.
+  float qs[4] = {1.0f, 1.0f, 1.0f, 1.0f}, inv_qs[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+  bool fix_ok = true;
+  {
+    float b4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (want_dv && Nadj > 0) {
+      const float lmax = floorf(3.4641017f / (vd.step * vd.inv_h)) + 2.0f;
+      const float c1 = fabsf(gimg[0]) + fabsf(gimg[1]) + fabsf(gimg[2]);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) b4[ch] = lmax * fabsf(gimg[ch]) * cut.maxw;
+      b4[3] = lmax * vd.step *
+              (fabsf(gimg[3]) * TN + c1 * (cut.swm + cut.tmax * cut.mmax));
+    }
+    wg_sum_n<NT>(b4, 4, fscratch);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int ch = 0; ch < 4; ++ch) fscratch[ch] = b4[ch];
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const float B = fscratch[ch] * 1.0001f;   // margin for the float32 sums
+      if (!(B < INFINITY)) {
+        fix_ok = false;
+      } else if (B > 0.0f) {
+        int ex;
+        (void)frexpf(B, &ex);          // B < 2^ex
+        const int e = 28 - ex;
+        if (e > 120) fix_ok = false;
+        else {
+          qs[ch] = ldexpf(1.0f, max(e, -120));
+          inv_qs[ch] = ldexpf(1.0f, -max(e, -120));
+        }
+      }
+    }
+  }
+  if (fix_ok)
+    color_adjoint_slabs<DT, true, XH>(vd, r, tx, ty, Nadj, acc, iscratch, vcap,
+                                      gmask, need_xhat, want_dv, s, x, qs, inv_qs);
+  else
+    color_adjoint_slabs<DT, false, XH>(vd, r, tx, ty, Nadj, acc, iscratch, vcap,
+                                       gmask, need_xhat, want_dv, s, x, qs, inv_qs);
+  if (XH && (gmask & (GRAD_CAM | GRAD_STEP))) {
+    float cg[13];
+    camera_adjoint(vd, r, x, Nadj > 0, cg);
     wg_sum_n<NT>(cg, 13, fscratch);
     if (threadIdx.x == 0) {
       if (gmask & GRAD_CAM)
@@ -2012,10 +2469,30 @@ static hipError_t launch_color2(const LaunchParams& p, int pass, bool xh, int bl
   return hipGetLastError();
 }
 
-int launch_color(const LaunchParams& p, int pass, int dtype, void* stream) {
+template <int DT>
+static hipError_t launch_color_lds2(const LaunchParams& p, int pass, bool xh, int blocks,
+                                    size_t lds, hipStream_t s) {
+  const dim3 g(blocks), b(256);
+  if (pass == PASS_FWD) hipLaunchKernelGGL((k_color_lds<DT, PASS_FWD, false>), g, b, lds, s, p);
+  else if (pass == PASS_ADJ && xh) hipLaunchKernelGGL((k_color_lds<DT, PASS_ADJ, true>), g, b, lds, s, p);
+  else if (pass == PASS_ADJ) hipLaunchKernelGGL((k_color_lds<DT, PASS_ADJ, false>), g, b, lds, s, p);
+  else if (xh) hipLaunchKernelGGL((k_color_lds<DT, PASS_FUSED, true>), g, b, lds, s, p);
+  else hipLaunchKernelGGL((k_color_lds<DT, PASS_FUSED, false>), g, b, lds, s, p);
+  return hipGetLastError();
+}
+
+int launch_color(const LaunchParams& p, int pass, int dtype, int slab, size_t lds_bytes,
+                 void* stream) {
   if (p.n_items <= 0) return 0;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const bool xh = (p.grad_mask & (GRAD_CAM | GRAD_STEP)) != 0;
+  if (slab) {
+    switch (dtype) {
+      case DDVR_F16: return (int)launch_color_lds2<DDVR_F16>(p, pass, xh, p.n_items, lds_bytes, s);
+      case DDVR_BF16: return (int)launch_color_lds2<DDVR_BF16>(p, pass, xh, p.n_items, lds_bytes, s);
+      default: return (int)launch_color_lds2<DDVR_F32>(p, pass, xh, p.n_items, lds_bytes, s);
+    }
+  }
   switch (dtype) {
     case DDVR_F16: return (int)launch_color2<DDVR_F16>(p, pass, xh, p.n_items, s);
     case DDVR_BF16: return (int)launch_color2<DDVR_BF16>(p, pass, xh, p.n_items, s);

@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 COLOR = 2
 RESIDUAL = 4
+PLAIN = 0x10
 
 
 def _say(msg):
@@ -58,9 +59,11 @@ def test_color_forward_matches_oracle(storage):
     assert np.abs(img[:, 3] - (1.0 - tr)).max() <= 1e-6
 
 
-@pytest.mark.parametrize("mode", [0, 1, RESIDUAL])
+@pytest.mark.parametrize("mode", [0, 1, RESIDUAL, PLAIN, PLAIN | 1])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_color_adjoint_matches_oracle(mode, storage):
+    """Slab-synchronous route (AUTO, INVERT_T) and direct route (PLAIN,
+    RESIDUAL)."""
     p = color_problem(storage=storage)
     _say(f"colour adjoint mode={mode} {storage}")
     ora = oracle_forward(p)
@@ -75,10 +78,12 @@ def test_color_adjoint_matches_oracle(mode, storage):
     assert_grad_close([got["dstep"]], [ref["dstep"]], "colour dstep")
 
 
-def test_color_opaque_rays_take_the_residual_form():
+def test_color_opaque_rays():
     """Extinction up to 2000 per world unit: most rays end below T_N = 2^-100,
-    where the T-form inversion has no float32 range left; AUTO runs them in
-    forward order with the residual identity and matches the oracle's tape."""
+    where the T-form inversion has no float32 range left.  The slab route
+    (AUTO) inverts them from their last sample entered above 2^-100, the
+    direct route (PLAIN, RESIDUAL) runs them in forward order with the
+    residual identity; both match the oracle's tape."""
     p = color_problem(W=48, H=40, tau_max=2000.0, seed=12)
     _say("colour opaque rays")
     ora = oracle_forward(p)
@@ -86,7 +91,10 @@ def test_color_opaque_rays_take_the_residual_form():
     assert (ora["trans"][hit] < 2.0 ** -100).mean() > 0.2
     g = _seed(p, ora, np.random.default_rng(5))
     ref = oracle_adjoint(p, g)
-    for mode in (0, RESIDUAL):
+    # slab route: inverted from the last sample above 2^-100 (the adjoint-only
+    # pass re-marches those rays; the fused pass is checked below); direct
+    # route: forward order
+    for mode in (0, RESIDUAL, PLAIN):
         got = gpu_adjoint(p, g, flags=mode)
         assert_dv_close(got["dV"], ref["dV"], f"opaque dV mode={mode}")
         assert_grad_close(got["dcam"], ref["dcam"], f"opaque dcam mode={mode}", floor_frac=5e-2)
@@ -194,3 +202,43 @@ def test_color_full_size_sampled_pixels():
     ref = oracle_adjoint(p, gs, pix=pix)
     assert_dv_close(got["dV"], ref["dV"], "full-size colour dV")
     del torch, d
+
+
+@pytest.mark.parametrize("lds_cap", [64, 1024, 16384])
+def test_color_brick_sizes_and_direct_slabs(lds_cap):
+    """Bricks that never fit (every slab on the direct path inside the slab
+    kernel), small ones (short slabs) and large ones give the same gradients;
+    the fused pass of an opaque problem (the cut taken from the in-kernel
+    forward) against the oracle."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    old = d.get_tuning()
+    try:
+        d.set_tuning(lds_cap=lds_cap, slab_k=min(old["slab_k"], old["slab_kmax"]))
+        p = color_problem(W=40, H=36, tau_max=300.0, seed=14)
+        _say(f"colour lds_cap={lds_cap}")
+        ora = oracle_forward(p)
+        hit = ora["nsamp"] > 0
+        assert (ora["trans"][hit] < 2.0 ** -100).mean() > 0.05
+        g = _seed(p, ora, np.random.default_rng(8))
+        ref = oracle_adjoint(p, g)
+        got = gpu_adjoint(p, g)
+        assert_dv_close(got["dV"], ref["dV"], f"dV lds_cap={lds_cap}")
+        assert_grad_close(got["dcam"], ref["dcam"], f"dcam lds_cap={lds_cap}", floor_frac=5e-2)
+        # fused with a target whose L2 gradient equals g on every pixel
+        img, _ = gpu_forward(p)
+        n = p.H * p.W * 4
+        scale = 1.0 / n
+        tgt = img - g / (2.0 * scale)
+        vol = device_volume(p)
+        dV = torch.zeros(p.volume.shape, device="cuda")
+        tr = torch.zeros(p.H * p.W, device="cuda")
+        im = torch.zeros(n, device="cuda")
+        d.render_fused_l2(vol, None, gpu_camera(p), p.step, COLOR,
+                          torch.from_numpy(tgt.astype(np.float32).ravel()).cuda(), scale, im, tr,
+                          d.grads_desc(dV))
+        torch.cuda.synchronize()
+        assert_dv_close(dV.cpu().double().numpy(), ref["dV"], f"fused dV lds_cap={lds_cap}",
+                        2e-3)
+    finally:
+        d.set_tuning(**old)
