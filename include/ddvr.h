@@ -244,7 +244,11 @@ int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, 
  *   workspace   device scratch of >= ddvr_adjoint_workspace_size bytes (may be
  *               NULL when that size is 0).
  *   n_fallback_rays (host, may be NULL): if given, the call synchronises the
- *               stream and returns how many rays took the checkpoint path. */
+ *               stream and returns how many rays took the checkpoint path.
+ * The colour model's default (slab) route re-marches the forward in the same
+ * kernel for the start of each ray's inversion and the scale of its
+ * fixed-point gradient brick; it reads d_image only (image and transmittance
+ * must still be given, as for every model). */
 int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
                         float step_world, int32_t model, const float* image,
                         const float* transmittance, const float* d_image,
