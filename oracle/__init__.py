@@ -65,6 +65,9 @@ def _load():
     lib.oracle_ray.argtypes = [p, i, i, i, i, i, i, i, d, p]
     lib.oracle_trace_ray.argtypes = [p, i, i, i, p, i, p, i, i, i, i, d, i, i, p, p, p, p]
     lib.oracle_kinks.argtypes = [p, i, i, i, p, i, p, i, i, d, i, p, i64, p, p, p]
+    u64 = ctypes.c_uint64
+    lib.oracle_splitmix64.argtypes = [u64, u64, p]
+    lib.oracle_density_from_color.argtypes = [p, i, i, i, p, i, p, d, d, u64, i, i, p, p, p, p]
     for f in (lib.oracle_camera_from_sphere, lib.oracle_camera_jacobian, lib.oracle_render,
               lib.oracle_adjoint, lib.oracle_render_dual, lib.oracle_trilinear,
               lib.oracle_tf_lookup, lib.oracle_ray, lib.oracle_num_threads,
@@ -244,3 +247,38 @@ def kinks(volume, tf, cam, W, H, step, model, pix=None, with_entry=False):
                                 float(step), int(model), _ptr(p), npix, _ptr(face), _ptr(knot),
                                 _ptr(entry)), "kinks")
     return (face, knot, entry) if with_entry else (face, knot)
+
+
+# ---------------------------------------------------------------------------
+# density from colour (Sec. 5.4)
+# ---------------------------------------------------------------------------
+def splitmix64(seed: int, n: int) -> int:
+    """Output n of the SplitMix64 stream of `seed` (the candidates' generator)."""
+    out = ctypes.c_uint64(0)
+    _check(_load().oracle_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(n),
+                                     ctypes.byref(out)), "splitmix64")
+    return int(out.value)
+
+
+def density_from_color(CV, tf, d_prev=None, alpha=1.0, beta=1.0, seed=0, iteration=0,
+                       ncand=256, all_costs=False):
+    """One estimation sweep: per voxel the least-cost candidate density.
+    CV [nz][ny][nx][4], tf [R][4], d_prev [nz][ny][nx] or None.
+    Returns dict(d, cost, index[, costs [nvox][ncand]])."""
+    V = _f64(CV)
+    nz, ny, nx = V.shape[:3]
+    T = _f64(tf)
+    P = None if d_prev is None else _f64(d_prev)
+    nvox = nx * ny * nz
+    d = np.zeros((nz, ny, nx))
+    c = np.zeros((nz, ny, nx))
+    idx = np.zeros((nz, ny, nx), dtype=np.int32)
+    allc = np.zeros((nvox, ncand)) if all_costs else None
+    _check(_load().oracle_density_from_color(
+        _ptr(V), nx, ny, nz, _ptr(T), T.shape[0], _ptr(P), float(alpha), float(beta),
+        ctypes.c_uint64(seed), int(iteration), int(ncand), _ptr(d), _ptr(c),
+        idx.ctypes.data_as(ctypes.c_void_p), _ptr(allc)), "density_from_color")
+    out = {"d": d, "cost": c, "index": idx}
+    if all_costs:
+        out["costs"] = allc
+    return out

@@ -603,6 +603,39 @@ bool check_common(int nx, int ny, int nz, int R, bool ea, int W, int H, double s
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Density from colour (Sec. 5.4, second stage of the reconstruction
+// pipeline): for every voxel, candidate densities drawn uniformly at random,
+// each mapped through the TF, and the candidate of least cost
+//   C(d) = ||C_T - C(d)||^2 + alpha log(1 + |tau_T - tau(d)|)
+//          + beta sum over the 6-neighbourhood (d - d_i)^2
+// kept.  (C_T, tau_T) is the voxel's entry of the colour volume; the
+// neighbours d_i are those of the previous estimate (none in the first
+// iteration), grid neighbours outside the volume are absent.  Ties keep the
+// lowest candidate index.
+//
+// Candidates come from a counter-based generator: SplitMix64 (Steele, Lea and
+// Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014),
+// whose n-th output for seed s is mix(s + (n + 1) * gamma), gamma =
+// 0x9e3779b97f4a7c15, with the variant-13 finaliser mix(z): z ^= z >> 30,
+// z *= 0xbf58476d1ce4e5b9, z ^= z >> 27, z *= 0x94d049bb133111eb,
+// z ^= z >> 31.  Candidate k of voxel v in iteration t is output n =
+// (t * nvox + v) * ncand + k, mapped to [0, 1) as (x >> 40) * 2^-24.
+// ---------------------------------------------------------------------------
+static inline uint64_t splitmix_output(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + (n + 1) * 0x9e3779b97f4a7c15ull;
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ull;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return z;
+}
+
+static inline double candidate_density(uint64_t seed, uint64_t n) {
+  return (double)(splitmix_output(seed, n) >> 40) * (1.0 / 16777216.0);
+}
+
 extern "C" {
 
 // Camera frame (12 doubles) from yaw/pitch/dist/fovy in RADIANS.
@@ -852,6 +885,59 @@ int oracle_kinks(const double* V, int nx, int ny, int nz, const double* tf, int 
     knot[q] = kmin;
     if (entry)
       entry[q] = (r.hit && r.entry_axis >= 0) ? r.t0 / std::fabs(r.omega[r.entry_axis]) : 0.0;
+  }
+  return 0;
+}
+
+int oracle_splitmix64(uint64_t seed, uint64_t n, uint64_t* out) {
+  if (!out) return -1;
+  *out = splitmix_output(seed, n);
+  return 0;
+}
+
+// CV [nz][ny][nx][4] (r, g, b, tau), tf [R][4], d_prev [nz][ny][nx] or null.
+// Outputs per voxel: d_out (the chosen candidate), cost_out (its cost),
+// idx_out (its index); all_costs [nvox][ncand] if not null.
+int oracle_density_from_color(const double* CV, int nx, int ny, int nz, const double* tf, int R,
+                              const double* d_prev, double alpha, double beta, uint64_t seed,
+                              int iter, int ncand, double* d_out, double* cost_out,
+                              int32_t* idx_out, double* all_costs) {
+  if (!CV || !tf || !d_out || nx < 1 || ny < 1 || nz < 1 || R < 2 || ncand < 1 || iter < 0)
+    return -1;
+  const int64_t nvox = (int64_t)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < nvox; ++v) {
+    const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+    const double* t = CV + 4 * v;
+    double nb[6];
+    int nn = 0;
+    if (d_prev) {
+      if (x > 0) nb[nn++] = d_prev[v - 1];
+      if (x + 1 < nx) nb[nn++] = d_prev[v + 1];
+      if (y > 0) nb[nn++] = d_prev[v - nx];
+      if (y + 1 < ny) nb[nn++] = d_prev[v + nx];
+      if (z > 0) nb[nn++] = d_prev[v - (int64_t)nx * ny];
+      if (z + 1 < nz) nb[nn++] = d_prev[v + (int64_t)nx * ny];
+    }
+    double best = 0.0, bestd = 0.0;
+    int bi = -1;
+    for (int k = 0; k < ncand; ++k) {
+      const uint64_t n = ((uint64_t)iter * (uint64_t)nvox + (uint64_t)v) * (uint64_t)ncand +
+                         (uint64_t)k;
+      const double d = candidate_density(seed, n);
+      const TFSample<double> m = tf_lookup(d, tf, R);
+      double c = 0.0;
+      for (int ch = 0; ch < 3; ++ch) c += (t[ch] - m.rgb[ch]) * (t[ch] - m.rgb[ch]);
+      c += alpha * std::log(1.0 + std::fabs(t[3] - m.tau));
+      double s = 0.0;
+      for (int q = 0; q < nn; ++q) s += (d - nb[q]) * (d - nb[q]);
+      c += beta * s;
+      if (all_costs) all_costs[v * ncand + k] = c;
+      if (bi < 0 || c < best) { best = c; bestd = d; bi = k; }
+    }
+    d_out[v] = bestd;
+    if (cost_out) cost_out[v] = best;
+    if (idx_out) idx_out[v] = bi;
   }
   return 0;
 }

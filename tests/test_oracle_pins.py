@@ -509,3 +509,84 @@ def test_colour_volume_adjoint_variants_dual_numbers_and_finite_differences():
     fd = (loss(CV + eps * Vd, cam + eps * cd, step + eps * sd) -
           loss(CV - eps * Vd, cam - eps * cd, step - eps * sd)) / (2 * eps)
     assert fd == pytest.approx(rhs, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# density from colour (Sec. 5.4): least-cost random candidates per voxel
+# ---------------------------------------------------------------------------
+def test_candidate_generator_known_outputs_and_uniformity():
+    # first outputs of the SplitMix64 stream of seed 0 (the published generator)
+    assert [oracle.splitmix64(0, n) for n in range(3)] == [
+        0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f]
+    u = np.array([(oracle.splitmix64(977, n) >> 40) / 2.0 ** 24 for n in range(40000)])
+    assert abs(u.mean() - 0.5) < 0.01 and abs(u.var() - 1.0 / 12.0) < 0.003
+    # Kolmogorov-Smirnov distance to U[0, 1)
+    s = np.sort(u)
+    ks = max(np.max(np.arange(1, len(s) + 1) / len(s) - s), np.max(s - np.arange(len(s)) / len(s)))
+    assert ks < 1.63 / np.sqrt(len(s))          # 1% level
+
+
+def _candidates(seed, iteration, nvox, v, ncand):
+    return np.array([(oracle.splitmix64(seed, (iteration * nvox + v) * ncand + k) >> 40)
+                     / 2.0 ** 24 for k in range(ncand)])
+
+
+def test_density_from_colour_colour_term_picks_the_nearest_candidate():
+    """TF rgb = (d, 1 - d, 0.5), alpha = beta = 0: the cost is 2 (d - a)^2 for
+    a target colour (a, 1 - a, 0.5), so the nearest candidate to a wins."""
+    rng = np.random.default_rng(40)
+    shape = (3, 4, 5)
+    a = rng.uniform(0, 1, shape)
+    CV = np.stack([a, 1 - a, np.full(shape, 0.5), rng.uniform(0, 3, shape)], axis=-1)
+    tf = np.array([[0.0, 1.0, 0.5, 0.0], [1.0, 0.0, 0.5, 2.0]])
+    out = oracle.density_from_color(CV, tf, alpha=0.0, beta=0.0, seed=5, iteration=2, ncand=64)
+    nvox = a.size
+    for v in range(nvox):
+        c = _candidates(5, 2, nvox, v, 64)
+        k = int(np.argmin(np.abs(c - a.flat[v])))
+        assert out["index"].flat[v] == k and out["d"].flat[v] == c[k]
+        assert out["cost"].flat[v] == pytest.approx(2 * (c[k] - a.flat[v]) ** 2, abs=1e-15)
+
+
+def test_density_from_colour_extinction_term_picks_the_nearest_candidate():
+    """Constant TF colour and tau(d) = 1 + 9 d: alpha log(1 + |tau_T - tau(d)|)
+    grows with |d - (tau_T - 1)/9|, so the nearest candidate to that wins."""
+    rng = np.random.default_rng(41)
+    shape = (2, 3, 4)
+    ds = rng.uniform(0, 1, shape)
+    CV = np.stack([np.full(shape, 0.2), np.full(shape, 0.4), np.full(shape, 0.6), 1 + 9 * ds],
+                  axis=-1)
+    tf = np.array([[0.2, 0.4, 0.6, 1.0], [0.2, 0.4, 0.6, 10.0]])
+    out = oracle.density_from_color(CV, tf, alpha=0.5, beta=0.0, seed=9, iteration=0, ncand=48)
+    for v in range(ds.size):
+        c = _candidates(9, 0, ds.size, v, 48)
+        k = int(np.argmin(np.abs(c - ds.flat[v])))
+        assert out["index"].flat[v] == k
+        assert out["cost"].flat[v] == pytest.approx(
+            0.5 * np.log1p(9 * abs(c[k] - ds.flat[v])), rel=1e-12, abs=1e-15)
+
+
+def test_density_from_colour_neighbour_term_picks_the_candidate_nearest_the_mean():
+    """Constant TF: beta sum_i (d - d_i)^2 = beta (n (d - m)^2 + const) over the
+    n neighbours present (6 inside, 3 at a corner), m their mean."""
+    rng = np.random.default_rng(42)
+    shape = (4, 3, 5)
+    prev = rng.uniform(0, 1, shape)
+    CV = np.tile(np.array([0.3, 0.3, 0.3, 1.0]), shape + (1,))
+    tf = np.array([[0.3, 0.3, 0.3, 1.0], [0.3, 0.3, 0.3, 1.0]])
+    out = oracle.density_from_color(CV, tf, prev, alpha=1.0, beta=2.0, seed=3, iteration=1,
+                                    ncand=32)
+    nz, ny, nx = shape
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                nb = [prev[zz, yy, xx] for zz, yy, xx in
+                      ((z, y, x - 1), (z, y, x + 1), (z, y - 1, x), (z, y + 1, x),
+                       (z - 1, y, x), (z + 1, y, x))
+                      if 0 <= zz < nz and 0 <= yy < ny and 0 <= xx < nx]
+                v = (z * ny + y) * nx + x
+                c = _candidates(3, 1, prev.size, v, 32)
+                k = int(np.argmin(np.abs(c - np.mean(nb))))
+                assert out["index"][z, y, x] == k, (z, y, x, len(nb))
+                assert out["cost"][z, y, x] == pytest.approx(
+                    2.0 * sum((c[k] - q) ** 2 for q in nb), rel=1e-12)
