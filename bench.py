@@ -173,7 +173,9 @@ def secondary(args):
           every view by forward-mode (delayed / immediate) and by the adjoint;
       color  pre-shaded colour volume 256^3 x (r, g, b, tau) bf16, the C3 views
           (64 at 512x512, step 0.2 voxel), fused L2 with the colour-volume
-          gradient, one launch per view."""
+          gradient, one launch per view;
+      dfc  density from colour on that volume: R=32 TF, 256 candidates per
+          voxel, one Jacobi sweep with the 6-neighbour term per step."""
     import numpy as np
     import torch
     import synth
@@ -292,6 +294,59 @@ def secondary(args):
                     "config": {"workload": w.name + ", fused L2, colour-volume gradient",
                                "samples_per_step": S},
                     "residual_form": res["residual"], "forward_ms": fwd_ms})
+    elif args.workload == "dfc":
+        w = synth.make_color()
+        vol = stored(w.volume, w.storage)
+        rng = synth.rng_for(9, 7)
+        tf = torch.from_numpy(synth.random_tf(32, rng, synth.COLOR_TAU_MAX)).to(dev)
+        shape = w.volume.shape[:3]
+        nvox = int(np.prod(shape))
+        ncand = 256
+        a = torch.zeros(shape, device=dev)
+        b = torch.zeros(shape, device=dev)
+        nch = torch.zeros(1, dtype=torch.int32, device=dev)
+        alpha = d.density_from_color(vol, tf, a, seed=7, sweep=0, ncand=ncand)
+        it = [1]
+
+        def sweep():
+            src, dst = (a, b) if it[0] % 2 else (b, a)
+            d.density_from_color(vol, tf, dst, d_prev=src, alpha=alpha, beta=1.0, seed=7,
+                                 sweep=it[0], ncand=ncand, n_changed=nch)
+            it[0] += 1
+
+        ms = _timed(sweep, args.steps, args.warmup, stream, torch)
+        log(f"dfc: {ms:.3f} ms per sweep, {nvox * ncand / (ms * 1e-3):.4g} candidates/s")
+        # ALU roofline: VALU lane-operations of the candidate loop (counted in
+        # the kernel's assembly) per sweep over its event-timed duration (one
+        # launch per sweep, on the timed stream)
+        try:
+            with open(os.path.join(ROOT, "profiles", "valu_per_candidate_dfc.json")) as f:
+                vc = json.load(f)
+        except (OSError, ValueError):
+            vc = None
+        h = hashlib.sha256()
+        for rel in ("paper_2107_12672_amd/csrc/ddvr_dfc.hip",
+                    "paper_2107_12672_amd/csrc/ddvr_internal.h"):
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        if vc and vc.get("kernel_source_sha") == h.hexdigest()[:16]:
+            ops = nvox * ncand * vc["valu_per_candidate"]
+            a = ops / (ms * 1e-3) / 1e12
+            out["roofline"] = {"bound": "alu", "achieved": round(a, 3), "peak": VALU_PEAK_TOPS,
+                               "unit": "TOP/s", "frac": round(a / VALU_PEAK_TOPS, 4),
+                               "traffic": None, "kernel": "k_density_from_color<bf16>",
+                               "kernel_ms": round(ms, 4), "ops_per_launch": ops,
+                               "ops": "VALU lane-operations: %d per candidate" %
+                                      vc["valu_per_candidate"]}
+        else:
+            out["roofline"] = None
+        out.update({"metric": "candidate evaluations/s (density from colour, one sweep)",
+                    "unit": "candidates/s", "value": nvox * ncand / (ms * 1e-3),
+                    "ms_per_step": ms,
+                    "config": {"workload": f"density from colour: {w.name.split(',')[0]}, "
+                                           f"R=32 TF, {ncand} candidates per voxel, "
+                                           "6-neighbour term", "voxels": nvox,
+                               "candidates": ncand}})
     elif args.workload == "viewpoint":
         # viewpoint gradients (yaw, pitch, dist) of every view of the C5 grid:
         # forward-delayed (one tangent pass per view), forward-immediate
@@ -396,7 +451,7 @@ def main():
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
     ap.add_argument("--step-vox", type=float, default=0.2)
-    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint", "color"),
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint", "color", "dfc"),
                     help="c3 (default) is the headline tomography step; the others print "
                          "their own line")
     ap.add_argument("--burn-in", type=int, default=4,

@@ -309,6 +309,40 @@ int ddvr_camera_sphere_tangents(float yaw, float pitch, float dist, float fovy, 
                                 int32_t height, float* d_frame);
 
 /* ------------------------------------------------------------------------
+ * Density from colour (Sec. 5.4, second stage of the reconstruction
+ * pipeline): a density grid whose TF colours match a pre-shaded colour volume.
+ * ------------------------------------------------------------------------ */
+/* One estimation sweep.  For every voxel, ncand candidate densities drawn
+ * uniformly from [0, 1) are mapped through the TF, and the one of least cost
+ *   C(d) = ||C_T - C(d)||^2 + alpha log(1 + |tau_T - tau(d)|)
+ *          + beta sum over the 6-neighbourhood (d - d_i)^2
+ * is kept (ties: the lowest candidate index).  (C_T, tau_T) is the voxel's
+ * entry of `color`; d_i are the previous estimate's grid neighbours (absent
+ * outside the grid).  The sweep is Jacobi: every voxel reads d_prev only.
+ *   color       colour volume (data [nz][ny][nx][4], as the DDVR_COLOR model).
+ *   tf          [R][4] float32 (r, g, b, tau), knots at k/(R-1), 2 <= R <= 4096.
+ *   d_prev      [nz][ny][nx] float32 (device) or NULL: no neighbour term (the
+ *               first sweep).  Must not alias d_out.
+ *   alpha, beta finite weights (the paper: alpha = 1/max(tau_T), beta = 1;
+ *               see ddvr_color_tau_max).
+ *   seed, sweep candidates are outputs (sweep*nvox + voxel)*ncand + k of the
+ *               SplitMix64 stream of `seed` (Steele, Lea and Flood 2014), top
+ *               24 bits times 2^-24; sweep >= 0 numbers the iterations.
+ *   ncand       candidates per voxel, 1..65536 (the paper: 256).
+ *   d_out       [nz][ny][nx] float32, written.
+ *   cost_out    [nz][ny][nx] float32 cost of the kept candidate, or NULL.
+ *   n_changed   (device, one uint32, or NULL) += voxels whose estimate differs
+ *               from d_prev (the paper's stopping test). */
+int ddvr_density_from_color(const ddvr_volume* color, const ddvr_tf* tf, const float* d_prev,
+                            float alpha, float beta, uint64_t seed, int32_t sweep,
+                            int32_t ncand, float* d_out, float* cost_out, uint32_t* n_changed,
+                            void* hip_stream);
+
+/* Largest extinction (channel 3) of a colour volume: *out (device, one float)
+ * is written (-inf for an empty volume). */
+int ddvr_color_tau_max(const ddvr_volume* color, float* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many views of one or several grids in ONE launch.
  * ------------------------------------------------------------------------ */
 typedef struct {

@@ -67,7 +67,8 @@ def _load():
     lib.oracle_kinks.argtypes = [p, i, i, i, p, i, p, i, i, d, i, p, i64, p, p, p]
     u64 = ctypes.c_uint64
     lib.oracle_splitmix64.argtypes = [u64, u64, p]
-    lib.oracle_density_from_color.argtypes = [p, i, i, i, p, i, p, d, d, u64, i, i, p, p, p, p]
+    lib.oracle_density_from_color.argtypes = [p, i, i, i, p, i, p, d, d, u64, i, i, p, i64,
+                                              p, p, p, p, p]
     for f in (lib.oracle_camera_from_sphere, lib.oracle_camera_jacobian, lib.oracle_render,
               lib.oracle_adjoint, lib.oracle_render_dual, lib.oracle_trilinear,
               lib.oracle_tf_lookup, lib.oracle_ray, lib.oracle_num_threads,
@@ -261,24 +262,31 @@ def splitmix64(seed: int, n: int) -> int:
 
 
 def density_from_color(CV, tf, d_prev=None, alpha=1.0, beta=1.0, seed=0, iteration=0,
-                       ncand=256, all_costs=False):
+                       ncand=256, all_costs=False, voxels=None):
     """One estimation sweep: per voxel the least-cost candidate density.
-    CV [nz][ny][nx][4], tf [R][4], d_prev [nz][ny][nx] or None.
-    Returns dict(d, cost, index[, costs [nvox][ncand]])."""
+    CV [nz][ny][nx][4], tf [R][4], d_prev [nz][ny][nx] or None; voxels: flat
+    indices to evaluate (outputs then follow that list), or None for all.
+    Returns dict(d, cost, index[, costs, cands: [voxel][ncand]])."""
     V = _f64(CV)
     nz, ny, nx = V.shape[:3]
     T = _f64(tf)
     P = None if d_prev is None else _f64(d_prev)
-    nvox = nx * ny * nz
-    d = np.zeros((nz, ny, nx))
-    c = np.zeros((nz, ny, nx))
-    idx = np.zeros((nz, ny, nx), dtype=np.int32)
-    allc = np.zeros((nvox, ncand)) if all_costs else None
+    sel = None if voxels is None else np.ascontiguousarray(np.asarray(voxels, dtype=np.int64))
+    shape = (nz, ny, nx) if sel is None else (len(sel),)
+    nq = int(np.prod(shape))
+    d = np.zeros(shape)
+    c = np.zeros(shape)
+    idx = np.zeros(shape, dtype=np.int32)
+    allc = np.zeros((nq, ncand)) if all_costs else None
+    alld = np.zeros((nq, ncand)) if all_costs else None
     _check(_load().oracle_density_from_color(
         _ptr(V), nx, ny, nz, _ptr(T), T.shape[0], _ptr(P), float(alpha), float(beta),
-        ctypes.c_uint64(seed), int(iteration), int(ncand), _ptr(d), _ptr(c),
-        idx.ctypes.data_as(ctypes.c_void_p), _ptr(allc)), "density_from_color")
+        ctypes.c_uint64(seed), int(iteration), int(ncand),
+        None if sel is None else sel.ctypes.data_as(ctypes.c_void_p), 0 if sel is None else len(sel),
+        _ptr(d), _ptr(c), idx.ctypes.data_as(ctypes.c_void_p), _ptr(allc), _ptr(alld)),
+        "density_from_color")
     out = {"d": d, "cost": c, "index": idx}
     if all_costs:
         out["costs"] = allc
+        out["cands"] = alld
     return out

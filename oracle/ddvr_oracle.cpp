@@ -896,17 +896,25 @@ int oracle_splitmix64(uint64_t seed, uint64_t n, uint64_t* out) {
 }
 
 // CV [nz][ny][nx][4] (r, g, b, tau), tf [R][4], d_prev [nz][ny][nx] or null.
-// Outputs per voxel: d_out (the chosen candidate), cost_out (its cost),
-// idx_out (its index); all_costs [nvox][ncand] if not null.
+// vox: the nsel voxel indices to evaluate, or null for every voxel.  Outputs
+// per evaluated voxel q: d_out (the chosen candidate), cost_out (its cost),
+// idx_out (its index); all_costs / all_cands [q][ncand] (every candidate's
+// cost / density) if not null.
 int oracle_density_from_color(const double* CV, int nx, int ny, int nz, const double* tf, int R,
                               const double* d_prev, double alpha, double beta, uint64_t seed,
-                              int iter, int ncand, double* d_out, double* cost_out,
-                              int32_t* idx_out, double* all_costs) {
+                              int iter, int ncand, const int64_t* vox, int64_t nsel,
+                              double* d_out, double* cost_out, int32_t* idx_out,
+                              double* all_costs, double* all_cands) {
   if (!CV || !tf || !d_out || nx < 1 || ny < 1 || nz < 1 || R < 2 || ncand < 1 || iter < 0)
     return -1;
   const int64_t nvox = (int64_t)nx * ny * nz;
+  const int64_t nq = vox ? nsel : nvox;
+  if (vox)
+    for (int64_t q = 0; q < nsel; ++q)
+      if (vox[q] < 0 || vox[q] >= nvox) return -2;
 #pragma omp parallel for schedule(static)
-  for (int64_t v = 0; v < nvox; ++v) {
+  for (int64_t q = 0; q < nq; ++q) {
+    const int64_t v = vox ? vox[q] : q;
     const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
     const double* t = CV + 4 * v;
     double nb[6];
@@ -932,12 +940,13 @@ int oracle_density_from_color(const double* CV, int nx, int ny, int nz, const do
       double s = 0.0;
       for (int q = 0; q < nn; ++q) s += (d - nb[q]) * (d - nb[q]);
       c += beta * s;
-      if (all_costs) all_costs[v * ncand + k] = c;
+      if (all_costs) all_costs[q * ncand + k] = c;
+      if (all_cands) all_cands[q * ncand + k] = d;
       if (bi < 0 || c < best) { best = c; bestd = d; bi = k; }
     }
-    d_out[v] = bestd;
-    if (cost_out) cost_out[v] = best;
-    if (idx_out) idx_out[v] = bi;
+    d_out[q] = bestd;
+    if (cost_out) cost_out[q] = best;
+    if (idx_out) idx_out[q] = bi;
   }
   return 0;
 }

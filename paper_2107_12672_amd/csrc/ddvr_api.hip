@@ -648,6 +648,53 @@ int ddvr_render_forward(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
                     nullptr, 0.0f, nullptr, flags, nullptr, 0, nullptr, nullptr, hip_stream);
 }
 
+int ddvr_density_from_color(const ddvr_volume* color, const ddvr_tf* tf, const float* d_prev,
+                            float alpha, float beta, uint64_t seed, int32_t sweep,
+                            int32_t ncand, float* d_out, float* cost_out, uint32_t* n_changed,
+                            void* hip_stream) {
+  int rc;
+  if ((rc = validate_volume(color)) || (rc = validate_color_volume(color)) ||
+      (rc = validate_tf(tf, DDVR_EMISSION_ABSORPTION)))
+    return rc;
+  if (!d_out) return fail(DDVR_ERR_NULL, "d_out is NULL");
+  if (d_prev && d_prev == d_out) return fail(DDVR_ERR_VALUE, "d_prev must not alias d_out");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(DDVR_ERR_VALUE, "alpha and beta must be finite");
+  if (sweep < 0) return fail(DDVR_ERR_VALUE, "sweep must be >= 0");
+  if (ncand < 1 || ncand > 65536) return fail(DDVR_ERR_VALUE, "ncand must be 1..65536");
+  if ((rc = check_pending())) return rc;
+  DfcParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.cv = color->data;
+  p.nx = color->nx; p.ny = color->ny; p.nz = color->nz;
+  p.tf = tf->rgba_tau;
+  p.R = tf->R;
+  p.d_prev = d_prev;
+  p.d_out = d_out;
+  p.cost_out = cost_out;
+  p.n_changed = n_changed;
+  p.alpha = alpha;
+  p.beta = beta;
+  p.seed = seed;
+  p.iter = sweep;
+  p.ncand = ncand;
+  const hipError_t e = (hipError_t)launch_density_from_color(p, color->dtype, hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "density-from-colour launch");
+  return DDVR_OK;
+}
+
+int ddvr_color_tau_max(const ddvr_volume* color, float* out, void* hip_stream) {
+  int rc;
+  if ((rc = validate_volume(color)) || (rc = validate_color_volume(color))) return rc;
+  if (!out) return fail(DDVR_ERR_NULL, "out is NULL");
+  if ((rc = check_pending())) return rc;
+  const int64_t nvox = (int64_t)color->nx * color->ny * color->nz;
+  const hipError_t e =
+      (hipError_t)launch_color_tau_max(color->data, color->dtype, nvox, out, hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "tau-max launch");
+  return DDVR_OK;
+}
+
 int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, float step_world,
                                 int32_t model, int32_t flags, size_t* bytes) {
   int rc;

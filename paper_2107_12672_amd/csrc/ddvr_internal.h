@@ -78,6 +78,21 @@ struct TangentParams {
   float* d_dir;           // [ndir] += <d_image, image_dot_k> or null (forward-delayed)
 };
 
+// Density-from-colour sweep (one voxel per lane).
+struct DfcParams {
+  const void* cv;         // colour volume [nz][ny][nx][4] (r, g, b, tau), storage dtype
+  int32_t nx, ny, nz;
+  const float* tf;        // [R][4]
+  int32_t R;
+  const float* d_prev;    // [nz][ny][nx] previous estimate or null (no neighbour term)
+  float* d_out;           // [nz][ny][nx]
+  float* cost_out;        // [nz][ny][nx] or null
+  uint32_t* n_changed;    // += voxels whose estimate changed, or null
+  float alpha, beta;
+  uint64_t seed;
+  int32_t iter, ncand;
+};
+
 enum GradBits { GRAD_V = 1, GRAD_TF = 2, GRAD_CAM = 4, GRAD_STEP = 8 };
 
 enum Pass { PASS_FWD = 0, PASS_ADJ = 1, PASS_FUSED = 2 };
@@ -95,6 +110,9 @@ int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, s
 int launch_color(const LaunchParams& p, int pass, int dtype, int slab, size_t lds_bytes,
                  void* stream);
 int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
+// implemented in ddvr_dfc.hip
+int launch_density_from_color(const DfcParams& p, int dtype, void* stream);
+int launch_color_tau_max(const void* cv, int dtype, int64_t nvox, float* out, void* stream);
 
 constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persistent launch
 constexpr int kMaxSamples = 1 << 22;    // per-ray sample cap (validated on the host)

@@ -30,7 +30,8 @@ EXPORTED = [
     "ddvr_render_adjoint", "ddvr_render_fused_l2", "ddvr_batch_create", "ddvr_batch_destroy",
     "ddvr_batch_workspace_size", "ddvr_batch_run", "ddvr_batch_run_graph",
     "ddvr_batch_sample_count", "ddvr_cast_volume", "ddvr_set_tuning", "ddvr_get_tuning",
-    "ddvr_render_tangent", "ddvr_camera_sphere_tangents",
+    "ddvr_render_tangent", "ddvr_camera_sphere_tangents", "ddvr_density_from_color",
+    "ddvr_color_tau_max",
 ]
 MAX_DIRECTIONS = 4
 
@@ -113,6 +114,9 @@ def lib():
         "ddvr_get_tuning": ([P], ctypes.c_int),
         "ddvr_render_tangent": ([P, P, P, F, I32, P, I32, P, P, P, P, I32, P], ctypes.c_int),
         "ddvr_camera_sphere_tangents": ([F, F, F, F, I32, I32, P], ctypes.c_int),
+        "ddvr_density_from_color": ([P, P, P, F, F, ctypes.c_uint64, I32, I32, P, P, P, P],
+                                    ctypes.c_int),
+        "ddvr_color_tau_max": ([P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -341,3 +345,28 @@ def make_view(volume_index: int, cam: Camera, step: float, image, transmittance=
               d_image=None, target=None, d_camera=None, d_step=None, tf_index: int = -1) -> View:
     return View(volume_index, tf_index, cam, step, _ptr(image), _ptr(transmittance),
                 _ptr(d_image), _ptr(target), _ptr(d_camera), _ptr(d_step))
+
+
+def color_tau_max(color, out, stream=None):
+    """out (device float32 tensor of one element) = max of the colour volume's
+    extinction channel."""
+    v = volume_desc(color)
+    _check(lib().ddvr_color_tau_max(ctypes.byref(v), _ptr(out), _stream(stream)))
+
+
+def density_from_color(color, tf, d_out, d_prev=None, alpha=None, beta: float = 1.0,
+                       seed: int = 0, sweep: int = 0, ncand: int = 256, cost_out=None,
+                       n_changed=None, stream=None):
+    """One density-from-colour sweep (Sec. 5.4) into d_out.  alpha=None takes
+    the paper's 1/max(tau_T), reduced on the device and read back."""
+    v, t = volume_desc(color), tf_desc(tf)
+    if alpha is None:
+        import torch
+        mx = torch.empty(1, dtype=torch.float32, device=d_out.device)
+        color_tau_max(color, mx, stream)
+        alpha = 1.0 / float(mx.item())
+    _check(lib().ddvr_density_from_color(
+        ctypes.byref(v), ctypes.byref(t), _ptr(d_prev), float(alpha), float(beta),
+        ctypes.c_uint64(seed), int(sweep), int(ncand), _ptr(d_out), _ptr(cost_out),
+        _ptr(n_changed), _stream(stream)))
+    return alpha

@@ -12,8 +12,11 @@ assembly and counts, for the absorption-only bf16 4-wave kernels:
     innermost loop that adds to the LDS brick (ds_add_u32), except the basic
     blocks that do the adding (the cell-exit flush, taken only when a ray
     leaves its cell) -- one sample, plus the flush block counted separately.
-``--write`` stores the counts with the source hash in
-``profiles/valu_per_sample_c3.json``, which the benchmark reads.
+It also counts, in ``csrc/ddvr_dfc.hip``, the VALU instructions of the
+density-from-colour candidate loop (bf16 colour volume): one candidate.
+``--write`` stores the counts with the source hashes in
+``profiles/valu_per_sample_c3.json`` and ``profiles/valu_per_candidate_dfc.json``,
+which the benchmark reads.
 """
 from __future__ import annotations
 
@@ -30,27 +33,30 @@ from . import build as _build
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
+OUT_DFC = os.path.join(ROOT, "profiles", "valu_per_candidate_dfc.json")
+DFC_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_dfc.hip", "paper_2107_12672_amd/csrc/ddvr_internal.h"]
+DFC = "_ZN4ddvr12_GLOBAL__N_120k_density_from_colorILi2EEEvNS_9DfcParamsE"
 KERNEL_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_kernels.hip",
                   "paper_2107_12672_amd/csrc/ddvr_internal.h"]
 FWD = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi0ELb0EEEvNS_12LaunchParamsE"
 FUSED = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi2ELb0EEEvNS_12LaunchParamsE"
 
 
-def source_hash() -> str:
+def source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (sources or KERNEL_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def assembly() -> str:
+def assembly(src: str = "ddvr_kernels.hip") -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = [f for f in _build.HIPCC_FLAGS if f != "-fPIC"]
     with tempfile.TemporaryDirectory() as tmp:
         out = os.path.join(tmp, "k.s")
         subprocess.check_call([hipcc] + flags + ["--cuda-device-only", "-S", "-o", out,
-                                                 os.path.join(_build.CSRC, "ddvr_kernels.hip")],
+                                                 os.path.join(_build.CSRC, src)],
                               stderr=subprocess.DEVNULL)
         with open(out) as f:
             return f.read()
@@ -74,7 +80,7 @@ def _loops(lines):
             cur = None
             m = re.match(r"^\.L(BB\S+):", l)
             nxt = lines[i + 1] if i + 1 < len(lines) else ""
-            if m and "Inner Loop Header" in nxt:
+            if m and ("Inner Loop Header" in l or "Inner Loop Header" in nxt):
                 cur = m.group(1)
             else:
                 h = re.search(r"in Loop: Header=(BB\S+)", l)
@@ -95,7 +101,8 @@ def _inner(lines):
     marked = set()
     for i, l in enumerate(lines):
         m = re.match(r"^\.L(BB\S+):", l)
-        if m and i + 1 < len(lines) and "Inner Loop Header" in lines[i + 1]:
+        if m and ("Inner Loop Header" in l or
+                  (i + 1 < len(lines) and "Inner Loop Header" in lines[i + 1])):
             marked.add(m.group(1))
     return {h: b for h, b in _loops(lines).items() if h in marked}
 
@@ -124,16 +131,32 @@ def count(asm: str) -> dict:
             "adjoint_cell_exit_flush_valu": flush}
 
 
+def count_dfc(asm: str) -> dict:
+    """VALU instructions of the candidate loop (the innermost loop holding the
+    log of the extinction term)."""
+    for blocks in _inner(_kernel(asm, DFC)).values():
+        ins = [x for _, blk in blocks for x in blk]
+        if any(x.startswith("v_log_f32") for x in ins):
+            return {"valu_per_candidate": sum(1 for x in ins if x.startswith("v_"))}
+    raise RuntimeError("candidate loop not found in the assembly")
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     res = count(assembly())
     res["kernel_source_sha"] = source_hash()
     res["kernels"] = {"forward": FWD, "fused": FUSED}
+    dfc = count_dfc(assembly("ddvr_dfc.hip"))
+    dfc["kernel_source_sha"] = source_hash(DFC_SOURCES)
+    dfc["kernel"] = DFC
     print(json.dumps(res, indent=1))
+    print(json.dumps(dfc, indent=1))
     if "--write" in argv:
         os.makedirs(os.path.dirname(OUT), exist_ok=True)
         with open(OUT, "w") as f:
             json.dump(res, f, indent=1)
+        with open(OUT_DFC, "w") as f:
+            json.dump(dfc, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -267,3 +267,25 @@ def test_colour_model_validation():
     vols = (d.Volume * 1)(vol)
     assert L.ddvr_batch_create(vols, 1, None, 0, views, 1, C, 0, None, None, None,
                                B(h)) == d.ERR_UNSUPPORTED
+
+
+def test_density_from_color_validation():
+    d = _ddvr()
+    L = d.lib()
+    vol, tf, cam = _descs(d)
+    B = ctypes.byref
+    f = L.ddvr_density_from_color
+    out = 0x7000
+    assert f(B(vol), B(tf), None, 1.0, 1.0, 0, 0, 256, None, None, None, None) == d.ERR_NULL
+    assert f(B(vol), None, None, 1.0, 1.0, 0, 0, 256, out, None, None, None) == d.ERR_NULL
+    assert f(B(vol), B(d.TF(0x2000, 1)), None, 1.0, 1.0, 0, 0, 256, out, None, None,
+             None) == d.ERR_SHAPE
+    assert f(B(vol), B(tf), None, 1.0, 1.0, 0, 0, 0, out, None, None, None) == d.ERR_VALUE
+    assert f(B(vol), B(tf), None, 1.0, 1.0, 0, 0, 65537, out, None, None, None) == d.ERR_VALUE
+    assert f(B(vol), B(tf), None, 1.0, 1.0, 0, -1, 256, out, None, None, None) == d.ERR_VALUE
+    assert f(B(vol), B(tf), None, float("nan"), 1.0, 0, 0, 256, out, None, None,
+             None) == d.ERR_VALUE
+    assert f(B(vol), B(tf), out, 1.0, 1.0, 0, 0, 256, out, None, None, None) == d.ERR_VALUE
+    assert f(B(d.Volume(0x1008, d.F32, 8, 8, 8)), B(tf), None, 1.0, 1.0, 0, 0, 256, out, None,
+             None, None) == d.ERR_VALUE       # 4-channel data must be 16-byte aligned
+    assert L.ddvr_color_tau_max(B(vol), None, None) == d.ERR_NULL

@@ -590,3 +590,22 @@ def test_density_from_colour_neighbour_term_picks_the_candidate_nearest_the_mean
                 assert out["index"][z, y, x] == k, (z, y, x, len(nb))
                 assert out["cost"][z, y, x] == pytest.approx(
                     2.0 * sum((c[k] - q) ** 2 for q in nb), rel=1e-12)
+
+
+def test_density_from_colour_voxel_selection_and_candidate_listing():
+    rng = np.random.default_rng(43)
+    shape = (3, 5, 4)
+    CV = rng.uniform(0, 1, shape + (4,)) * np.array([1, 1, 1, 6.0])
+    tf = rng.uniform(0, 1, (7, 4)) * np.array([1, 1, 1, 6.0])
+    prev = rng.uniform(0, 1, shape)
+    full = oracle.density_from_color(CV, tf, prev, alpha=0.3, beta=0.7, seed=11, iteration=4,
+                                     ncand=20)
+    sel = np.array([0, 7, 33, 59, 21])
+    part = oracle.density_from_color(CV, tf, prev, alpha=0.3, beta=0.7, seed=11, iteration=4,
+                                     ncand=20, voxels=sel, all_costs=True)
+    assert np.array_equal(part["d"], full["d"].ravel()[sel])
+    assert np.array_equal(part["index"], full["index"].ravel()[sel])
+    for q, v in enumerate(sel):
+        assert np.array_equal(part["cands"][q], _candidates(11, 4, prev.size, v, 20))
+        assert part["costs"][q].min() == part["cost"][q]
+        assert part["costs"][q][part["index"][q]] == part["cost"][q]
