@@ -609,3 +609,104 @@ def test_density_from_colour_voxel_selection_and_candidate_listing():
         assert np.array_equal(part["cands"][q], _candidates(11, 4, prev.size, v, 20))
         assert part["costs"][q].min() == part["cost"][q]
         assert part["costs"][q][part["index"][q]] == part["cost"][q]
+
+
+# ---------------------------------------------------------------------------
+# losses, priors and optimiser of the reconstruction loop (Sec. 5.1-5.3)
+# ---------------------------------------------------------------------------
+from oracle import losses as OL
+
+
+def _fd(f, x, h=1e-6):
+    g = np.zeros_like(x)
+    it = np.nditer(x, flags=["multi_index"])
+    for _ in it:
+        i = it.multi_index
+        xp = x.copy(); xp[i] += h
+        xm = x.copy(); xm[i] -= h
+        g[i] = (f(xp) - f(xm)) / (2 * h)
+    return g
+
+
+def test_l1_loss_and_seed_by_hand():
+    loss, g = OL.l1_loss_and_seed([0.5, 0.2, 0.7], [0.25, 0.2, 1.0], 0.5)
+    assert loss == pytest.approx(0.5 * (0.25 + 0.0 + 0.3))
+    assert list(g) == [0.5, 0.0, -0.5]
+
+
+def test_tf_prior_closed_forms_and_finite_differences():
+    R = 9
+    lam = 0.4
+    T = np.tile(np.array([0.1, 0.5, 0.9, 3.0]), (R, 1))
+    loss, g = OL.tf_prior(T, lam)
+    assert loss == 0.0 and not g.any()
+    b = np.array([0.1, -0.05, 0.02, 0.5])
+    T = np.array([0.0, 0.3, 0.6, 1.0]) + np.arange(R)[:, None] * b
+    loss, g = OL.tf_prior(T, lam)
+    assert loss == pytest.approx(lam * (b ** 2).sum() / 4.0, rel=1e-12)
+    assert np.abs(g[1:-1]).max() < 1e-15                     # second differences vanish
+    assert np.allclose(g[0], -2 * lam * b / (4 * (R - 1))) and np.allclose(g[-1], -g[0])
+    T = np.random.default_rng(60).normal(size=(R, 4))
+    assert np.allclose(OL.tf_prior(T, lam)[1], _fd(lambda t: OL.tf_prior(t, lam)[0], T),
+                       atol=1e-8)
+
+
+def test_volume_prior_closed_forms_and_finite_differences():
+    lam = 0.5
+    nz, ny, nx = 4, 5, 6
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    V = 0.3 + 0.2 * x
+    loss, g = OL.volume_prior(V, lam)
+    pairs = (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
+    assert loss == pytest.approx(lam * (nx - 1) * ny * nz * 0.04 / pairs, rel=1e-12)
+    assert np.abs(g[:, :, 1:-1]).max() < 1e-15              # affine: zero inside
+    V = np.random.default_rng(61).normal(size=(3, 4, 5))
+    assert np.allclose(OL.volume_prior(V, lam)[1], _fd(lambda v: OL.volume_prior(v, lam)[0], V),
+                       atol=1e-8)
+
+
+def test_opacity_entropy_closed_forms_invariance_and_finite_differences():
+    N = 37
+    H, g = OL.opacity_entropy(np.full(N, 0.3))
+    assert H == pytest.approx(-1.0, rel=1e-14)                # uniform: log2(1/N)/log2 N
+    assert np.abs(g).max() < 1e-15                             # the uniform point is stationary
+    one = np.zeros(N); one[5] = 0.7
+    assert OL.opacity_entropy(one)[0] == 0.0                   # one-hot: 1 log 1 = 0
+    x = np.random.default_rng(62).uniform(0.05, 1.0, (5, 7))
+    H, g = OL.opacity_entropy(x)
+    assert OL.opacity_entropy(3.0 * x)[0] == pytest.approx(H, rel=1e-13)   # scale-free
+    assert abs((x * g).sum()) < 1e-12                          # Euler: degree-0 homogeneous
+    assert np.allclose(g, _fd(lambda a: OL.opacity_entropy(a)[0], x), atol=1e-8)
+
+
+def test_adam_first_step_and_clamp():
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    x0 = np.array([0.2, 0.4, 0.6, 0.8])
+    x, m, v = OL.adam_step(x0[:3], g[:3], np.zeros(3), np.zeros(3), 1, lr=0.1, eps=0.0)
+    # t = 1: bias-corrected moments are g and g^2, the step is lr sign(g)
+    assert np.allclose(x, x0[:3] - 0.1 * np.sign(g[:3]), rtol=1e-14)
+    x, m, v = OL.adam_step(x0, g, np.zeros(4), np.zeros(4), 1, lr=0.1)
+    assert x[3] == x0[3]                      # no gradient, no move
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    x, _, _ = OL.adam_step(x0, g, np.zeros(4), np.zeros(4), 1, lr=0.5, eps=1e-8, lo=0.0, hi=1.0)
+    assert x.min() >= 0.0 and x.max() <= 1.0 and x[0] == 0.0
+    assert x[1] == pytest.approx(0.9, rel=1e-8)
+
+
+def test_resample_reproduces_affine_fields_and_matches_trilinear():
+    nz, ny, nx = 5, 4, 6
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    V = 0.1 + 0.2 * x - 0.3 * y + 0.05 * z
+    out = OL.resample(V, (9, 7, 11))
+    Z, Y, X = np.meshgrid(np.arange(9) * 4 / 8, np.arange(7) * 3 / 6, np.arange(11) * 5 / 10,
+                          indexing="ij")
+    assert np.allclose(out, 0.1 + 0.2 * X - 0.3 * Y + 0.05 * Z, atol=1e-14)
+    assert np.allclose(OL.resample(V, V.shape), V, rtol=1e-15, atol=1e-15)
+    # random field: against the renderer oracle's trilinear at the same points
+    W = np.random.default_rng(63).normal(size=(5, 4, 6))
+    out = OL.resample(W, (8, 9, 7))
+    h = 2.0 / (6 - 1)
+    bmin = -0.5 * (np.array([6, 4, 5]) - 1) * h
+    for (k, j, i) in [(0, 0, 0), (7, 8, 6), (3, 4, 2), (5, 1, 6), (2, 7, 3)]:
+        q = np.array([i * 5 / 6, j * 3 / 8, k * 4 / 7])       # input grid units (x, y, z)
+        assert out[k, j, i] == pytest.approx(oracle.trilinear(W, bmin + q * h), abs=1e-12)
