@@ -123,6 +123,13 @@ typedef enum {
  *              float rounding; kept as the straightforward baseline.  (The
  *              colour model always gathers directly; it ignores PLAIN.) */
 #define DDVR_LAUNCH_PLAIN 0x10
+/* Loss of the fused passes (render_fused_l2, batch pass 2):
+ *   LOSS_L1    loss = loss_scale * sum |image - target|, upstream gradient
+ *              loss_scale * sign(image - target) (0 where equal): the L1 image
+ *              loss of eq. (tf-loss) with loss_scale = 1/(N W H).  Without it
+ *              the loss is L2, loss_scale * sum (image - target)^2.  Other
+ *              passes ignore the bit. */
+#define DDVR_LOSS_L1 0x20
 
 /* A scalar grid: data -> [nz][ny][nx] values of `dtype` (device). */
 typedef struct {
@@ -255,8 +262,9 @@ int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
                         const ddvr_grads* grads, int32_t flags, void* workspace,
                         size_t workspace_bytes, int32_t* n_fallback_rays, void* hip_stream);
 
-/* Fused forward -> L2 loss gradient -> adjoint of one view, one launch
- * (pixel-local loss only).  loss = loss_scale * sum((image - target)^2).
+/* Fused forward -> loss gradient -> adjoint of one view, one launch
+ * (pixel-local loss only).  loss = loss_scale * sum((image - target)^2), or
+ * loss_scale * sum |image - target| with DDVR_LOSS_L1 in flags.
  *   target      layout of `image`.
  *   image, transmittance  written as by render_forward (transmittance may be
  *               NULL unless the fallback path is possible).
@@ -341,6 +349,53 @@ int ddvr_density_from_color(const ddvr_volume* color, const ddvr_tf* tf, const f
 /* Largest extinction (channel 3) of a colour volume: *out (device, one float)
  * is written (-inf for an empty volume). */
 int ddvr_color_tau_max(const ddvr_volume* color, float* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * The reconstruction loop around the renderer (Sec. 5.1-5.3): priors, the
+ * opacity entropy, the optimiser and the multi-resolution resampling.  All
+ * pointers are device pointers; gradients and losses ACCUMULATE (+=).
+ * ------------------------------------------------------------------------ */
+/* TF smoothing prior of eq. (tf-loss): loss_out (one double, or NULL) +=
+ * lambda/(4(R-1)) sum_c sum_r (T[r+1][c] - T[r][c])^2, d_tf ([R][4], or NULL)
+ * += its gradient.  tf [R][4], 2 <= R <= 2^24. */
+int ddvr_tf_prior(const float* tf, int32_t R, float lambda, float* d_tf, double* loss_out,
+                  void* hip_stream);
+
+/* The same prior on a density grid in 3D (Sec. 5.3): loss_out += lambda times
+ * the mean over all pairs of grid neighbours along x, y and z of the squared
+ * difference; d_volume += its gradient.  volume, d_volume [nz][ny][nx]
+ * float32 (the master copy); sizes >= 1 with at least one pair. */
+int ddvr_volume_prior(const float* volume, int32_t nx, int32_t ny, int32_t nz, float lambda,
+                      float* d_volume, double* loss_out, void* hip_stream);
+
+/* Opacity entropy of Sec. 5.1, OE = H(alpha) over the npix alphas of an
+ * image, H(x) = 1/log2(N) sum p_i log2 p_i, p_i = x_i / sum x (0 log 0 = 0).
+ *   image     [npix][channels] float32, channels 4 (alpha = channel 3) or 1.
+ *   work      two doubles of scratch (overwritten).
+ *   value_out one double, written (or NULL).
+ *   d_image   layout of image, or NULL: += scale * dOE/dalpha on the alpha
+ *             channel; pixels with alpha = 0 (unbounded derivative) get none.
+ * The alphas must not all be zero (the entropy is then undefined). */
+int ddvr_opacity_entropy(const float* image, int64_t npix, int32_t channels, double* work,
+                         double* value_out, float* d_image, float scale, void* hip_stream);
+
+/* One Adam step (Kingma and Ba 2014) on n float32 parameters, step t >= 1:
+ *   m = beta1 m + (1-beta1) g;  v = beta2 v + (1-beta2) g^2;
+ *   param -= lr (m/(1-beta1^t)) / (sqrt(v/(1-beta2^t)) + eps), then clamped to
+ *   [lo, hi] (pass -inf / +inf for none).
+ * Fused into the same pass: store (or NULL) gets the new parameters in
+ * store_dtype (round to nearest even, as ddvr_cast_volume), and grad is
+ * zeroed when zero_grad != 0. */
+int ddvr_adam_step(float* param, float* grad, float* m, float* v, int64_t n, int32_t t,
+                   float lr, float beta1, float beta2, float eps, float lo, float hi, void* store,
+                   int32_t store_dtype, int32_t zero_grad, void* hip_stream);
+
+/* Trilinear resampling of a vertex grid onto another spanning the same box
+ * (the multi-resolution schedule of Sec. 5.3): destination vertex i of an
+ * axis sits at i (s-1)/(d-1) source grid units.  src [sz][sy][sx], dst
+ * [dz][dy][dx] float32; every size >= 2; src and dst must not overlap. */
+int ddvr_resample_volume(const float* src, int32_t sx, int32_t sy, int32_t sz, float* dst,
+                         int32_t dx, int32_t dy, int32_t dz, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many views of one or several grids in ONE launch.

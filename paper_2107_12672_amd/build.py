@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddvr.so")
-SOURCES = ["ddvr_kernels.hip", "ddvr_dfc.hip", "ddvr_api.hip"]
+SOURCES = ["ddvr_kernels.hip", "ddvr_dfc.hip", "ddvr_train.hip", "ddvr_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -249,7 +249,7 @@ bool needs_fallback(int model, int flags) {
 int validate_flags(int flags) {
   const int mode = flags & DDVR_ADJ_MODE_MASK;
   if (mode > DDVR_ADJ_RESIDUAL) return fail(DDVR_ERR_VALUE, "unknown adjoint mode %d", mode);
-  if (flags & ~(DDVR_ADJ_MODE_MASK | DDVR_LAUNCH_PLAIN))
+  if (flags & ~(DDVR_ADJ_MODE_MASK | DDVR_LAUNCH_PLAIN | DDVR_LOSS_L1))
     return fail(DDVR_ERR_VALUE, "unknown flag bits 0x%x", flags);
   return DDVR_OK;
 }
@@ -693,6 +693,81 @@ int ddvr_color_tau_max(const ddvr_volume* color, float* out, void* hip_stream) {
       (hipError_t)launch_color_tau_max(color->data, color->dtype, nvox, out, hip_stream);
   if (e != hipSuccess) return hip_fail(e, "tau-max launch");
   return DDVR_OK;
+}
+
+int ddvr_tf_prior(const float* tf, int32_t R, float lambda, float* d_tf, double* loss_out,
+                  void* hip_stream) {
+  if (!tf) return fail(DDVR_ERR_NULL, "tf is NULL");
+  if (R < 2 || R > (1 << 24)) return fail(DDVR_ERR_SHAPE, "R=%d not in [2, 2^24]", R);
+  if (!std::isfinite(lambda)) return fail(DDVR_ERR_VALUE, "lambda is not finite");
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const hipError_t e = (hipError_t)launch_tf_prior(tf, R, lambda, d_tf, loss_out, hip_stream);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "tf prior launch");
+}
+
+int ddvr_volume_prior(const float* volume, int32_t nx, int32_t ny, int32_t nz, float lambda,
+                      float* d_volume, double* loss_out, void* hip_stream) {
+  if (!volume) return fail(DDVR_ERR_NULL, "volume is NULL");
+  if (nx < 1 || ny < 1 || nz < 1 || (nx < 2 && ny < 2 && nz < 2) ||
+      (int64_t)nx * ny * nz > ((int64_t)1 << 34))
+    return fail(DDVR_ERR_SHAPE, "grid %dx%dx%d", nx, ny, nz);
+  if (!std::isfinite(lambda)) return fail(DDVR_ERR_VALUE, "lambda is not finite");
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const hipError_t e =
+      (hipError_t)launch_volume_prior(volume, nx, ny, nz, lambda, d_volume, loss_out, hip_stream);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "volume prior launch");
+}
+
+int ddvr_opacity_entropy(const float* image, int64_t npix, int32_t channels, double* work,
+                         double* value_out, float* d_image, float scale, void* hip_stream) {
+  if (!image || !work) return fail(DDVR_ERR_NULL, "image or work is NULL");
+  if (npix < 2) return fail(DDVR_ERR_SHAPE, "need at least 2 pixels");
+  if (channels != 1 && channels != 4) return fail(DDVR_ERR_VALUE, "channels must be 1 or 4");
+  if (!std::isfinite(scale)) return fail(DDVR_ERR_VALUE, "scale is not finite");
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const hipError_t e = (hipError_t)launch_opacity_entropy(
+      image, npix, channels, channels == 4 ? 3 : 0, work, value_out, d_image, scale, hip_stream);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "opacity entropy launch");
+}
+
+int ddvr_adam_step(float* param, float* grad, float* m, float* v, int64_t n, int32_t t,
+                   float lr, float beta1, float beta2, float eps, float lo, float hi, void* store,
+                   int32_t store_dtype, int32_t zero_grad, void* hip_stream) {
+  if (!param || !grad || !m || !v) return fail(DDVR_ERR_NULL, "param, grad, m or v is NULL");
+  if (n < 0) return fail(DDVR_ERR_SHAPE, "n < 0");
+  if (t < 1) return fail(DDVR_ERR_VALUE, "step t must be >= 1");
+  if (!std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps >= 0.0f) || std::isnan(lo) || std::isnan(hi) || lo > hi)
+    return fail(DDVR_ERR_VALUE, "Adam hyper-parameters out of range");
+  if (store && store_dtype != DDVR_F32 && store_dtype != DDVR_F16 && store_dtype != DDVR_BF16)
+    return fail(DDVR_ERR_DTYPE, "unknown store dtype %d", store_dtype);
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)t)));
+  const hipError_t e = (hipError_t)launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, c1,
+                                               c2, lo, hi, store, store_dtype, zero_grad,
+                                               hip_stream);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "Adam launch");
+}
+
+int ddvr_resample_volume(const float* src, int32_t sx, int32_t sy, int32_t sz, float* dst,
+                         int32_t dx, int32_t dy, int32_t dz, void* hip_stream) {
+  if (!src || !dst) return fail(DDVR_ERR_NULL, "src or dst is NULL");
+  if (sx < 2 || sy < 2 || sz < 2 || dx < 2 || dy < 2 || dz < 2 ||
+      (int64_t)dx * dy * dz > ((int64_t)1 << 34) || (int64_t)sx * sy * sz > ((int64_t)1 << 34))
+    return fail(DDVR_ERR_SHAPE, "resample %dx%dx%d -> %dx%dx%d", sx, sy, sz, dx, dy, dz);
+  const char* a = reinterpret_cast<const char*>(src);
+  const char* b = reinterpret_cast<const char*>(dst);
+  if (a < b + (int64_t)dx * dy * dz * 4 && b < a + (int64_t)sx * sy * sz * 4)
+    return fail(DDVR_ERR_VALUE, "src and dst overlap");
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const hipError_t e = (hipError_t)launch_resample(src, sx, sy, sz, dst, dx, dy, dz, hip_stream);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "resample launch");
 }
 
 int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, float step_world,

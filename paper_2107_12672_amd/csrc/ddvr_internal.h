@@ -110,6 +110,17 @@ int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, s
 int launch_color(const LaunchParams& p, int pass, int dtype, int slab, size_t lds_bytes,
                  void* stream);
 int launch_cast(const float* src, void* dst, int dtype, int64_t n, void* stream);
+// implemented in ddvr_train.hip
+int launch_tf_prior(const float* tf, int R, float lam, float* dtf, double* loss, void* stream);
+int launch_volume_prior(const float* V, int nx, int ny, int nz, float lam, float* dV,
+                        double* loss, void* stream);
+int launch_opacity_entropy(const float* img, int64_t n, int stride, int offset, double* work,
+                           double* value, float* dimg, float scale, void* stream);
+int launch_adam(float* x, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                float eps, float c1, float c2, float lo, float hi, void* store, int store_dtype,
+                int zero_grad, void* stream);
+int launch_resample(const float* src, int sx, int sy, int sz, float* dst, int dx, int dy,
+                    int dz, void* stream);
 // implemented in ddvr_dfc.hip
 int launch_density_from_color(const DfcParams& p, int dtype, void* stream);
 int launch_color_tau_max(const void* cv, int dtype, int64_t nvox, float* out, void* stream);

@@ -299,6 +299,19 @@ __device__ __forceinline__ void tf_eval(const float4* tf, int R, float d, TFv& s
   s.tau = fmaf(s.phi, b.w - a.w, a.w);
 }
 
+// Pixel-local loss of the fused pass and its upstream gradient: L2
+// (loss_scale (x - y)^2, seed 2 loss_scale (x - y)) or, with DDVR_LOSS_L1, the
+// L1 loss of eq. (tf-loss) (loss_scale |x - y|, seed loss_scale sign(x - y),
+// 0 where x = y).  `acc` collects the unscaled loss.
+__device__ __forceinline__ float loss_seed(bool l1, float scale, float dlt, float& acc) {
+  if (l1) {
+    acc += fabsf(dlt);
+    return dlt > 0.0f ? scale : (dlt < 0.0f ? -scale : 0.0f);
+  }
+  acc = fmaf(dlt, dlt, acc);
+  return 2.0f * scale * dlt;
+}
+
 // ---------------------------------------------------------------------------
 // workgroup helpers
 // ---------------------------------------------------------------------------
@@ -988,8 +1001,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
       if (valid) {
         for (int ch = 0; ch < C; ++ch) {
           const float dlt = out[ch] - vd.target[pix * C + ch];
-          loss = fmaf(dlt, dlt, loss);
-          gimg[ch] = 2.0f * p.loss_scale * dlt;
+          gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale, dlt, loss);
         }
       }
       if (p.loss_out) {
@@ -1502,7 +1514,10 @@ __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
     const int C = EA ? 4 : 1;
     float gimg[4];
     for (int ch = 0; ch < C; ++ch) {
-      if (FUSED) gimg[ch] = 2.0f * p.loss_scale * (vd.image[pix * C + ch] - vd.target[pix * C + ch]);
+      float unused = 0.0f;
+      if (FUSED)
+        gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale,
+                             vd.image[pix * C + ch] - vd.target[pix * C + ch], unused);
       else gimg[ch] = vd.d_image[pix * C + ch];
     }
     const float4* tfl = reinterpret_cast<const float4*>(vd.tf);
@@ -1752,8 +1767,7 @@ __global__ __launch_bounds__(256) void k_color(const LaunchParams p) {
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch) {
         const float dlt = out[ch] - vd.target[pix * 4 + ch];
-        loss = fmaf(dlt, dlt, loss);
-        gimg[ch] = 2.0f * p.loss_scale * dlt;
+        gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale, dlt, loss);
       }
     }
     if (p.loss_out) {
@@ -2163,8 +2177,7 @@ __global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch) {
         const float dlt = out[ch] - vd.target[pix * 4 + ch];
-        loss = fmaf(dlt, dlt, loss);
-        gimg[ch] = 2.0f * p.loss_scale * dlt;
+        gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale, dlt, loss);
       }
     }
     if (p.loss_out) {

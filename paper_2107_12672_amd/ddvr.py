@@ -22,6 +22,7 @@ F32, F16, BF16 = 0, 1, 2
 ABSORPTION, EMISSION_ABSORPTION, COLOR = 0, 1, 2
 ADJ_AUTO, ADJ_INVERT_T, ADJ_INVERT_ALPHA, ADJ_CHECKPOINT, ADJ_RESIDUAL = 0, 1, 2, 3, 4
 LAUNCH_PLAIN = 0x10
+LOSS_L1 = 0x20
 PASS_FORWARD, PASS_ADJOINT, PASS_FUSED = 0, 1, 2
 
 EXPORTED = [
@@ -31,7 +32,8 @@ EXPORTED = [
     "ddvr_batch_workspace_size", "ddvr_batch_run", "ddvr_batch_run_graph",
     "ddvr_batch_sample_count", "ddvr_cast_volume", "ddvr_set_tuning", "ddvr_get_tuning",
     "ddvr_render_tangent", "ddvr_camera_sphere_tangents", "ddvr_density_from_color",
-    "ddvr_color_tau_max",
+    "ddvr_color_tau_max", "ddvr_tf_prior", "ddvr_volume_prior", "ddvr_opacity_entropy",
+    "ddvr_adam_step", "ddvr_resample_volume",
 ]
 MAX_DIRECTIONS = 4
 
@@ -117,6 +119,12 @@ def lib():
         "ddvr_density_from_color": ([P, P, P, F, F, ctypes.c_uint64, I32, I32, P, P, P, P],
                                     ctypes.c_int),
         "ddvr_color_tau_max": ([P, P, P], ctypes.c_int),
+        "ddvr_tf_prior": ([P, I32, F, P, P, P], ctypes.c_int),
+        "ddvr_volume_prior": ([P, I32, I32, I32, F, P, P, P], ctypes.c_int),
+        "ddvr_opacity_entropy": ([P, ctypes.c_int64, I32, P, P, P, F, P], ctypes.c_int),
+        "ddvr_adam_step": ([P, P, P, P, ctypes.c_int64, I32, F, F, F, F, F, F, P, I32, I32, P],
+                           ctypes.c_int),
+        "ddvr_resample_volume": ([P, I32, I32, I32, P, I32, I32, I32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -370,3 +378,49 @@ def density_from_color(color, tf, d_out, d_prev=None, alpha=None, beta: float = 
         ctypes.c_uint64(seed), int(sweep), int(ncand), _ptr(d_out), _ptr(cost_out),
         _ptr(n_changed), _stream(stream)))
     return alpha
+
+
+# ---------------------------------------------------------------------------
+# the reconstruction loop (Sec. 5.1-5.3)
+# ---------------------------------------------------------------------------
+def tf_prior(tf, lam: float, d_tf=None, loss_out=None, stream=None):
+    """loss_out += lam L_prior(tf), d_tf += its gradient (device tensors)."""
+    assert tf.is_contiguous() and tf.dim() == 2 and tf.shape[1] == 4
+    _check(lib().ddvr_tf_prior(_ptr(tf), tf.shape[0], float(lam), _ptr(d_tf), _ptr(loss_out),
+                               _stream(stream)))
+
+
+def volume_prior(volume, lam: float, d_volume=None, loss_out=None, stream=None):
+    """The smoothing prior on a [nz][ny][nx] float32 grid in 3D."""
+    assert volume.is_contiguous() and volume.dim() == 3
+    nz, ny, nx = volume.shape
+    _check(lib().ddvr_volume_prior(_ptr(volume), nx, ny, nz, float(lam), _ptr(d_volume),
+                                   _ptr(loss_out), _stream(stream)))
+
+
+def opacity_entropy(image, work, value_out=None, d_image=None, scale: float = 1.0, stream=None):
+    """OE of an [H][W][4] (alpha = channel 3) or [H][W] image; work: 2 float64."""
+    ch = 4 if (image.dim() == 3 and image.shape[-1] == 4) else 1
+    _check(lib().ddvr_opacity_entropy(_ptr(image), image.numel() // ch, ch, _ptr(work),
+                                      _ptr(value_out), _ptr(d_image), float(scale),
+                                      _stream(stream)))
+
+
+def adam_step(param, grad, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, lo: float = float("-inf"), hi: float = float("inf"),
+              store=None, zero_grad: bool = False, stream=None):
+    """One fused Adam step on float32 tensors (optionally writing the storage
+    copy `store` and zeroing `grad`)."""
+    st = dtype_code(store) if store is not None else F32
+    _check(lib().ddvr_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), int(t),
+                                float(lr), float(beta1), float(beta2), float(eps), float(lo),
+                                float(hi), _ptr(store), st, 1 if zero_grad else 0,
+                                _stream(stream)))
+
+
+def resample_volume(src, dst, stream=None):
+    """Trilinear resampling of src [sz][sy][sx] onto dst [dz][dy][dx] (float32)."""
+    sz, sy, sx = src.shape
+    dz, dy, dx = dst.shape
+    _check(lib().ddvr_resample_volume(_ptr(src), sx, sy, sz, _ptr(dst), dx, dy, dz,
+                                      _stream(stream)))

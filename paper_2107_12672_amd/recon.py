@@ -1,0 +1,144 @@
+"""Multi-resolution density reconstruction from images (Sec. 5.3), driven
+entirely through the library's entry points: every step of the loop runs in
+the HIP kernels; this module only sequences the calls.
+
+Per optimiser step, on a batch of views:
+  1. one fused launch per batch: forward, L1 image loss of eq. (tf-loss) and
+     its upstream gradient, adjoint into the density gradient (batch pass 2,
+     ``DDVR_LOSS_L1``, replayed from a HIP graph);
+  2. the smoothing prior on the densities in 3D (``ddvr_volume_prior``);
+  3. one Adam step on the float32 master grid, clamped to [0, inf), fused with
+     the bf16 storage copy the renderer reads and the clearing of the
+     gradient (``ddvr_adam_step``).
+The grid starts at `start`^3 vertices and doubles its resolution per axis
+after `steps_per_level` steps (``ddvr_resample_volume``), up to `final`^3,
+where `final_steps` steps are taken.
+
+Readings (the paper is silent): an "iteration" of the schedule is one
+optimiser step on one batch (the views are visited in order, batch after
+batch); Adam's moments restart at every level; densities are clamped at 0.
+
+`Reconstructor` plans every level's batches and allocates its buffers once;
+`run()` then executes the schedule from a zero grid.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List
+
+from . import ddvr as d
+
+
+@dataclass
+class Schedule:
+    start: int = 32
+    final: int = 256
+    steps_per_level: int = 10
+    final_steps: int = 50
+    batch: int = 8
+    lr: float = 0.3
+    prior: float = 0.5
+    step_vox: float = 0.2
+
+    def levels(self) -> List[int]:
+        out, n = [], self.start
+        while n < self.final:
+            out.append(n)
+            n *= 2
+        out.append(self.final)
+        return out
+
+    def total_steps(self) -> int:
+        return self.steps_per_level * (len(self.levels()) - 1) + self.final_steps
+
+
+@dataclass
+class Result:
+    steps: int = 0
+    samples: int = 0
+    losses: object = None      # [steps] float64 device tensor: L1 + prior of every step
+    volume: object = None      # the float32 master grid at the end
+
+
+class _Level:
+    def __init__(self, n, targets, cams, sched, stream):
+        import torch
+        dev = targets.device
+        nview, H, W = targets.shape
+        shape = (n, n, n)
+        self.n = n
+        self.master = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.store = torch.zeros(shape, dtype=torch.bfloat16, device=dev)
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.images = torch.empty((nview, H, W), device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        step_world = sched.step_vox * 2.0 / (n - 1)
+        self.batches = []
+        for b0 in range(0, nview, sched.batch):
+            idx = range(b0, min(nview, b0 + sched.batch))
+            views = [d.make_view(0, cams[i], step_world, self.images[i], target=targets[i])
+                     for i in idx]
+            b = d.Batch([self.store], None, views, d.ABSORPTION, flags=d.LOSS_L1,
+                        d_volumes=[self.grad], stream=stream)
+            self.batches.append((b, 1.0 / (len(views) * H * W), b.sample_count()))
+
+    def close(self):
+        for b, _, _ in self.batches:
+            b.close()
+
+
+class Reconstructor:
+    def __init__(self, targets, cams, sched: Schedule, stream=None):
+        """targets: [V][H][W] float32 device tensor of absorption-only images;
+        cams: their V cameras."""
+        self.sched = sched
+        self.stream = stream
+        self.levels = [_Level(n, targets, cams, sched, stream) for n in sched.levels()]
+
+    def run(self, on_step=None) -> Result:
+        import torch
+        sched, s = self.sched, self.stream
+        res = Result()
+        res.losses = torch.zeros(sched.total_steps(), dtype=torch.float64,
+                                 device=self.levels[0].master.device)
+        prev = None
+        for li, L in enumerate(self.levels):
+            if prev is None:
+                L.master.zero_()
+            else:
+                d.resample_volume(prev.master, L.master, s)
+            d.cast_volume(L.master, L.store, s)
+            L.grad.zero_()
+            L.m.zero_()
+            L.v.zero_()
+            steps = sched.final_steps if L.n == sched.final else sched.steps_per_level
+            for t in range(1, steps + 1):
+                b, scale, samples = L.batches[(t - 1) % len(L.batches)]
+                L.loss.zero_()
+                b.run(d.PASS_FUSED, scale, L.loss, graph=True, stream=s)
+                d.volume_prior(L.master, sched.prior, L.grad, L.loss, s)
+                d.adam_step(L.master, L.grad, L.m, L.v, t, sched.lr, lo=0.0, store=L.store,
+                            zero_grad=True, stream=s)
+                res.losses[res.steps:res.steps + 1].copy_(L.loss)
+                res.samples += samples
+                res.steps += 1
+                if on_step is not None:
+                    on_step(li, t, L.loss)
+            prev = L
+        res.volume = self.levels[-1].master
+        return res
+
+    def close(self):
+        for L in self.levels:
+            L.close()
+
+
+def reconstruct(targets, cams, sched: Schedule, stream=None, on_step=None) -> Result:
+    """Plan, run the schedule once, release the batches."""
+    r = Reconstructor(targets, cams, sched, stream)
+    try:
+        return r.run(on_step)
+    finally:
+        r.close()

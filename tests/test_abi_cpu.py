@@ -289,3 +289,38 @@ def test_density_from_color_validation():
     assert f(B(d.Volume(0x1008, d.F32, 8, 8, 8)), B(tf), None, 1.0, 1.0, 0, 0, 256, out, None,
              None, None) == d.ERR_VALUE       # 4-channel data must be 16-byte aligned
     assert L.ddvr_color_tau_max(B(vol), None, None) == d.ERR_NULL
+
+
+def test_training_loop_validation():
+    d = _ddvr()
+    L = d.lib()
+    inf = float("inf")
+    assert L.ddvr_tf_prior(None, 8, 0.4, None, None, None) == d.ERR_NULL
+    assert L.ddvr_tf_prior(0x1000, 1, 0.4, None, None, None) == d.ERR_SHAPE
+    assert L.ddvr_tf_prior(0x1000, 8, float("nan"), None, None, None) == d.ERR_VALUE
+    assert L.ddvr_volume_prior(0x1000, 1, 1, 1, 0.5, None, None, None) == d.ERR_SHAPE
+    assert L.ddvr_opacity_entropy(0x1000, 100, 3, 0x2000, None, None, 1.0, None) == d.ERR_VALUE
+    assert L.ddvr_opacity_entropy(0x1000, 1, 4, 0x2000, None, None, 1.0, None) == d.ERR_SHAPE
+    assert L.ddvr_opacity_entropy(0x1000, 100, 4, None, None, None, 1.0, None) == d.ERR_NULL
+    A = L.ddvr_adam_step
+    assert A(0x1000, 0x2000, 0x3000, 0x4000, 10, 0, 0.1, 0.9, 0.999, 1e-8, -inf, inf, None, 0, 0,
+             None) == d.ERR_VALUE                              # t = 0
+    assert A(0x1000, 0x2000, 0x3000, 0x4000, 10, 1, 0.1, 1.0, 0.999, 1e-8, -inf, inf, None, 0, 0,
+             None) == d.ERR_VALUE                              # beta1 = 1
+    assert A(0x1000, 0x2000, 0x3000, 0x4000, 10, 1, 0.1, 0.9, 0.999, 1e-8, 1.0, 0.0, None, 0, 0,
+             None) == d.ERR_VALUE                              # lo > hi
+    assert A(0x1000, 0x2000, 0x3000, 0x4000, 10, 1, 0.1, 0.9, 0.999, 1e-8, -inf, inf, 0x5000, 7,
+             0, None) == d.ERR_DTYPE
+    assert A(0x1000, None, 0x3000, 0x4000, 10, 1, 0.1, 0.9, 0.999, 1e-8, -inf, inf, None, 0, 0,
+             None) == d.ERR_NULL
+    R = L.ddvr_resample_volume
+    assert R(0x1000, 1, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_SHAPE
+    assert R(0x1000, 4, 4, 4, 0x1010, 8, 8, 8, None) == d.ERR_VALUE       # overlap
+    assert R(None, 4, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_NULL
+    # the L1 loss bit is a valid flag of the fused pass
+    vol, tf, cam = _descs(d)
+    B = ctypes.byref
+    g = d.Grads(0x5000, None, None, None)
+    assert L.ddvr_render_fused_l2(B(vol), B(tf), B(cam), 0.1, 1, 0x3000, 1.0, 0x4000, 0x4100,
+                                  B(g), d.LOSS_L1 | 0x100, None, 0, None, None,
+                                  None) == d.ERR_VALUE

@@ -1,0 +1,242 @@
+"""The reconstruction loop's kernels (Sec. 5.1-5.3) on the GPU against the
+FP64 reference of `oracle.losses` and the renderer oracle, on the same seeded
+inputs: the L1 loss of the fused passes, the TF and 3D smoothing priors, the
+opacity entropy, the fused Adam step and the multi-resolution resampling.
+
+Tolerances: float32 elementwise kernels within 1e-5 relative of the FP64
+value (1e-6 absolute for the resampling); the losses, accumulated in float64
+on the GPU, within 1e-6 relative; the fused L1 passes to the renderer's
+parity tolerances (harness).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import losses as OL
+from harness import (assert_dv_close, assert_grad_close, device_volume, gpu_camera, kink_mask,
+                     oracle_adjoint, oracle_forward, tie_mask)
+from test_gpu_parity import c1_problem, ea_problem
+from test_gpu_color import color_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype or np.float32)).cuda()
+
+
+def test_tf_prior_matches_reference():
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    rng = np.random.default_rng(70)
+    for R in (2, 64, 300):
+        _say(f"tf prior R={R}")
+        T = synth.random_tf(R, rng, 8.0)
+        tf = _t(T)
+        g = torch.zeros_like(tf)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        d.tf_prior(tf, 0.4, g, loss)
+        torch.cuda.synchronize()
+        ref_l, ref_g = OL.tf_prior(T, 0.4)
+        assert float(loss.item()) == pytest.approx(ref_l, rel=1e-6)
+        assert np.allclose(g.cpu().numpy(), ref_g, rtol=1e-5, atol=1e-6 * np.abs(ref_g).max())
+
+
+def test_volume_prior_matches_reference():
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    rng = np.random.default_rng(71)
+    for shape in ((23, 29, 37), (2, 1, 5)):
+        _say(f"volume prior {shape}")
+        V = rng.uniform(0, 1, shape).astype(np.float32)
+        vd = _t(V)
+        ref_l, ref_g = OL.volume_prior(V, 0.5)
+        g0 = float(np.abs(ref_g).max())        # accumulates (+=) onto a value of its scale
+        g = torch.full_like(vd, g0)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        d.volume_prior(vd, 0.5, g, loss)
+        torch.cuda.synchronize()
+        assert float(loss.item()) == pytest.approx(ref_l, rel=1e-6)
+        assert np.allclose(g.cpu().numpy().astype(np.float64) - g0, ref_g, rtol=1e-4,
+                           atol=1e-5 * g0)
+
+
+@pytest.mark.parametrize("channels", [4, 1])
+def test_opacity_entropy_matches_reference(channels):
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    rng = np.random.default_rng(72 + channels)
+    H, W = 45, 61
+    img = rng.uniform(0, 1, (H, W, channels)).astype(np.float32)
+    img[rng.uniform(size=(H, W)) < 0.2, -1] = 0.0          # rays that miss: alpha 0
+    if channels == 1:
+        img = img[..., 0]
+    _say(f"opacity entropy channels={channels}")
+    x = _t(img)
+    work = torch.zeros(2, dtype=torch.float64, device="cuda")
+    val = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(x)
+    d.opacity_entropy(x, work, val, g, scale=0.5)
+    torch.cuda.synchronize()
+    alpha = img[..., 3] if channels == 4 else img
+    ref_h, ref_g = OL.opacity_entropy(alpha)
+    assert float(val.item()) == pytest.approx(ref_h, rel=1e-9)
+    got = g.cpu().numpy()
+    got_a = got[..., 3] if channels == 4 else got
+    assert np.allclose(got_a, 0.5 * ref_g, rtol=1e-5, atol=1e-6 * np.abs(ref_g).max())
+    if channels == 4:
+        assert not got[..., :3].any()                        # colour unused
+
+
+def test_adam_step_matches_reference_and_fuses_cast_and_zeroing():
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    rng = np.random.default_rng(73)
+    n = 4099                                   # not a multiple of 4: ragged tail
+    x = rng.uniform(0, 1, n).astype(np.float32)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    xd, md, vd = _t(x), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    store = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    xr = x.astype(np.float64)
+    for t in (1, 2, 3):
+        _say(f"adam t={t}")
+        gn = rng.normal(size=n).astype(np.float32)
+        gd = _t(gn)
+        d.adam_step(xd, gd, md, vd, t, lr=0.3, lo=0.0, hi=1.0, store=store, zero_grad=True)
+        torch.cuda.synchronize()
+        # the reference takes the hyper-parameters the kernel receives (float32)
+        xr, m, v = OL.adam_step(xr, gn, m, v, t, lr=float(np.float32(0.3)),
+                                beta1=float(np.float32(0.9)), beta2=float(np.float32(0.999)),
+                                eps=float(np.float32(1e-8)), lo=0.0, hi=1.0)
+        assert np.allclose(xd.cpu().numpy(), xr, rtol=1e-5, atol=1e-6)
+        assert np.allclose(md.cpu().numpy(), m, rtol=1e-5, atol=1e-7)
+        assert np.allclose(vd.cpu().numpy(), v, rtol=1e-5, atol=1e-9)
+        assert not gd.any()
+        ref = torch.empty_like(store)
+        d.cast_volume(xd, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(store, ref)
+
+
+def test_resample_matches_reference():
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    rng = np.random.default_rng(74)
+    for src_shape, dst_shape in (((11, 13, 17), (21, 25, 33)), ((32, 32, 32), (64, 64, 64)),
+                                 ((5, 4, 6), (5, 4, 6))):
+        _say(f"resample {src_shape} -> {dst_shape}")
+        V = rng.uniform(0, 1, src_shape).astype(np.float32)
+        out = torch.full(dst_shape, float("nan"), device="cuda")
+        d.resample_volume(_t(V), out)
+        torch.cuda.synchronize()
+        assert np.allclose(out.cpu().numpy(), OL.resample(V, dst_shape), rtol=0, atol=1e-6)
+
+
+def _fused_l1(p, offset_seed):
+    """GPU fused pass with the L1 loss against the oracle adjoint seeded with
+    the L1 gradient of the oracle's image.  The target sits at least 1e-3 away
+    from the image in every element, so both signs agree; on tie and kink rays
+    it equals the GPU's own image, so their seed is exactly zero."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    from harness import gpu_forward
+    ora = oracle_forward(p)
+    rng = np.random.default_rng(offset_seed)
+    off = rng.uniform(1e-3, 0.2, ora["image"].shape) * rng.choice([-1.0, 1.0], ora["image"].shape)
+    target = ora["image"] + off
+    mask = tie_mask(ora["ratio"]) | kink_mask(p)
+    own, _ = gpu_forward(p)
+    target[mask] = own[mask]
+    target = target.astype(np.float32)
+    n = ora["image"].size
+    scale = 1.0 / n
+    vol = device_volume(p)
+    tf = _t(p.tf) if p.tf is not None else None
+    cam = gpu_camera(p)
+    img = torch.zeros(n, device="cuda")
+    tr = torch.zeros(p.H * p.W, device="cuda")
+    dV = torch.zeros(p.volume.shape, device="cuda")
+    dTF = torch.zeros_like(tf) if tf is not None else None
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws_n = d.adjoint_workspace_size(vol, cam, p.step, p.model, 0)
+    ws = torch.zeros(max(ws_n, 4) // 4, dtype=torch.int32, device="cuda")
+    d.render_fused_l2(vol, tf, cam, p.step, p.model, _t(target.ravel()), scale, img, tr,
+                      d.grads_desc(dV, dTF, None, None), flags=d.LOSS_L1, workspace=ws,
+                      loss_out=loss)
+    torch.cuda.synchronize()
+    gimg = img.cpu().numpy().reshape(ora["image"].shape)
+    l_gpu, seed_gpu = OL.l1_loss_and_seed(gimg, target, scale)
+    assert float(loss.item()) == pytest.approx(l_gpu, rel=1e-5)
+    _, seed = OL.l1_loss_and_seed(ora["image"], target, scale)
+    seed[mask] = 0.0
+    assert np.array_equal(seed_gpu, seed)
+    ref = oracle_adjoint(p, seed)
+    assert_dv_close(dV.cpu().double().numpy(), ref["dV"], "L1 dV")
+    if dTF is not None:
+        assert_grad_close(dTF.cpu().numpy(), ref["dTF"], "L1 dTF")
+
+
+@pytest.mark.parametrize("which", ["ao", "ea", "color"])
+def test_fused_l1_loss_matches_oracle(which):
+    _say(f"fused L1 {which}")
+    p = {"ao": lambda: c1_problem()[0], "ea": lambda: ea_problem(W=56, H=44),
+         "color": lambda: color_problem()}[which]()
+    _fused_l1(p, 80)
+
+
+def test_batched_l1_and_reconstruction_loop():
+    """A batch's fused L1 pass adds up its views' single-view L1 gradients;
+    the multi-resolution loop (16^3 -> 32^3, 4 views at 48^2 in batches of
+    2) lowers the loss and moves the grid toward the ground truth."""
+    import math
+    import torch
+    from paper_2107_12672_amd import ddvr as d, recon
+    _say("batched L1 + reconstruction loop")
+    rng = np.random.default_rng(75)
+    gt = synth.blob_volume((32, 32, 32), 5, rng, sigma_vox=(3.0, 6.0), amplitude=0.6)
+    gt_d = _t(gt)
+    views = [(20.0, 10.0), (110.0, -25.0), (200.0, 40.0), (290.0, 0.0)]
+    cams = [d.camera_from_sphere(math.radians(y), math.radians(p_), 2.5, math.radians(60), 48, 48)
+            for y, p_ in views]
+    step = 0.5 * 2.0 / 31
+    targets = torch.empty((4, 48, 48), device="cuda")
+    for i in range(4):
+        d.render_forward(gt_d, None, cams[i], step, d.ABSORPTION, targets[i])
+    # batch L1 gradient == sum of the single-view L1 gradients
+    vol = _t(0.5 * gt + 0.1)
+    g_b = torch.zeros_like(vol)
+    img = torch.empty_like(targets)
+    b = d.Batch([vol], None, [d.make_view(0, cams[i], step, img[i], target=targets[i])
+                              for i in range(4)], d.ABSORPTION, flags=d.LOSS_L1, d_volumes=[g_b])
+    b.run(d.PASS_FUSED, 1.0 / targets.numel())
+    g_s = torch.zeros_like(vol)
+    for i in range(4):
+        d.render_fused_l2(vol, None, cams[i], step, d.ABSORPTION, targets[i],
+                          1.0 / targets.numel(), img[i], None, d.grads_desc(g_s),
+                          flags=d.LOSS_L1)
+    torch.cuda.synchronize()
+    b.close()
+    assert_dv_close(g_b.cpu().double().numpy(), g_s.cpu().double().numpy(), "batch L1", 1e-5)
+    sched = recon.Schedule(start=16, final=32, steps_per_level=6, final_steps=12, batch=2,
+                           lr=0.05, prior=0.5, step_vox=0.5)
+    res = recon.reconstruct(targets, cams, sched)
+    torch.cuda.synchronize()
+    losses = res.losses.cpu().numpy()
+    assert res.steps == 18 and res.volume.shape == (32, 32, 32)
+    assert losses[-2:].mean() < 0.5 * losses[:2].mean(), losses
+    err = float(torch.linalg.vector_norm(res.volume - gt_d) / torch.linalg.vector_norm(gt_d))
+    print(f"[result] reconstruction loss {losses[0]:.4g} -> {losses[-1]:.4g}, "
+          f"relative volume error {err:.3f}", flush=True)
+    assert err < 0.95
+    assert float(res.volume.min()) >= 0.0
