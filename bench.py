@@ -145,6 +145,59 @@ def cpu_baseline(work, n_views_max, budget_s=12.0):
                       f"{samples} samples in {dt:.1f} s"}
 
 
+def cpu_baseline_color(work, volume_np, budget_s=10.0):
+    """FP64 oracle forward + stored-tape adjoint of the colour volume on every
+    16th row and column of successive views until the budget is spent."""
+    import numpy as np
+    import oracle
+    import synth
+    oracle.build(force=False)
+    V = np.asarray(volume_np, np.float64)
+    W = H = work.views[0].width
+    pix = np.array([y * W + x for y in range(0, H, 16) for x in range(0, W, 16)], np.int32)
+    rng = synth.rng_for(9, 8)
+    samples = views = 0
+    t0 = time.perf_counter()
+    for v in work.views:
+        cam = oracle.camera_from_sphere(v.yaw, v.pitch, v.dist, v.fovy, W, H)
+        out = oracle.render(V, None, cam, W, H, work.step_world, oracle.COLOR, pix=pix)
+        g = 2.0 * (out["image"] - rng.uniform(0.0, 1.0, out["image"].shape)) / out["image"].size
+        oracle.adjoint(V, None, cam, W, H, work.step_world, oracle.COLOR, g, pix=pix)
+        samples += int(out["nsamp"].sum())
+        views += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": samples / dt, "unit": "ray-samples/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"fp64 colour-volume forward + stored-tape adjoint, every 16th row and "
+                      f"column ({len(pix)} rays/view) of {views} views, {samples} samples in "
+                      f"{dt:.1f} s"}
+
+
+def cpu_baseline_dfc(CV, tf, prev, alpha, ncand, budget_s=10.0):
+    """FP64 oracle sweep on growing samples of random voxels until the budget
+    is spent."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    nvox = int(np.prod(CV.shape[:3]))
+    rng = np.random.default_rng(5)
+    done = 0
+    t0 = time.perf_counter()
+    k = 4096
+    while time.perf_counter() - t0 < budget_s and done < nvox:
+        sel = rng.choice(nvox, size=min(k, nvox), replace=False)
+        oracle.density_from_color(CV, tf, prev, alpha=alpha, beta=1.0, seed=7, iteration=1,
+                                  ncand=ncand, voxels=sel)
+        done += len(sel)
+        k *= 2
+    dt = time.perf_counter() - t0
+    return {"value": done * ncand / dt, "unit": "candidates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"fp64 sweep of {done} random voxels x {ncand} candidates in {dt:.1f} s"}
+
+
 def _timed(fn, steps, warmup, stream, torch):
     for _ in range(warmup):
         fn()
@@ -292,6 +345,9 @@ def secondary(args):
                                                   images[i], trans[i]) for i in range(nv)],
                         args.steps, args.warmup, stream, torch)
         log(f"color forward only: {fwd_ms:.3f} ms")
+        if not getattr(args, "no_cpu_baseline", False):
+            out["cpu_baseline"] = cpu_baseline_color(w, w.volume)
+            log(f"cpu baseline: {out['cpu_baseline']}")
         out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
                     "value": res["auto"]["value"], "ms_per_step": res["auto"]["ms_per_step"],
                     "config": {"workload": w.name + ", fused L2, colour-volume gradient",
@@ -319,6 +375,11 @@ def secondary(args):
 
         ms = _timed(sweep, args.steps, args.warmup, stream, torch)
         log(f"dfc: {ms:.3f} ms per sweep, {nvox * ncand / (ms * 1e-3):.4g} candidates/s")
+        if not getattr(args, "no_cpu_baseline", False):
+            cv_read = vol.to(torch.float64).cpu().numpy()
+            out["cpu_baseline"] = cpu_baseline_dfc(cv_read, tf.cpu().numpy(),
+                                                   b.cpu().numpy(), alpha, ncand)
+            log(f"cpu baseline: {out['cpu_baseline']}")
         # ALU roofline: VALU lane-operations of the candidate loop (counted in
         # the kernel's assembly) per sweep over its event-timed duration (one
         # launch per sweep, on the timed stream)

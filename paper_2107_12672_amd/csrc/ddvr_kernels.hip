@@ -1904,7 +1904,13 @@ struct ColorAdjL {
   float TK1;        // T^(K-1)
   int ckey;         // LDS byte offset of the current cell's corner 0 (-1: none)
   int64_t gkey;     // vertex index of the current cell's corner 0 (direct slabs)
-  float cg[4][8];   // gradient of the current cell's corners, per channel
+  // gradient of the current cell's corners: the colour channels' gradients
+  // of a sample are one scalar alpha_i T^(i) times the ray's C_hat, so the
+  // cell keeps sum w_c alpha_i T^(i) (ca) and the extinction part (ct) and
+  // multiplies by C_hat (cq: C_hat times the channel's fixed-point scale) on
+  // exit
+  float ca[8], ct[8];
+  float cq[3];
 };
 
 // Add the registered cell gradient to the LDS brick ([vertex][4] floats) or
@@ -1920,15 +1926,21 @@ __device__ __forceinline__ void color_cell_flush(const ViewDesc& vd, const Brick
     const int sy = 4 * br.bx4, sz = 4 * br.bxy4;
     const int off[8] = {0, 16, sy, sy + 16, sz, sz + 16, sz + sy, sz + sy + 16};
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 8; ++k) {
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
+      for (int ch = 0; ch < 3; ++ch) {
         if (FIX)
-          atomicAdd(reinterpret_cast<int*>(p0 + off[k]) + ch, round_i32(s.cg[ch][k] * qs[ch]));
+          atomicAdd(reinterpret_cast<int*>(p0 + off[k]) + ch, round_i32(s.ca[k] * s.cq[ch]));
         else
-          atomicAdd(reinterpret_cast<float*>(p0 + off[k]) + ch, s.cg[ch][k]);
-        s.cg[ch][k] = 0.0f;
+          atomicAdd(reinterpret_cast<float*>(p0 + off[k]) + ch, s.ca[k] * s.cq[ch]);
       }
+      if (FIX)
+        atomicAdd(reinterpret_cast<int*>(p0 + off[k]) + 3, round_i32(s.ct[k] * qs[3]));
+      else
+        atomicAdd(reinterpret_cast<float*>(p0 + off[k]) + 3, s.ct[k]);
+      s.ca[k] = 0.0f;
+      s.ct[k] = 0.0f;
+    }
     s.ckey = -1;
   } else {
     if (s.gkey < 0) return;
@@ -1936,12 +1948,13 @@ __device__ __forceinline__ void color_cell_flush(const ViewDesc& vd, const Brick
     const int64_t off[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
     float* g = vd.dV + 4 * s.gkey;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 8; ++k) {
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        gadd(g + 4 * off[k] + ch, s.cg[ch][k]);
-        s.cg[ch][k] = 0.0f;
-      }
+      for (int ch = 0; ch < 3; ++ch) gadd(g + 4 * off[k] + ch, s.ca[k] * s.Chat[ch]);
+      gadd(g + 4 * off[k] + 3, s.ct[k]);
+      s.ca[k] = 0.0f;
+      s.ct[k] = 0.0f;
+    }
     s.gkey = -1;
   }
 }
@@ -1987,12 +2000,19 @@ __device__ __forceinline__ void color_adj_sample(const ViewDesc& vd, const RayG&
       color_cell_flush<false, false>(vd, br, acc, s, qs);
       s.gkey = vidx;
     }
-    float w8[8];
-    trilerp_weights(c.f, w8);
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) s.cg[ch][k] = fmaf(w8[k], g4[ch], s.cg[ch][k]);
+    // trilinear weights with the two sample factors folded into the x terms
+    const float gy = 1.0f - c.f[1], gz = 1.0f - c.f[2];
+    const float a00 = gy * gz, a10 = c.f[1] * gz, a01 = gy * c.f[2], a11 = c.f[1] * c.f[2];
+    const float w0 = (1.0f - c.f[0]) * wgt, w1 = c.f[0] * wgt;
+    const float t0 = (1.0f - c.f[0]) * g4[3], t1 = c.f[0] * g4[3];
+    s.ca[0] = fmaf(w0, a00, s.ca[0]); s.ca[1] = fmaf(w1, a00, s.ca[1]);
+    s.ca[2] = fmaf(w0, a10, s.ca[2]); s.ca[3] = fmaf(w1, a10, s.ca[3]);
+    s.ca[4] = fmaf(w0, a01, s.ca[4]); s.ca[5] = fmaf(w1, a01, s.ca[5]);
+    s.ca[6] = fmaf(w0, a11, s.ca[6]); s.ca[7] = fmaf(w1, a11, s.ca[7]);
+    s.ct[0] = fmaf(t0, a00, s.ct[0]); s.ct[1] = fmaf(t1, a00, s.ct[1]);
+    s.ct[2] = fmaf(t0, a10, s.ct[2]); s.ct[3] = fmaf(t1, a10, s.ct[3]);
+    s.ct[4] = fmaf(t0, a01, s.ct[4]); s.ct[5] = fmaf(t1, a01, s.ct[5]);
+    s.ct[6] = fmaf(t0, a11, s.ct[6]); s.ct[7] = fmaf(t1, a11, s.ct[7]);
   }
   if (need_xhat) {
     float gp[3] = {0.0f, 0.0f, 0.0f};
@@ -2136,9 +2156,8 @@ __device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const Ra
 }
 
 template <int DT, int PASS, bool XH>
-__global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
+__device__ __forceinline__ void color_lds_tile(const LaunchParams& p, float* smem) {
   constexpr int NT = 256, TW = 16, TH = 16;
-  extern __shared__ __align__(16) float smem[];
   const ViewDesc& vd = p.one;
   const int vcap = p.lds_cap;          // vertices per brick (4 floats each)
   float* acc = smem;
@@ -2217,9 +2236,7 @@ __global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
   s.ckey = -1;
   s.gkey = -1;
 #pragma unroll
-  for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s.cg[ch][k] = 0.0f;
+  for (int k = 0; k < 8; ++k) s.ca[k] = s.ct[k] = 0.0f;
   AdjState x;
   x.xo_hat[0] = x.xo_hat[1] = x.xo_hat[2] = 0.0;
   x.si[0] = x.si[1] = x.si[2] = 0.0;
@@ -2271,6 +2288,8 @@ __global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
       }
     }
   }
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) s.cq[ch] = s.Chat[ch] * (fix_ok ? qs[ch] : 1.0f);
   if (fix_ok)
     color_adjoint_slabs<DT, true, XH>(vd, r, tx, ty, Nadj, acc, iscratch, vcap,
                                       gmask, need_xhat, want_dv, s, x, qs, inv_qs);
@@ -2288,6 +2307,13 @@ __global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
       if ((gmask & GRAD_STEP) && cg[12] != 0.0f) gadd(vd.dstep, cg[12]);
     }
   }
+}
+
+// The slab-synchronous colour kernel (one 16x16 tile per workgroup).
+template <int DT, int PASS, bool XH>
+__global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
+  extern __shared__ __align__(16) float smem[];
+  color_lds_tile<DT, PASS, XH>(p, smem);
 }
 
 // float32 master -> storage copy (round to nearest even), 4 values per lane
