@@ -1666,44 +1666,63 @@ struct ColorCut {
   float maxw, swm, tmax, mmax;
 };
 
-template <int DT, bool TRACK>
-__device__ __forceinline__ void color_march_fwd(const ViewDesc& vd, const RayG& r, int n,
-                                                float* C, float& T, ColorCut& cut) {
+__device__ __forceinline__ void color_fwd_init(float* C, float& T, ColorCut& cut) {
   C[0] = C[1] = C[2] = 0.0f;
   T = 1.0f;
   cut.K = 0;
   cut.TK1 = 1.0f;
   cut.CK[0] = cut.CK[1] = cut.CK[2] = 0.0f;
   cut.maxw = cut.swm = cut.tmax = cut.mmax = 0.0f;
-  for (float fi = 0.0f; fi < (float)n; fi += 1.0f) {
+}
+
+// One sample of the colour forward from its 8 corners' (r, g, b, tau).
+template <bool TRACK>
+__device__ __forceinline__ void color_fwd_sample(const ViewDesc& vd, float fi, const Cell& c,
+                                                 const float (*v)[8], float* C, float& T,
+                                                 ColorCut& cut) {
+  float q[4];
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
+  const float e = __expf(-vd.step * q[3]);
+  const float Ti = T;
+  // explicitly rounded (no contraction): every route renders the same image
+  const float w = __fmul_rn(T, __fsub_rn(1.0f, e));
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, q[ch], C[ch]);
+  T *= e;
+  if (TRACK) {
+    if (Ti >= kFallbackTmin) {
+      cut.K = (int)fi + 1;
+      cut.TK1 = Ti;
+      cut.CK[0] = C[0]; cut.CK[1] = C[1]; cut.CK[2] = C[2];
+    }
+    const float m = fmaxf(fabsf(q[0]), fmaxf(fabsf(q[1]), fabsf(q[2])));
+    const float aw = fabsf(w);
+    cut.maxw = fmaxf(cut.maxw, aw);
+    cut.swm = fmaf(aw, m, cut.swm);
+    cut.tmax = fmaxf(cut.tmax, T);
+    cut.mmax = fmaxf(cut.mmax, m);
+  }
+}
+
+// samples [a, b) of a ray with direct gathers
+template <int DT, bool TRACK>
+__device__ __forceinline__ void color_fwd_direct(const ViewDesc& vd, const RayG& r, int a, int b,
+                                                 float* C, float& T, ColorCut& cut) {
+  for (float fi = (float)a; fi < (float)b; fi += 1.0f) {
     Cell c;
     locate(r, fi, vd, c);
     float v[4][8];
     fetch_color<DT>(vd, cell_index(vd, c), v);
-    float q[4];
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) q[ch] = trilerp(v[ch], c.f);
-    const float e = __expf(-vd.step * q[3]);
-    const float Ti = T;
-    // explicitly rounded (no contraction): every route renders the same image
-    const float w = __fmul_rn(T, __fsub_rn(1.0f, e));
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, q[ch], C[ch]);
-    T *= e;
-    if (TRACK) {
-      if (Ti >= kFallbackTmin) {
-        cut.K = (int)fi + 1;
-        cut.TK1 = Ti;
-        cut.CK[0] = C[0]; cut.CK[1] = C[1]; cut.CK[2] = C[2];
-      }
-      const float m = fmaxf(fabsf(q[0]), fmaxf(fabsf(q[1]), fabsf(q[2])));
-      const float aw = fabsf(w);
-      cut.maxw = fmaxf(cut.maxw, aw);
-      cut.swm = fmaf(aw, m, cut.swm);
-      cut.tmax = fmaxf(cut.tmax, T);
-      cut.mmax = fmaxf(cut.mmax, m);
-    }
+    color_fwd_sample<TRACK>(vd, fi, c, v, C, T, cut);
   }
+}
+
+template <int DT, bool TRACK>
+__device__ __forceinline__ void color_march_fwd(const ViewDesc& vd, const RayG& r, int n,
+                                                float* C, float& T, ColorCut& cut) {
+  color_fwd_init(C, T, cut);
+  color_fwd_direct<DT, TRACK>(vd, r, 0, n, C, T, cut);
 }
 
 // per-ray colour adjoint state
@@ -2067,6 +2086,137 @@ __device__ __forceinline__ void color_brick_flush(const ViewDesc& vd, const Bric
   }
 }
 
+// Axis slabs of a tile.  Slabs lie between planes q_ax = const of the grid
+// axis ax closest to the tile's centre ray, in march order (t = sgn * q_ax
+// grows along every ray): an axis-aligned slab has a tight bounding box at
+// any view angle, where a shell of constant distance from the eye cut
+// obliquely through the grid spans a box many times its volume (the
+// 4-channel brick holds a quarter of the scalar brick's vertices).  Each
+// ray's samples between two planes form one index range; consecutive slabs
+// share their boundary plane, so the ranges partition the ray.
+__device__ __forceinline__ void tile_axis(const ViewDesc& vd, int tx, int ty, int tw, int th,
+                                          const RayG& r, float& t0, float& dta) {
+  const float uc = 2.0f * ((float)(tx * tw) + 0.5f * tw) / (float)vd.W - 1.0f;
+  const float vc = 1.0f - 2.0f * ((float)(ty * th) + 0.5f * th) / (float)vd.H;
+  float wc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) wc[k] = vd.fwd[k] + uc * vd.right[k] + vc * vd.up[k];
+  const int ax = fabsf(wc[0]) >= fabsf(wc[1]) ? (fabsf(wc[0]) >= fabsf(wc[2]) ? 0 : 2)
+                                               : (fabsf(wc[1]) >= fabsf(wc[2]) ? 1 : 2);
+  const float sgn = wc[ax] >= 0.0f ? 1.0f : -1.0f;
+  t0 = sgn * r.qo[ax];
+  dta = sgn * r.dq[ax];
+}
+
+// first sample index at or past plane t (clamped to [0, n])
+__device__ __forceinline__ int axis_index(float t, float t0, float dta, int n) {
+  return (int)fminf(fmaxf(ceilf((t - t0) / dta), 0.0f), (float)n);
+}
+
+// The tile's plane range [tlo, thi] covering every ray's samples [0, n);
+// returns false if some ray with samples does not advance along the axis.
+template <int NT>
+__device__ __forceinline__ bool axis_range(float t0, float dta, int n, int* iscratch, int& tlo,
+                                           int& thi) {
+  const bool bad = n > 0 && !(dta > 0.0f);
+  int v[3] = {n > 0 ? -(int)floorf(t0) : -0x3fffffff,
+              n > 0 ? (int)ceilf(fmaf((float)(n - 1), dta, t0)) + 1 : -0x3fffffff, bad ? 1 : 0};
+  wg_max_n<NT>(v, 3, iscratch);
+  tlo = -v[0];
+  thi = v[1];
+  return v[2] == 0;
+}
+
+// Stage the brick's (r, g, b, tau) as float4 per vertex, 4 loads in flight
+// per lane.
+template <int NT, int DT>
+__device__ __forceinline__ void stage_color(const ViewDesc& vd, const Brick& br, float* stage) {
+  const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
+  const int64_t org = br.z0 * sz + br.y0 * sy + br.x0;
+  const bool narrow = brick_narrow(br, sz);
+  float4* s4 = reinterpret_cast<float4*>(stage);
+  constexpr int U = 4;
+  for (int i0 = threadIdx.x; i0 < br.size; i0 += U * NT) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = min(i0 + u * NT, br.size - 1);
+      v[u] = Vox4<DT>::ld(vd.vol, org + (narrow ? brick_goff<true>(br, idx, sy, sz)
+                                                : brick_goff<false>(br, idx, sy, sz)));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * NT < br.size) s4[i0 + u * NT] = v[u];
+  }
+}
+
+// samples [a, b) of a ray from the staged brick
+template <bool TRACK>
+__device__ __forceinline__ void color_fwd_lds(const ViewDesc& vd, const RayG& r, int a, int b,
+                                              const float* stage, const Brick& br, float* C,
+                                              float& T, ColorCut& cut) {
+  const int sy = 4 * br.bx4, sz = 4 * br.bxy4;
+  for (float fi = (float)a; fi < (float)b; fi += 1.0f) {
+    Cell c;
+    locate(r, fi, vd, c);
+    const char* p0 = reinterpret_cast<const char*>(stage) + 4 * brick_base(br, c);
+    const int off[8] = {0, 16, sy, sy + 16, sz, sz + 16, sz + sy, sz + sy + 16};
+    float v[4][8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float4 x = *reinterpret_cast<const float4*>(p0 + off[k]);
+      v[0][k] = x.x; v[1][k] = x.y; v[2][k] = x.z; v[3][k] = x.w;
+    }
+    color_fwd_sample<TRACK>(vd, fi, c, v, C, T, cut);
+  }
+}
+
+// The tile's colour forward, front to back over axis slabs: every slab whose
+// brick fits `vcap` vertices is staged in LDS, the others gathered directly.
+template <int DT, bool TRACK>
+__device__ __forceinline__ void color_fwd_slabs(const ViewDesc& vd, const RayG& r, int tx,
+                                                int ty, int n, float* stage, int* iscratch,
+                                                int vcap, float* C, float& T, ColorCut& cut) {
+  constexpr int NT = 256;
+  color_fwd_init(C, T, cut);
+  float t0, dta;
+  tile_axis(vd, tx, ty, 16, 16, r, t0, dta);
+  int tlo, thi;
+  if (!axis_range<NT>(t0, dta, n, iscratch, tlo, thi)) {
+    color_fwd_direct<DT, TRACK>(vd, r, 0, n, C, T, cut);
+    return;
+  }
+  float dz = 4.0f;
+  for (float tl = (float)tlo; tl < (float)thi;) {
+    int st, a = 0, b = 0;
+    float th;
+    Brick br;
+    for (;;) {
+      th = fminf(tl + dz, (float)thi);
+      a = axis_index(tl, t0, dta, n);
+      b = axis_index(th, t0, dta, n);
+      if (n <= 0) a = b = 0;
+      if (!range_brick<NT>(vd, r, a, b, iscratch, br)) { st = 0; dz = fminf(2.0f * dz, 64.0f); break; }
+      if (vcap > 0 && br.size <= vcap) {
+        if (4 * br.size < vcap) dz = fminf(2.0f * dz, 64.0f);
+        st = 1;
+        break;
+      }
+      if (vcap <= 0 || dz <= 0.25f) { st = 2; break; }
+      dz *= 0.5f;
+    }
+    tl = th;
+    if (st == 1) {
+      // the previous slab's reads finished before range_brick's barriers
+      stage_color<NT, DT>(vd, br, stage);
+      __syncthreads();
+      color_fwd_lds<TRACK>(vd, r, a, b, stage, br, C, T, cut);
+    } else if (st == 2) {
+      color_fwd_direct<DT, TRACK>(vd, r, a, b, C, T, cut);
+    }
+  }
+}
+
 // The back-to-front slab march of a tile's colour adjoint.
 template <int DT, bool FIX, bool XH>
 __device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const RayG& r, int tx,
@@ -2076,45 +2226,18 @@ __device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const Ra
                                                     AdjState& x, const float* qs,
                                                     const float* inv_qs) {
   constexpr int NT = 256, TW = 16, TH = 16;
-  // Slabs between planes q_ax = const of the grid axis ax closest to the
-  // tile's centre ray, in march order (t = sgn * q_ax grows along every ray):
-  // an axis-aligned slab has a tight bounding box at any view angle, where a
-  // shell of constant distance from the eye cut obliquely through the grid
-  // spans a box many times its volume (the 4-channel brick holds a quarter
-  // of the scalar brick's vertices).  Each ray's samples between two planes
-  // form one index range; consecutive slabs share their boundary plane, so
-  // the ranges partition the ray.
-  int ax;
-  float sgn;
-  {
-    const float uc = 2.0f * ((float)(tx * TW) + 0.5f * TW) / (float)vd.W - 1.0f;
-    const float vc = 1.0f - 2.0f * ((float)(ty * TH) + 0.5f * TH) / (float)vd.H;
-    float wc[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) wc[k] = vd.fwd[k] + uc * vd.right[k] + vc * vd.up[k];
-    ax = fabsf(wc[0]) >= fabsf(wc[1]) ? (fabsf(wc[0]) >= fabsf(wc[2]) ? 0 : 2)
-                                       : (fabsf(wc[1]) >= fabsf(wc[2]) ? 1 : 2);
-    sgn = wc[ax] >= 0.0f ? 1.0f : -1.0f;
-  }
-  const float t0 = sgn * r.qo[ax], dt_ax = sgn * r.dq[ax];
+  // axis slabs (tile_axis), back to front
+  float t0, dt_ax;
+  tile_axis(vd, tx, ty, TW, TH, r, t0, dt_ax);
   int tlo, thi;
-  {
-    // every ray with work must advance along the axis (else the tile runs
-    // its rays whole on the direct path)
-    const bool bad = Nadj > 0 && !(dt_ax > 0.0f);
-    int v[3] = {Nadj > 0 ? -(int)floorf(t0) : -0x3fffffff,
-                Nadj > 0 ? (int)ceilf(fmaf((float)(Nadj - 1), dt_ax, t0)) + 1 : -0x3fffffff,
-                bad ? 1 : 0};
-    wg_max_n<NT>(v, 3, iscratch);
-    tlo = -v[0];
-    thi = v[1];
-    if (v[2]) {
-      const Brick none{};
-      for (float fi = (float)(Nadj - 1); fi >= 0.0f; fi -= 1.0f)
-        color_adj_sample<DT, false, false, XH>(vd, r, fi, acc, none, gmask, need_xhat, s, x, qs);
-      if (want_dv) color_cell_flush<false, false>(vd, none, acc, s, qs);
-      tlo = thi = 0;
-    }
+  if (!axis_range<NT>(t0, dt_ax, Nadj, iscratch, tlo, thi)) {
+    // some ray does not advance along the axis: the tile runs its rays whole
+    // on the direct path
+    const Brick none{};
+    for (float fi = (float)(Nadj - 1); fi >= 0.0f; fi -= 1.0f)
+      color_adj_sample<DT, false, false, XH>(vd, r, fi, acc, none, gmask, need_xhat, s, x, qs);
+    if (want_dv) color_cell_flush<false, false>(vd, none, acc, s, qs);
+    tlo = thi = 0;
   }
   const int acap = want_dv ? vcap : 0;
   float dz = 4.0f;
@@ -2124,8 +2247,8 @@ __device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const Ra
     Brick br;
     for (;;) {
       tl = fmaxf(th - dz, (float)tlo);
-      a = (int)fminf(fmaxf(ceilf((tl - t0) / dt_ax), 0.0f), (float)Nadj);
-      b = (int)fminf(fmaxf(ceilf((th - t0) / dt_ax), 0.0f), (float)Nadj);
+      a = axis_index(tl, t0, dt_ax, Nadj);
+      b = axis_index(th, t0, dt_ax, Nadj);
       if (Nadj <= 0) a = b = 0;
       if (!range_brick<NT>(vd, r, a, b, iscratch, br)) { st = 0; dz = fminf(2.0f * dz, 64.0f); break; }
       if (acap > 0 && br.size <= acap) {
@@ -2183,7 +2306,7 @@ __device__ __forceinline__ void color_lds_tile(const LaunchParams& p, float* sme
   // start of each ray's inversion and the bound of the fixed-point brick
   // (reproducing the image and T_N the forward pass wrote, bit for bit).
   ColorCut cut;
-  color_march_fwd<DT, PASS != PASS_FWD>(vd, r, N, CN, TN, cut);
+  color_fwd_slabs<DT, PASS != PASS_FWD>(vd, r, tx, ty, N, acc, iscratch, vcap, CN, TN, cut);
   if (PASS != PASS_ADJ) {
     if (valid) {
       reinterpret_cast<float4*>(vd.image)[pix] = make_float4(CN[0], CN[1], CN[2], 1.0f - TN);

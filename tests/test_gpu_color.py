@@ -207,9 +207,10 @@ def test_color_full_size_sampled_pixels():
 @pytest.mark.parametrize("lds_cap", [64, 1024, 16384])
 def test_color_brick_sizes_and_direct_slabs(lds_cap):
     """Bricks that never fit (every slab on the direct path inside the slab
-    kernel), small ones (short slabs) and large ones give the same gradients;
+    kernel), small ones (short slabs) and large ones: the forward's image is
+    bitwise the direct route's, the gradients match the oracle, and so does
     the fused pass of an opaque problem (the cut taken from the in-kernel
-    forward) against the oracle."""
+    forward)."""
     import torch
     from paper_2107_12672_amd import ddvr as d
     old = d.get_tuning()
@@ -217,6 +218,10 @@ def test_color_brick_sizes_and_direct_slabs(lds_cap):
         d.set_tuning(lds_cap=lds_cap, slab_k=min(old["slab_k"], old["slab_kmax"]))
         p = color_problem(W=40, H=36, tau_max=300.0, seed=14)
         _say(f"colour lds_cap={lds_cap}")
+        # staged and direct gathers render the same image, bit for bit
+        img_s, tr_s = gpu_forward(p)
+        img_d, tr_d = gpu_forward(p, flags=PLAIN)
+        assert np.array_equal(img_s, img_d) and np.array_equal(tr_s, tr_d)
         ora = oracle_forward(p)
         hit = ora["nsamp"] > 0
         assert (ora["trans"][hit] < 2.0 ** -100).mean() > 0.05
