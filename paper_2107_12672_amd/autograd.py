@@ -58,11 +58,12 @@ class SphereCamera(torch.autograd.Function):
 class DDVRFunction(torch.autograd.Function):
     """image = render(volume, tf, frame, step).
 
-    volume  float32 [nz][ny][nx] device tensor (the master copy)
-    tf      float32 [R][4] device tensor, or None (absorption-only)
+    volume  float32 [nz][ny][nx] device tensor (the master copy), or
+            [nz][ny][nx][4] (r, g, b, tau) for the colour-volume model
+    tf      float32 [R][4] device tensor, or None (absorption-only, colour)
     frame   float32 [12] tensor (any device) -- camera frame
     step    scalar tensor, world units
-    Returns [H][W][4] (emission-absorption) or [H][W] (absorption-only).
+    Returns [H][W][4] (emission-absorption, colour) or [H][W] (absorption-only).
     """
 
     @staticmethod
@@ -83,7 +84,7 @@ class DDVRFunction(torch.autograd.Function):
                 raise ValueError("emission-absorption needs a transfer function")
             tf = tf.contiguous()
         cam = _camera_struct(frame, width, height)
-        C = 4 if model == _d.EMISSION_ABSORPTION else 1
+        C = 1 if model == _d.ABSORPTION else 4
         image = torch.empty((height, width, C) if C == 4 else (height, width),
                             device=volume.device, dtype=torch.float32)
         trans = torch.empty((height, width), device=volume.device, dtype=torch.float32)

@@ -136,3 +136,37 @@ def test_viewpoint_autograd_forward_mode_matches_oracle():
     assert_grad_close([step.grad.item()], [ref["dstep"]], "forward-mode step")
     assert_dv_close(V.grad.double().cpu().numpy(), ref["dV"], "viewpoint dV")
     assert_grad_close(T.grad.double().cpu().numpy(), ref["dTF"], "viewpoint dTF")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_autograd_colour_volume(storage):
+    """The wrapper on the pre-shaded colour volume: gradients of the 4-channel
+    master grid, the pose and the step against the oracle."""
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    from test_gpu_color import color_problem
+    p = color_problem(storage=storage, W=48, H=40)
+    _say(f"autograd colour storage={storage}")
+    ora = oracle_forward(p)
+    mask = tie_mask(ora["ratio"]) | kink_mask(p)
+    rng = np.random.default_rng(23)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[mask] = 0.0
+    dev = torch.device("cuda")
+    V = torch.from_numpy(p.volume).to(dev).requires_grad_(True)
+    yaw, pitch = (torch.tensor(math.radians(p.yaw), requires_grad=True),
+                  torch.tensor(math.radians(p.pitch), requires_grad=True))
+    step = torch.tensor(p.step, requires_grad=True)
+    frame = ag.camera_frame(yaw, pitch, torch.tensor(p.dist), math.radians(p.fovy), p.W, p.H)
+    sdt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
+    img = ag.render(V, None, frame, step, d.COLOR, p.W, p.H, storage=sdt)
+    assert img.shape == (p.H, p.W, 4)
+    gt = torch.from_numpy(g.reshape(p.H, p.W, 4).astype(np.float32)).to(dev)
+    (img * gt).sum().backward()
+    ref = oracle_adjoint(p, g)
+    assert V.grad.shape == V.shape
+    assert_dv_close(V.grad.double().cpu().numpy(), ref["dV"], "autograd colour dV")
+    sph = oracle.sphere_grad(ref["dcam"], p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H)
+    got = np.array([yaw.grad.item(), pitch.grad.item()])
+    assert_grad_close(got, sph[:2], "autograd colour yaw/pitch", rtol=2e-3)
+    assert_grad_close([step.grad.item()], [ref["dstep"]], "autograd colour step")

@@ -240,3 +240,39 @@ def test_batched_l1_and_reconstruction_loop():
           f"relative volume error {err:.3f}", flush=True)
     assert err < 0.95
     assert float(res.volume.min()) >= 0.0
+
+
+def test_prior_and_adam_at_full_size_sampled():
+    """The 256^3 grid of the reconstruction benchmark, the launch the driver
+    uses: the 3D prior's loss and its gradient on sampled vertices (faces,
+    edges, corners, interior), and one Adam step on the same vertices."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    _say("prior + Adam 256^3")
+    w = synth.make_c3()
+    V = w.target_volume
+    vd = _t(V)
+    g = torch.zeros_like(vd)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d.volume_prior(vd, 0.5, g, loss)
+    torch.cuda.synchronize()
+    ref_l, ref_g = OL.volume_prior(V, 0.5)
+    assert float(loss.item()) == pytest.approx(ref_l, rel=1e-6)
+    n = 256
+    rng = np.random.default_rng(76)
+    sel = np.unique(np.concatenate([rng.choice(n ** 3, 4000, replace=False),
+                                    [0, n - 1, n * n - 1, n ** 3 - 1, n * n * 128 + n * 7]]))
+    gs = g.cpu().numpy().ravel()[sel]
+    rs = ref_g.ravel()[sel]
+    scale = float(np.abs(ref_g).max())
+    assert np.allclose(gs, rs, rtol=1e-4, atol=1e-5 * scale)
+    # one Adam step on the whole grid with that gradient
+    m = torch.zeros_like(vd)
+    v = torch.zeros_like(vd)
+    x = vd.clone()
+    d.adam_step(x, g, m, v, 1, 0.3, lo=0.0)
+    torch.cuda.synchronize()
+    xr, _, _ = OL.adam_step(V.ravel()[sel].astype(np.float64), gs, 0.0, 0.0, 1,
+                            lr=float(np.float32(0.3)), beta1=float(np.float32(0.9)),
+                            beta2=float(np.float32(0.999)), eps=float(np.float32(1e-8)), lo=0.0)
+    assert np.allclose(x.cpu().numpy().ravel()[sel], xr, rtol=1e-5, atol=1e-6)
