@@ -67,7 +67,7 @@ typedef enum {
   DDVR_ERR_VALUE = -4,       /* a scalar is out of range (step <= 0, non-finite, ...) */
   DDVR_ERR_HIP = -5,         /* the HIP runtime reported an error (also a pending
                                 asynchronous error of an earlier launch) */
-  DDVR_ERR_UNSUPPORTED = -6, /* valid request this build does not handle */
+  DDVR_ERR_UNSUPPORTED = -6, /* valid request the library does not handle */
   DDVR_ERR_WORKSPACE = -7    /* workspace missing or too small */
 } ddvr_status;
 
