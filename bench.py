@@ -580,8 +580,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(views would shard across GPUs with one all-reduce of the gradients; "
-              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+              "(views would shard across GPUs with one all-reduce of the gradients). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

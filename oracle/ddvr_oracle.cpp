@@ -22,8 +22,7 @@
 // segment checkpointing, the forward-order residual form and forward-mode
 // dual numbers, Sec. 4.2) is a cross-variant that must agree with it.
 //
-// Readings where the paper is silent or garbled (all stated again in the
-// design notes):
+// Readings where the paper is silent or garbled:
 //   - blending adjoint: the colour-sample adjoint is (1 - alpha^(i)) * Chat
 //     (the printed "(C - alpha^(i))" is a typo; it follows from eq.
 //     blend-forward); Alg. 2's right-hand side "color_N" is read as
