@@ -821,11 +821,17 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
   if ((rc = validate_model(model)) || (rc = validate_flags(flags)) ||
       (rc = validate_mode(model, flags)))
     return rc;
-  if (model == DDVR_COLOR) return fail(DDVR_ERR_UNSUPPORTED, "batches: colour model");
+  if (model == DDVR_COLOR &&
+      ((flags & DDVR_LAUNCH_PLAIN) || (flags & DDVR_ADJ_MODE_MASK) == DDVR_ADJ_RESIDUAL))
+    return fail(DDVR_ERR_UNSUPPORTED, "colour batches take the slab route only (no PLAIN, no RESIDUAL)");
   if (model == DDVR_EMISSION_ABSORPTION && (!tfs || ntf <= 0))
     return fail(DDVR_ERR_NULL, "emission-absorption batch without transfer functions");
-  for (int i = 0; i < nvol; ++i)
+  for (int i = 0; i < nvol; ++i) {
     if ((rc = validate_volume(&vols[i]))) return rc;
+    if (model == DDVR_COLOR && (rc = validate_color_volume(&vols[i]))) return rc;
+    if (model == DDVR_COLOR && vols[i].dtype != vols[0].dtype)
+      return fail(DDVR_ERR_UNSUPPORTED, "colour batches need one storage type");
+  }
   if (model == DDVR_EMISSION_ABSORPTION)
     for (int i = 0; i < ntf; ++i)
       if ((rc = validate_tf(&tfs[i], model))) return rc;
@@ -850,6 +856,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
     const ddvr_tf* tf = model == DDVR_EMISSION_ABSORPTION ? &tfs[v.tf] : nullptr;
     ViewDesc& d = b->views[i];
     fill_view(d, &vols[v.volume], tf, &v.cam, v.step_world, model, cap);
+    if (model == DDVR_COLOR) {   // the colour kernel's 16x16 tiles
+      d.tiles_x = (v.cam.width + 15) / 16;
+      d.tiles_y = (v.cam.height + 15) / 16;
+    }
     d.image = v.image;
     d.trans = v.transmittance;
     d.d_image = v.d_image;
@@ -876,7 +886,8 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
   // workgroup per tile with contiguous ranges per XCD.  Uneven batches (or
   // schedule = 2) become a persistent launch whose workgroups pop tiles from a
   // queue ordered by estimated cost, longest first.
-  const int tw = tile_w(b->tuning.waves), th = tile_h(b->tuning.waves);
+  const int tw = model == DDVR_COLOR ? 16 : tile_w(b->tuning.waves);
+  const int th = model == DDVR_COLOR ? 16 : tile_h(b->tuning.waves);
   std::vector<std::pair<int64_t, int32_t>> items;
   bool even = true;
   for (int i = 0; i < nview; ++i) {
@@ -889,8 +900,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
     if (d.W != b->views[0].W || d.H != b->views[0].H || d.vol != b->views[0].vol) even = false;
   }
   // batches mixing storage types always take the persistent (per-view type) launch
-  b->persistent = b->tuning.schedule == 2 || (b->tuning.schedule == 0 && !even) ||
-                  b->launch_dtype == kDtypeDynamic;
+  // (the colour kernel takes one item per workgroup, in list order)
+  b->persistent = model != DDVR_COLOR &&
+                  (b->tuning.schedule == 2 || (b->tuning.schedule == 0 && !even) ||
+                   b->launch_dtype == kDtypeDynamic);
   if (b->persistent) b->launch_dtype = kDtypeDynamic;
   if (b->persistent)
     std::stable_sort(items.begin(), items.end(),
@@ -955,6 +968,19 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.views = b->d_views;
   p.flags = b->flags;
   p.grad_mask = b->grad_mask;
+  if (b->model == DDVR_COLOR) {
+    p.lds_cap = std::max(b->tuning.lds_cap / 4, 16);
+    p.loss_scale = loss_scale;
+    p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
+    p.work = b->d_work;
+    p.n_items = b->n_items;
+    p.xcd_remap = 1;
+    const size_t lds = (size_t)p.lds_cap * 4 * sizeof(float) + 64 * sizeof(int);
+    int rc;
+    if ((rc = check_lds(lds))) return rc;
+    const hipError_t e = (hipError_t)launch_color(p, pass, b->launch_dtype, 1, lds, s);
+    return e == hipSuccess ? DDVR_OK : hip_fail(e, "colour batch launch");
+  }
   p.lds_two = needs_two_bricks(pass, b->model, b->flags, b->grad_mask);
   {
     const int rc = fit_cap((b->flags & DDVR_LAUNCH_PLAIN) ? 0 : b->tuning.lds_cap, p.lds_two,

@@ -2281,12 +2281,20 @@ __device__ __forceinline__ void color_adjoint_slabs(const ViewDesc& vd, const Ra
 template <int DT, int PASS, bool XH>
 __device__ __forceinline__ void color_lds_tile(const LaunchParams& p, float* smem) {
   constexpr int NT = 256, TW = 16, TH = 16;
-  const ViewDesc& vd = p.one;
+  // one (view, tile) item per workgroup: a single view's tiles, or a batch's
+  // work list of (view << 20 | tile)
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  int view = 0, tile = item;
+  if (p.work) {
+    const int w = p.work[item];
+    view = w >> 20;
+    tile = w & 0xFFFFF;
+  }
+  const ViewDesc vd = p.views ? p.views[view] : p.one;
   const int vcap = p.lds_cap;          // vertices per brick (4 floats each)
   float* acc = smem;
   int* iscratch = reinterpret_cast<int*>(smem + 4 * vcap);
   float* fscratch = reinterpret_cast<float*>(iscratch);
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int lx, ly;

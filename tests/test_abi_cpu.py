@@ -265,7 +265,12 @@ def test_colour_model_validation():
     h = ctypes.c_void_p()
     views = (d.View * 1)(d.View(0, -1, cam, 0.1, 0x3000, None, None, None, None, None))
     vols = (d.Volume * 1)(vol)
-    assert L.ddvr_batch_create(vols, 1, None, 0, views, 1, C, 0, None, None, None,
+    # colour batches: the slab route only, one storage type
+    for flags in (d.LAUNCH_PLAIN, d.ADJ_RESIDUAL):
+        assert L.ddvr_batch_create(vols, 1, None, 0, views, 1, C, flags, None, None, None,
+                                   B(h)) == d.ERR_UNSUPPORTED
+    mixed = (d.Volume * 2)(vol, d.Volume(0x1000, d.BF16, 8, 8, 8))
+    assert L.ddvr_batch_create(mixed, 2, None, 0, views, 1, C, 0, None, None, None,
                                B(h)) == d.ERR_UNSUPPORTED
 
 

@@ -247,3 +247,47 @@ def test_color_brick_sizes_and_direct_slabs(lds_cap):
                         2e-3)
     finally:
         d.set_tuning(**old)
+
+
+def test_color_batch_equals_single_views():
+    """Uneven colour batch (two grids, images of 56x44, 40x36 and 33x47, one
+    launch per pass): images bitwise the single-view renders, gradients equal
+    to the sum of the single-view adjoints, loss equal to their sum."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    _say("colour batch")
+    pa = color_problem(seed=15)
+    pb = color_problem(n=(30, 26, 28), seed=16, yaw=200.0, pitch=35.0)
+    va, vb = device_volume(pa), device_volume(pb)
+    specs = [(va, pa, 56, 44, 63.0), (vb, pb, 40, 36, 150.0), (va, pa, 33, 47, 300.0)]
+    rng = np.random.default_rng(17)
+    imgs, trs, tgts, cams, views = [], [], [], [], []
+    dva = torch.zeros(pa.volume.shape, device="cuda")
+    dvb = torch.zeros(pb.volume.shape, device="cuda")
+    for k, (v, p, W, H, yaw) in enumerate(specs):
+        cam = d.camera_from_sphere(np.radians(yaw), np.radians(p.pitch), p.dist,
+                                   np.radians(p.fovy), W, H)
+        cams.append(cam)
+        imgs.append(torch.zeros(H * W * 4, device="cuda"))
+        trs.append(torch.zeros(H * W, device="cuda"))
+        tgts.append(torch.from_numpy(rng.uniform(0, 1, H * W * 4).astype(np.float32)).cuda())
+        views.append(d.make_view(0 if v is va else 1, cam, p.step, imgs[k], transmittance=trs[k],
+                                 target=tgts[k]))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    b = d.Batch([va, vb], None, views, d.COLOR, d_volumes=[dva, dvb])
+    b.run(d.PASS_FUSED, 1e-3, loss)
+    torch.cuda.synchronize()
+    b.close()
+    ref_a = torch.zeros_like(dva)
+    ref_b = torch.zeros_like(dvb)
+    ref_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k, (v, p, W, H, yaw) in enumerate(specs):
+        im = torch.zeros_like(imgs[k])
+        tr = torch.zeros_like(trs[k])
+        d.render_fused_l2(v, None, cams[k], p.step, COLOR, tgts[k], 1e-3, im, tr,
+                          d.grads_desc(ref_a if v is va else ref_b), loss_out=ref_loss)
+        torch.cuda.synchronize()
+        assert torch.equal(im, imgs[k]) and torch.equal(tr, trs[k])
+    assert abs(loss.item() - ref_loss.item()) <= 1e-9 * abs(ref_loss.item())
+    assert_dv_close(dva.cpu().double().numpy(), ref_a.cpu().double().numpy(), "batch dV a", 1e-5)
+    assert_dv_close(dvb.cpu().double().numpy(), ref_b.cpu().double().numpy(), "batch dV b", 1e-5)
