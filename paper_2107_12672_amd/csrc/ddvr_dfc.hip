@@ -69,7 +69,8 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_density_from_color(const DfcParams p) {
   extern __shared__ __align__(16) float dfc_lds[];
   float4* tfl = reinterpret_cast<float4*>(dfc_lds);
-  for (int k = threadIdx.x; k < p.R; k += 256) tfl[k] = reinterpret_cast<const float4*>(p.tf)[k];
+  // (the table is copied by floats: its pointer need only be 4-byte aligned)
+  for (int k = threadIdx.x; k < 4 * p.R; k += 256) dfc_lds[k] = p.tf[k];
   __syncthreads();
 
   const int64_t nxy = (int64_t)p.nx * p.ny, nvox = nxy * p.nz;
