@@ -335,17 +335,20 @@ def secondary(args):
                                   images[i], trans[i], grads, loss_out=loss)
 
         res = {}
-        for mode, flags in (("auto", d.ADJ_AUTO), ("residual", d.ADJ_RESIDUAL)):
+        routes = () if args.no_plain else (("auto", d.ADJ_AUTO), ("residual", d.ADJ_RESIDUAL))
+        for mode, flags in routes:
             fn = step if flags == 0 else (lambda: [d.render_fused_l2(
                 vol, None, cams[i], w.step_world, d.COLOR, targets[i], scale, images[i], trans[i],
                 grads, flags=flags, loss_out=loss) for i in range(nv)])
             ms = _timed(fn, args.steps, args.warmup, stream, torch)
             res[mode] = {"ms_per_step": ms, "value": S / (ms * 1e-3)}
             log(f"color {mode}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
-        fwd_ms = _timed(lambda: [d.render_forward(vol, None, cams[i], w.step_world, d.COLOR,
-                                                  images[i], trans[i]) for i in range(nv)],
-                        args.steps, args.warmup, stream, torch)
-        log(f"color forward only: {fwd_ms:.3f} ms")
+        fwd_ms = None
+        if not args.no_plain:
+            fwd_ms = _timed(lambda: [d.render_forward(vol, None, cams[i], w.step_world, d.COLOR,
+                                                      images[i], trans[i]) for i in range(nv)],
+                            args.steps, args.warmup, stream, torch)
+            log(f"color forward only: {fwd_ms:.3f} ms")
         # the same step as one batched launch per pass, replayed from a HIP graph
         cb = d.Batch([vol], None, [d.make_view(0, cams[i], w.step_world, images[i],
                                                transmittance=trans[i], target=targets[i])
@@ -356,6 +359,26 @@ def secondary(args):
         log(f"color batched (one launch, graph): {b_ms:.3f} ms, {S / (b_ms * 1e-3):.4g} "
             f"ray-samples/s")
         res["batched"] = {"ms_per_step": b_ms, "value": S / (b_ms * 1e-3)}
+        # HBM roofline of the batched launch on algorithmic bytes: per sample pair
+        # 8 corner gathers of 4 channels in the forward and again in the adjoint,
+        # and 8 x 4 float32 gradient scatters (the LDS bricks serve most of them)
+        alg = S * (2 * 8 * 4 * 2 + 8 * 4 * 4)
+        gbs = alg / (b_ms * 1e-3) / 1e9
+        tr = None
+        try:
+            with open(os.path.join(ROOT, "profiles", "traffic_color_batched.json")) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha") == kernel_source_hash():
+                tr = t.get("bytes_per_launch")
+        except (OSError, ValueError):
+            pass
+        out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr,
+                           "kernel": "k_color_lds<bf16, fused> (64 views, one launch)",
+                           "kernel_ms": round(b_ms, 4), "alg_bytes_per_launch": alg,
+                           "note": "algorithmic bytes (256 per sample pair, bf16): LDS bricks "
+                                   "serve the forward gathers and absorb the scatters; the "
+                                   "adjoint's global float atomics bound it"}
         if not getattr(args, "no_cpu_baseline", False):
             out["cpu_baseline"] = cpu_baseline_color(w, w.volume)
             log(f"cpu baseline: {out['cpu_baseline']}")
@@ -364,7 +387,7 @@ def secondary(args):
                     "config": {"workload": w.name + ", fused L2, colour-volume gradient",
                                "samples_per_step": S,
                                "launch": "one batched launch per step, HIP graph replay"},
-                    "per_view_launches": res["auto"], "residual_form": res["residual"],
+                    "per_view_launches": res.get("auto"), "residual_form": res.get("residual"),
                     "forward_ms_per_view_launches": fwd_ms})
     elif args.workload == "dfc":
         w = synth.make_color()
