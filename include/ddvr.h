@@ -83,11 +83,10 @@ typedef enum { DDVR_F32 = 0, DDVR_F16 = 1, DDVR_BF16 = 2 } ddvr_dtype;
  *                           then the emission-absorption segment and blend;
  *                           no TF (tf may be NULL), d_volume is
  *                           [nz][ny][nx][4] float32, images as
- *                           emission-absorption.  Single views and batches
- *                           (batches: one storage type, not PLAIN, not
- *                           RESIDUAL, one workgroup per 16x16 tile in list
- *                           order); render_tangent returns
- *                           DDVR_ERR_UNSUPPORTED. */
+ *                           emission-absorption.  Single views, batches
+ *                           (one storage type, not PLAIN, not RESIDUAL, one
+ *                           workgroup per 16x16 tile in list order) and
+ *                           render_tangent (direct gathers). */
 typedef enum {
   DDVR_ABSORPTION = 0,
   DDVR_EMISSION_ABSORPTION = 1,

@@ -553,7 +553,7 @@ int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
   if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
       (rc = validate_camera(cam)) || (rc = validate_step(vol, step_world)))
     return rc;
-  if (model == DDVR_COLOR) return fail(DDVR_ERR_UNSUPPORTED, "render_tangent: colour model");
+  if (model == DDVR_COLOR && (rc = validate_color_volume(vol))) return rc;
   if (flags & ~DDVR_LAUNCH_PLAIN) return fail(DDVR_ERR_VALUE, "tangent flags: only DDVR_LAUNCH_PLAIN");
   if (!dirs) return fail(DDVR_ERR_NULL, "dirs is NULL");
   if (ndir < 1 || ndir > DDVR_MAX_DIRECTIONS)
@@ -586,7 +586,8 @@ int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
   }
   p.image_dot = image_dot;
   p.d_dir = d_dir;
-  const size_t lds = lds_bytes(p.lds_cap, 0, model, p.one.R);
+  // (the colour volume's tangent kernel gathers directly: no brick)
+  const size_t lds = model == DDVR_COLOR ? 0 : lds_bytes(p.lds_cap, 0, model, p.one.R);
   if ((rc = check_lds(lds))) return rc;
   const hipError_t e = (hipError_t)launch_tangent(p, model, vol->dtype,
                                                    p.one.tiles_x * p.one.tiles_y, lds, hip_stream);

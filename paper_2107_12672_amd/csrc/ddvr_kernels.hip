@@ -2447,6 +2447,103 @@ __global__ __launch_bounds__(256) void k_color_lds(const LaunchParams p) {
   color_lds_tile<DT, PASS, XH>(p, smem);
 }
 
+// Forward-mode derivatives of the colour volume (direct gathers, one 16x16
+// tile per workgroup): every channel's interpolated value carries its
+// derivative along the P directions, q_c' = grad(q_c) . q' (grid units), and
+// the blend propagates them as for the emission-absorption model with the
+// channels in place of the TF's output.  The primal is bit for bit the
+// colour forward's.
+template <int DT, int P>
+__global__ __launch_bounds__(256) void k_tangent_color(const TangentParams p) {
+  constexpr int NT = 256, TW = 16, TH = 16;
+  __shared__ float fscratch[64];
+  const ViewDesc& vd = p.one;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % vd.tiles_x, ty = tile / vd.tiles_x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int lx, ly;
+  tile_pixel<4>(false, wid, lane, lx, ly);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool valid = px < vd.W && py < vd.H;
+  const int64_t pix = (int64_t)py * vd.W + px;
+  RayG r;
+  setup_ray(vd, px, py, valid, r);
+  RayTan<P> t;
+  setup_tangent<P>(vd, r, p.dir, t);
+  float C[3] = {0.0f, 0.0f, 0.0f}, T = 1.0f;
+  float Cd[P][3], Td[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) { Cd[k][0] = Cd[k][1] = Cd[k][2] = 0.0f; Td[k] = 0.0f; }
+  for (float fi = 0.0f; fi < (float)r.N; fi += 1.0f) {
+    Cell c;
+    locate(r, fi, vd, c);
+    float v[4][8];
+    fetch_color<DT>(vd, cell_index(vd, c), v);
+    float q[4], qd[P][4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      q[ch] = trilerp(v[ch], c.f);
+      float g[3];
+      trilerp_grad(v[ch], c.f, g);
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        float x = 0.0f;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) x = fmaf(g[ax], fmaf(fi, t.dq[k][ax], t.qo[k][ax]), x);
+        qd[k][ch] = x;
+      }
+    }
+    const float e = __expf(-vd.step * q[3]);
+    const float alpha = __fsub_rn(1.0f, e);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      // c = alpha rgb: c' = alpha' rgb + alpha rgb'; C' += T' c + T c'; T' = T' e + T e'
+      const float ed = -e * fmaf(p.dir[k][12], q[3], vd.step * qd[k][3]);
+      const float ad = -ed;
+      const float ta = Td[k] * alpha;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float cd = fmaf(ad, q[ch], alpha * qd[k][ch]);
+        Cd[k][ch] = fmaf(ta, q[ch], fmaf(T, cd, Cd[k][ch]));
+      }
+      Td[k] = fmaf(Td[k], e, T * ed);
+    }
+    // primal exactly as the colour forward (bitwise the same image)
+    const float w = __fmul_rn(T, alpha);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, q[ch], C[ch]);
+    T *= e;
+  }
+  if (valid) {
+    if (vd.image)
+      reinterpret_cast<float4*>(vd.image)[pix] = make_float4(C[0], C[1], C[2], 1.0f - T);
+    if (p.image_dot) {
+      const int64_t plane = (int64_t)vd.W * vd.H * 4;
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+        reinterpret_cast<float4*>(p.image_dot + k * plane)[pix] =
+            make_float4(Cd[k][0], Cd[k][1], Cd[k][2], -Td[k]);
+    }
+  }
+  if (p.d_dir) {
+    // forward-delayed: contract with the upstream gradient in the same pass
+    float dk[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      float x = 0.0f;
+      if (valid) {
+        const float4 g = reinterpret_cast<const float4*>(vd.d_image)[pix];
+        x = fmaf(g.x, Cd[k][0], fmaf(g.y, Cd[k][1], fmaf(g.z, Cd[k][2], -g.w * Td[k])));
+      }
+      dk[k] = x;
+    }
+    wg_sum_n<NT>(dk, P, fscratch);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < P; ++k)
+        if (dk[k] != 0.0f) gadd(p.d_dir + k, dk[k]);
+  }
+}
+
 // float32 master -> storage copy (round to nearest even), 4 values per lane
 __global__ void k_cast(const float* __restrict__ src, void* __restrict__ dst, int dtype,
                        int64_t n) {
@@ -2609,9 +2706,27 @@ static hipError_t launch_tan1(const TangentParams& p, int dtype, int n_blocks, s
   }
 }
 
+template <int DT>
+static hipError_t launch_tan_color(const TangentParams& p, int n_blocks, hipStream_t s) {
+  switch (p.ndir) {
+    case 1: hipLaunchKernelGGL((k_tangent_color<DT, 1>), dim3(n_blocks), dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_tangent_color<DT, 2>), dim3(n_blocks), dim3(256), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_tangent_color<DT, 3>), dim3(n_blocks), dim3(256), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_tangent_color<DT, 4>), dim3(n_blocks), dim3(256), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
 int launch_tangent(const TangentParams& p, int model, int dtype, int n_blocks, size_t lds_bytes,
                    void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (model == DDVR_COLOR) {
+    switch (dtype) {
+      case DDVR_F16: return (int)launch_tan_color<DDVR_F16>(p, n_blocks, s);
+      case DDVR_BF16: return (int)launch_tan_color<DDVR_BF16>(p, n_blocks, s);
+      default: return (int)launch_tan_color<DDVR_F32>(p, n_blocks, s);
+    }
+  }
   return (int)(model == DDVR_EMISSION_ABSORPTION
                    ? launch_tan1<DDVR_EMISSION_ABSORPTION>(p, dtype, n_blocks, lds_bytes, s)
                    : launch_tan1<DDVR_ABSORPTION>(p, dtype, n_blocks, lds_bytes, s));

@@ -260,8 +260,9 @@ def test_colour_model_validation():
     assert L.ddvr_adjoint_workspace_size(B(vol), B(cam), 0.05, C, d.ADJ_CHECKPOINT,
                                          B(n)) == d.ERR_UNSUPPORTED
     dirs = (d.Direction * 1)()
-    assert L.ddvr_render_tangent(B(vol), None, B(cam), 0.1, C, dirs, 1, 0x3000, None, None, None,
-                                 0, None) == d.ERR_UNSUPPORTED
+    # forward mode takes the colour volume; its 4-channel data must be aligned
+    assert L.ddvr_render_tangent(B(d.Volume(0x1008, d.F32, 8, 8, 8)), None, B(cam), 0.1, C,
+                                 dirs, 1, 0x3000, None, None, None, 0, None) == d.ERR_VALUE
     h = ctypes.c_void_p()
     views = (d.View * 1)(d.View(0, -1, cam, 0.1, 0x3000, None, None, None, None, None))
     vols = (d.Volume * 1)(vol)

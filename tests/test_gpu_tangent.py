@@ -141,3 +141,32 @@ def test_tangent_low_precision_storage():
         ref = _oracle_dot(p, direction)
         ok = keep & ~_unstable(p, direction, ref)
         assert_grad_close(dot[k][ok], ref[ok], f"bf16 dir {k}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_colour_volume_tangents(storage):
+    """Forward mode on the pre-shaded colour volume: tangent images against the
+    oracle's dual numbers, the image bitwise the forward's, and the
+    forward-delayed contraction against the oracle adjoint."""
+    from test_gpu_color import color_problem
+    p = color_problem(storage=storage, W=48, H=40)
+    rng = np.random.default_rng(24)
+    _say(f"colour tangents {storage}")
+    dirs = _directions(p, rng)[:4]
+    ora = oracle_forward(p)
+    keep = ~(tie_mask(ora["ratio"]) | kink_mask(p))
+    img, dot, _ = _gpu_tangent(p, dirs)
+    fwd, _ = gpu_forward(p)
+    assert np.array_equal(img, fwd)
+    for k, direction in enumerate(dirs):
+        ref = _oracle_dot(p, direction)
+        ok = keep & ~_unstable(p, direction, ref)
+        assert ok.sum() >= 0.95 * keep.sum()
+        assert_grad_close(dot[k][ok], ref[ok], f"colour image_dot dir {k}")
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[~keep] = 0.0
+    _, _, dd = _gpu_tangent(p, dirs, d_image=g)
+    adj = oracle_adjoint(p, g)
+    refd = np.array([np.dot(adj["dcam"], np.asarray(x[:12], np.float64)) + adj["dstep"] * x[12]
+                     for x in dirs])
+    assert_grad_close(dd, refd, "colour forward-delayed")
