@@ -149,7 +149,7 @@ class ViewpointFunction(torch.autograd.Function):
             tf = tf.contiguous()
         pose = [float(t) for t in (yaw, pitch, dist, fovy)]
         cam = _d.camera_from_sphere(*pose, width, height)
-        C = 4 if model == _d.EMISSION_ABSORPTION else 1
+        C = 1 if model == _d.ABSORPTION else 4
         image = torch.empty((height, width, C) if C == 4 else (height, width),
                             device=volume.device, dtype=torch.float32)
         trans = torch.empty((height, width), device=volume.device, dtype=torch.float32)

@@ -170,3 +170,34 @@ def test_autograd_colour_volume(storage):
     got = np.array([yaw.grad.item(), pitch.grad.item()])
     assert_grad_close(got, sph[:2], "autograd colour yaw/pitch", rtol=2e-3)
     assert_grad_close([step.grad.item()], [ref["dstep"]], "autograd colour step")
+
+
+def test_viewpoint_autograd_colour_volume():
+    """The forward-mode viewpoint wrapper on the colour volume: pose and step
+    gradients from the tangent pass, volume gradient from the adjoint."""
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    from test_gpu_color import color_problem
+    p = color_problem(W=48, H=40)
+    _say("viewpoint autograd colour")
+    ora = oracle_forward(p)
+    mask = tie_mask(ora["ratio"]) | kink_mask(p)
+    rng = np.random.default_rng(25)
+    g = rng.normal(size=ora["image"].shape) / ora["image"].size
+    g[mask] = 0.0
+    dev = torch.device("cuda")
+    V = torch.from_numpy(p.volume).to(dev).requires_grad_(True)
+    yaw, pitch, dist = (torch.tensor(math.radians(p.yaw), requires_grad=True),
+                        torch.tensor(math.radians(p.pitch), requires_grad=True),
+                        torch.tensor(p.dist, requires_grad=True))
+    step = torch.tensor(p.step, requires_grad=True)
+    img = ag.render_viewpoint(V, None, yaw, pitch, dist, math.radians(p.fovy), step, d.COLOR,
+                              p.W, p.H)
+    gt = torch.from_numpy(g.reshape(p.H, p.W, 4).astype(np.float32)).to(dev)
+    (img * gt).sum().backward()
+    ref = oracle_adjoint(p, g)
+    assert_dv_close(V.grad.double().cpu().numpy(), ref["dV"], "viewpoint colour dV")
+    sph = oracle.sphere_grad(ref["dcam"], p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H)
+    got = np.array([yaw.grad.item(), pitch.grad.item(), dist.grad.item()])
+    assert_grad_close(got, sph[:3], "viewpoint colour yaw/pitch/dist", rtol=2e-3)
+    assert_grad_close([step.grad.item()], [ref["dstep"]], "viewpoint colour step")
