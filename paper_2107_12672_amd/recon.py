@@ -20,6 +20,10 @@ batch); Adam's moments restart at every level; densities are clamped at 0.
 
 `Reconstructor` plans every level's batches and allocates its buffers once;
 `run()` then executes the schedule from a zero grid.
+
+`optimize_tf` is the TF reconstruction of Sec. 5.2 through the same entry
+points: a fused L1 batch pass into the TF gradient, the TF smoothing prior
+and Adam on the table, per step.
 """
 from __future__ import annotations
 
@@ -142,3 +146,44 @@ def reconstruct(targets, cams, sched: Schedule, stream=None, on_step=None) -> Re
         return r.run(on_step)
     finally:
         r.close()
+
+
+@dataclass
+class TFSchedule:
+    """TF reconstruction (Sec. 5.2): L1 image loss plus lambda times the
+    smoothing prior of eq. (tf-loss), Adam with lr 0.8, all views in one batch
+    per step (an "epoch" of the paper's 8 views)."""
+    steps: int = 200
+    lr: float = 0.8
+    prior: float = 0.4
+
+
+def optimize_tf(volume, tf0, targets, cams, step_world: float, sched: TFSchedule,
+                stream=None):
+    """volume: stored grid [nz][ny][nx] (device); tf0: [R][4] float32 start;
+    targets: [V][H][W][4] emission-absorption images.  Returns (tf, losses):
+    the optimised table (clamped to >= 0) and the loss of every step."""
+    import torch
+    dev = targets.device
+    nview, H, W, _ = targets.shape
+    tf = tf0.clone().contiguous()
+    grad = torch.zeros_like(tf)
+    m = torch.zeros_like(tf)
+    v = torch.zeros_like(tf)
+    images = torch.empty_like(targets)
+    trans = torch.empty((nview, H, W), device=dev)
+    views = [d.make_view(0, cams[i], step_world, images[i], transmittance=trans[i],
+                         target=targets[i], tf_index=0) for i in range(nview)]
+    b = d.Batch([volume], [tf], views, d.EMISSION_ABSORPTION, flags=d.LOSS_L1,
+                d_tfs=[grad], stream=stream)
+    ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+    losses = torch.zeros(sched.steps, dtype=torch.float64, device=dev)
+    try:
+        for t in range(1, sched.steps + 1):
+            loss = losses[t - 1:t]
+            b.run(d.PASS_FUSED, 1.0 / targets.numel(), loss, workspace=ws, stream=stream)
+            d.tf_prior(tf, sched.prior, grad, loss, stream)
+            d.adam_step(tf, grad, m, v, t, sched.lr, lo=0.0, zero_grad=True, stream=stream)
+    finally:
+        b.close()
+    return tf, losses
