@@ -9,6 +9,11 @@ a PyTorch custom operation with a backward pass, Sec. 4.4 last paragraph).
   ``ddvr_cast_volume``); backward = ``ddvr_render_adjoint`` in AUTO mode, i.e.
   the inversion trick with the segment-checkpoint fallback for nearly opaque
   rays.  Gradients are returned in float32 for the master grid.
+* :class:`BatchFunction` -- V views of one grid rendered by one batched
+  forward launch (``ddvr_batch_run``, forward pass) and differentiated by one
+  batched adjoint launch (AUTO mode), with gradients to the grid, the TF, every
+  view's camera frame and the shared step.  The batch is planned once in the
+  forward and kept for the backward.
 * :class:`ViewpointFunction` -- the same render with the camera given as its
   sphere pose; the gradients of the pose and the step come from forward-mode
   derivatives (``ddvr_render_tangent``, "forward-delayed" of Sec. 5.1: the
@@ -197,6 +202,87 @@ class ViewpointFunction(torch.autograd.Function):
                               _d.grads_desc(dV, dTF), workspace=ws)
             grads[0], grads[1] = dV, dTF
         return tuple(grads)
+
+
+class BatchFunction(torch.autograd.Function):
+    """images = render(volume, tf, frames[v], step) for v < V.
+
+    volume  float32 master grid, as for DDVRFunction (colour: [nz][ny][nx][4])
+    tf      float32 [R][4] device tensor, or None (absorption-only, colour)
+    frames  float32 [V][12] tensor (any device) -- one camera frame per view
+    step    scalar tensor, world units, shared by the views
+    Returns [V][H][W][4] (emission-absorption, colour) or [V][H][W].
+    """
+
+    @staticmethod
+    def forward(ctx, volume, tf, frames, step, model: int, width: int, height: int,
+                storage: torch.dtype = torch.float32):
+        stored = _stored(volume, storage)
+        if model == _d.EMISSION_ABSORPTION:
+            if tf is None:
+                raise ValueError("emission-absorption needs a transfer function")
+            tf = tf.contiguous()
+        else:
+            tf = None
+        if frames.dim() != 2 or frames.shape[1] != 12 or frames.shape[0] < 1:
+            raise ValueError("frames must be [V][12]")
+        nview = frames.shape[0]
+        dev = volume.device
+        need = ctx.needs_input_grad
+        C = 1 if model == _d.ABSORPTION else 4
+        shape = (nview, height, width, C) if C == 4 else (nview, height, width)
+        images = torch.empty(shape, device=dev, dtype=torch.float32)
+        trans = torch.empty((nview, height, width), device=dev, dtype=torch.float32)
+        g_buf = torch.zeros_like(images)          # upstream gradient, filled by backward
+        dV = torch.zeros(stored.shape, device=dev, dtype=torch.float32) if need[0] else None
+        dTF = torch.zeros_like(tf) if (need[1] and tf is not None) else None
+        dcam = torch.zeros((nview, 12), device=dev, dtype=torch.float32) if need[2] else None
+        dstep = torch.zeros(1, device=dev, dtype=torch.float32) if need[3] else None
+        s = float(step)
+        host = frames.detach().to("cpu", torch.float32)
+        views = [_d.make_view(0, _camera_struct(host[i], width, height), s, images[i], trans[i],
+                              d_image=g_buf[i], d_camera=None if dcam is None else dcam[i],
+                              d_step=dstep, tf_index=0 if tf is not None else -1)
+                 for i in range(nview)]
+        batch = _d.Batch([stored], None if tf is None else [tf], views, model,
+                         d_volumes=None if dV is None else [dV],
+                         d_tfs=None if dTF is None else [dTF])
+        batch.run(_d.PASS_FORWARD)
+        # the batch keeps raw pointers to the images: the version check of
+        # saved tensors catches in-place changes before the adjoint reads them
+        ctx.save_for_backward(images, trans)
+        ctx.batch = batch
+        ctx.bufs = (stored, tf, g_buf, dV, dTF, dcam, dstep)
+        ctx.frames_device = frames.device
+        ctx.step_device = step.device if isinstance(step, torch.Tensor) else torch.device("cpu")
+        return images
+
+    @staticmethod
+    def backward(ctx, g_images):
+        ctx.saved_tensors
+        stored, tf, g_buf, dV, dTF, dcam, dstep = ctx.bufs
+        if dV is None and dTF is None and dcam is None and dstep is None:
+            return (None,) * 8
+        g_buf.copy_(g_images)
+        for t in (dV, dTF, dcam, dstep):
+            if t is not None:
+                t.zero_()
+        n = ctx.batch.workspace_size()
+        ws = torch.empty((n + 3) // 4, device=stored.device, dtype=torch.int32) if n else None
+        ctx.batch.run(_d.PASS_ADJOINT, workspace=ws)
+        g_frames = dcam.to(ctx.frames_device) if dcam is not None else None
+        g_step = dstep.reshape(()).to(ctx.step_device) if dstep is not None else None
+        return dV, dTF, g_frames, g_step, None, None, None, None
+
+
+def render_batch(volume: torch.Tensor, tf: Optional[torch.Tensor], frames: torch.Tensor, step,
+                 model: int, width: int, height: int,
+                 storage: torch.dtype = torch.float32) -> torch.Tensor:
+    """Differentiable render of V views of one grid in one batched launch per
+    pass (see BatchFunction)."""
+    if not isinstance(step, torch.Tensor):
+        step = torch.tensor(float(step))
+    return BatchFunction.apply(volume, tf, frames, step, model, width, height, storage)
 
 
 def render_viewpoint(volume: torch.Tensor, tf: Optional[torch.Tensor], yaw, pitch, dist, fovy,

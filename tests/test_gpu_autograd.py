@@ -9,8 +9,9 @@ import pytest
 
 import oracle
 import synth
-from harness import (Problem, assert_dv_close, assert_grad_close, dequantized, kink_mask,
-                     oracle_adjoint, oracle_camera, oracle_forward, tie_mask)
+from harness import (Problem, assert_dv_close, assert_grad_close, assert_images_close,
+                     dequantized, gpu_camera, kink_mask, oracle_adjoint, oracle_camera,
+                     oracle_forward, tie_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -201,3 +202,68 @@ def test_viewpoint_autograd_colour_volume():
     got = np.array([yaw.grad.item(), pitch.grad.item(), dist.grad.item()])
     assert_grad_close(got, sph[:3], "viewpoint colour yaw/pitch/dist", rtol=2e-3)
     assert_grad_close([step.grad.item()], [ref["dstep"]], "viewpoint colour step")
+
+
+@pytest.mark.parametrize("case", ["ea-f32", "ea-bf16", "ao-bf16", "colour-bf16"])
+def test_batch_autograd_matches_oracle(case):
+    """The batched wrapper: 3 views of one grid in one forward and one adjoint
+    launch.  Images per view, the grid (and TF) gradient summed over the views,
+    every view's camera-frame gradient and the shared step gradient, against
+    the oracle view by view."""
+    import dataclasses
+    import torch
+    from paper_2107_12672_amd import autograd as ag, ddvr as d
+    from test_gpu_color import color_problem
+    model_name, storage = case.split("-")
+    if model_name == "colour":
+        base = color_problem(storage=storage, W=48, H=40)
+    else:
+        base = _ea(storage)
+        if model_name == "ao":
+            base = dataclasses.replace(base, model=0, tf=None)
+    poses = [(base.yaw, base.pitch), (base.yaw + 71.0, base.pitch - 20.0),
+             (base.yaw - 133.0, base.pitch + 9.0)]
+    probs = [dataclasses.replace(base, yaw=y, pitch=pt) for y, pt in poses]
+    _say(f"batched autograd {case}, {len(probs)} views {base.W}x{base.H}")
+    rng = np.random.default_rng(25)
+    gs, oras = [], []
+    for p in probs:
+        ora = oracle_forward(p)
+        g = rng.normal(size=ora["image"].shape) / ora["image"].size
+        g[tie_mask(ora["ratio"]) | kink_mask(p)] = 0.0
+        gs.append(g)
+        oras.append(ora)
+    dev = torch.device("cuda")
+    V = torch.from_numpy(base.volume).to(dev).requires_grad_(True)
+    T = None
+    if base.model == 1:
+        T = torch.from_numpy(base.tf).to(dev).requires_grad_(True)
+    step = torch.tensor(base.step, requires_grad=True)
+    frames = torch.tensor([gpu_camera(p).frame() for p in probs], dtype=torch.float32,
+                          requires_grad=True)
+    sdt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
+    model = {"ea": d.EMISSION_ABSORPTION, "ao": d.ABSORPTION, "colour": d.COLOR}[model_name]
+    imgs = ag.render_batch(V, T, frames, step, model, base.W, base.H, storage=sdt)
+    C = base.C
+    shape = (base.H, base.W, C) if C == 4 else (base.H, base.W)
+    assert imgs.shape == (len(probs),) + shape
+    for i, ora in enumerate(oras):
+        got = imgs[i].detach().double().cpu().numpy().reshape(ora["image"].shape)
+        assert_images_close(got, ora, f"batched {case} view {i} image")
+    gt = torch.from_numpy(np.stack([g.reshape(shape) for g in gs]).astype(np.float32)).to(dev)
+    (imgs * gt).sum().backward()
+    refs = [oracle_adjoint(p, g) for p, g in zip(probs, gs)]
+    dV = sum(r["dV"] for r in refs)
+    assert_dv_close(V.grad.double().cpu().numpy(), dV, f"batched {case} dV")
+    if T is not None:
+        assert_grad_close(T.grad.double().cpu().numpy(), sum(r["dTF"] for r in refs),
+                          f"batched {case} dTF")
+    for i, r in enumerate(refs):
+        assert_grad_close(frames.grad[i].double().numpy(), r["dcam"], f"batched {case} view {i} dcam")
+    assert_grad_close([step.grad.item()], [sum(r["dstep"] for r in refs)], f"batched {case} step")
+    # a second backward through a new forward reuses nothing stale
+    V.grad = None
+    imgs2 = ag.render_batch(V, T, frames.detach(), float(base.step), model, base.W, base.H,
+                            storage=sdt)
+    (imgs2 * gt).sum().backward()
+    assert_dv_close(V.grad.double().cpu().numpy(), dV, f"batched {case} dV again")
