@@ -248,19 +248,20 @@ class BatchFunction(torch.autograd.Function):
                          d_volumes=None if dV is None else [dV],
                          d_tfs=None if dTF is None else [dTF])
         batch.run(_d.PASS_FORWARD)
-        # the batch keeps raw pointers to the images: the version check of
-        # saved tensors catches in-place changes before the adjoint reads them
-        ctx.save_for_backward(images, trans)
+        # the batch keeps raw pointers to the grid, the TF and the images: the
+        # version check of saved tensors catches in-place changes to any of
+        # them before the adjoint reads them
+        ctx.save_for_backward(stored, tf if tf is not None else torch.empty(0), images, trans)
         ctx.batch = batch
-        ctx.bufs = (stored, tf, g_buf, dV, dTF, dcam, dstep)
+        ctx.bufs = (g_buf, dV, dTF, dcam, dstep)
         ctx.frames_device = frames.device
         ctx.step_device = step.device if isinstance(step, torch.Tensor) else torch.device("cpu")
         return images
 
     @staticmethod
     def backward(ctx, g_images):
-        ctx.saved_tensors
-        stored, tf, g_buf, dV, dTF, dcam, dstep = ctx.bufs
+        stored = ctx.saved_tensors[0]
+        g_buf, dV, dTF, dcam, dstep = ctx.bufs
         if dV is None and dTF is None and dcam is None and dstep is None:
             return (None,) * 8
         g_buf.copy_(g_images)

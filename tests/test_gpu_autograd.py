@@ -267,3 +267,11 @@ def test_batch_autograd_matches_oracle(case):
                             storage=sdt)
     (imgs2 * gt).sum().backward()
     assert_dv_close(V.grad.double().cpu().numpy(), dV, f"batched {case} dV again")
+    if storage == "f32":
+        # the float32 grid is rendered in place: changing it before the
+        # backward must be refused, not differentiated at the new values
+        imgs3 = ag.render_batch(V, T, frames.detach(), float(base.step), model, base.W, base.H)
+        with torch.no_grad():
+            V.mul_(1.0)
+        with pytest.raises(RuntimeError):
+            imgs3.sum().backward()
