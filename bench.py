@@ -429,12 +429,20 @@ def secondary(args):
                     "paper_2107_12672_amd/csrc/ddvr_internal.h"):
             with open(os.path.join(ROOT, rel), "rb") as f:
                 h.update(f.read())
+        tr = None
+        try:
+            with open(os.path.join(ROOT, "profiles", "traffic_dfc.json")) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha") == h.hexdigest()[:16]:
+                tr = t.get("bytes_per_launch")
+        except (OSError, ValueError):
+            pass
         if vc and vc.get("kernel_source_sha") == h.hexdigest()[:16]:
             ops = nvox * ncand * vc["valu_per_candidate"]
             a = ops / (ms * 1e-3) / 1e12
             out["roofline"] = {"bound": "alu", "achieved": round(a, 3), "peak": VALU_PEAK_TOPS,
                                "unit": "TOP/s", "frac": round(a / VALU_PEAK_TOPS, 4),
-                               "traffic": None, "kernel": "k_density_from_color<bf16>",
+                               "traffic": tr, "kernel": "k_density_from_color<bf16>",
                                "kernel_ms": round(ms, 4), "ops_per_launch": ops,
                                "ops": "VALU lane-operations: %d per candidate" %
                                       vc["valu_per_candidate"]}
