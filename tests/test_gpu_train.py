@@ -352,3 +352,37 @@ def test_tf_reconstruction_loop():
     e0 = np.abs(tf0.cpu().numpy() - tf_true).mean()
     e1 = np.abs(tf.cpu().numpy() - tf_true).mean()
     assert e1 < e0
+
+
+def test_viewpoint_selection_loop():
+    """Sec. 5.1's best-viewpoint selection through the library: eight runs from
+    the paper's starting poses, 20 iterations each.  OE never rises along a
+    run, most runs lower it, the best run beats the median of 64 poses spread
+    over the sphere, and the OE reported at the best run's final pose is the
+    oracle's OE of the oracle's image there."""
+    import dataclasses
+    from paper_2107_12672_amd import viewpoint as vp
+    _say("viewpoint selection loop")
+    p = ea_problem(W=64, H=64)
+    vol = device_volume(p)
+    tf = _t(p.tf)
+    sched = vp.ViewpointSchedule(iterations=20, width=64, height=64)
+    runs = vp.optimize_viewpoint(vol, tf, p.step, sched)
+    assert len(runs) == 8
+    for r in runs:
+        assert len(r.oe) == 21 and len(r.poses) == 21
+        assert all(b <= a for a, b in zip(r.oe, r.oe[1:]))
+        assert all(abs(pt) < 0.5 * math.pi for _, pt in r.poses)
+    lowered = sum(r.oe[-1] < r.oe[0] for r in runs)
+    assert lowered >= 6, [(r.oe[0], r.oe[-1]) for r in runs]
+    obj = vp._Objective(vol, tf, p.step, sched, None)
+    sampled = [obj.value(math.radians(y), math.radians(pt)) for y, pt in synth.fibonacci_sphere(64)]
+    best = min(runs, key=lambda r: r.oe[-1])
+    print(f"[result] viewpoint: starts {min(r.oe[0] for r in runs):.5f}, best run "
+          f"{best.oe[-1]:.5f}; 64 sampled poses min {min(sampled):.5f} median "
+          f"{float(np.median(sampled)):.5f}", flush=True)
+    assert best.oe[-1] <= float(np.median(sampled))
+    y, pt = best.poses[-1]
+    q = dataclasses.replace(p, yaw=math.degrees(y), pitch=math.degrees(pt))
+    H_ref, _ = OL.opacity_entropy(oracle_forward(q)["image"][:, 3])
+    assert best.oe[-1] == pytest.approx(H_ref, rel=1e-5)
