@@ -24,6 +24,10 @@ batch); Adam's moments restart at every level; densities are clamped at 0.
 `optimize_tf` is the TF reconstruction of Sec. 5.2 through the same entry
 points: a fused L1 batch pass into the TF gradient, the TF smoothing prior
 and Adam on the table, per step.
+
+`reconstruct_via_color` is the pipeline of Sec. 5.4 for non-monotonic TFs:
+colour volume from the images, densities from the colour volume, density
+optimisation with the TF.
 """
 from __future__ import annotations
 
@@ -187,3 +191,107 @@ def optimize_tf(volume, tf0, targets, cams, step_world: float, sched: TFSchedule
     finally:
         b.close()
     return tf, losses
+
+
+@dataclass
+class ColorPipelineSchedule:
+    """The pipeline of Sec. 5.4: a pre-shaded colour volume reconstructed from
+    the images, densities estimated from it through the TF, then the density
+    optimisation with the TF from that start."""
+    color_steps: int = 200
+    color_lr: float = 0.05
+    dfc_sweeps: int = 10
+    dfc_stop: float = 1e-3     # stop once fewer than this fraction of voxels change
+    ncand: int = 256
+    beta: float = 1.0
+    density_steps: int = 100
+    density_lr: float = 0.02
+    prior: float = 20.0
+    seed: int = 0
+
+
+@dataclass
+class ColorPipelineResult:
+    color: object = None           # [n][n][n][4] float32: the reconstructed colour volume
+    density_init: object = None    # [n][n][n] float32: the estimate from the colour volume
+    density: object = None         # [n][n][n] float32: after the density optimisation
+    color_losses: object = None    # [color_steps] float64 (device)
+    density_losses: object = None  # [density_steps] float64 (device): L1 + prior
+    sweeps: int = 0
+
+
+def reconstruct_via_color(targets, cams, tf, n: int, step_world: float,
+                          sched: ColorPipelineSchedule = None, stream=None) -> ColorPipelineResult:
+    """targets: [V][H][W][4] emission-absorption images of an unknown density
+    grid under the known TF `tf` ([R][4] float32, device); cams: their V
+    cameras; n: edge of the grid to reconstruct (float32 throughout).
+
+    Readings (the paper is silent): the colour volume is reconstructed at the
+    final resolution only (the library's resampling is scalar) with the L1
+    loss alone, starting from zero and clamped to [0, inf); the densities are
+    clamped to [0, 1], the range the TF covers; the TF stays fixed."""
+    import torch
+    sched = sched or ColorPipelineSchedule()
+    dev = targets.device
+    nview, H, W, _ = targets.shape
+    scale = 1.0 / targets.numel()
+    res = ColorPipelineResult()
+    images = torch.empty_like(targets)
+    trans = torch.empty((nview, H, W), device=dev)
+
+    def views():
+        return [d.make_view(0, cams[i], step_world, images[i], transmittance=trans[i],
+                            target=targets[i], tf_index=0) for i in range(nview)]
+
+    # 1. the colour volume from the images
+    color = torch.zeros((n, n, n, 4), device=dev)
+    cg, cm, cv = (torch.zeros_like(color) for _ in range(3))
+    res.color_losses = torch.zeros(sched.color_steps, dtype=torch.float64, device=dev)
+    b = d.Batch([color], None, views(), d.COLOR, flags=d.LOSS_L1, d_volumes=[cg], stream=stream)
+    try:
+        for t in range(1, sched.color_steps + 1):
+            b.run(d.PASS_FUSED, scale, res.color_losses[t - 1:t], stream=stream)
+            d.adam_step(color, cg, cm, cv, t, sched.color_lr, lo=0.0, zero_grad=True,
+                        stream=stream)
+    finally:
+        b.close()
+    res.color = color
+    del cg, cm, cv
+
+    # 2. densities from the colour volume (Jacobi sweeps, alpha = 1/max tau)
+    a = torch.zeros((n, n, n), device=dev)
+    bb = torch.zeros_like(a)
+    nch = torch.zeros(1, dtype=torch.int32, device=dev)
+    alpha = d.density_from_color(color, tf, a, seed=sched.seed, sweep=0, ncand=sched.ncand,
+                                 stream=stream)
+    cur, nxt = a, bb
+    res.sweeps = 1
+    for s in range(1, sched.dfc_sweeps):
+        nch.zero_()
+        d.density_from_color(color, tf, nxt, d_prev=cur, alpha=alpha, beta=sched.beta,
+                             seed=sched.seed, sweep=s, ncand=sched.ncand, n_changed=nch,
+                             stream=stream)
+        cur, nxt = nxt, cur
+        res.sweeps += 1
+        if int(nch.item()) < sched.dfc_stop * cur.numel():
+            break
+    res.density_init = cur.clone()
+
+    # 3. the density optimisation with the TF, from that start
+    dens = cur
+    dg, dm, dv = (torch.zeros_like(dens) for _ in range(3))
+    res.density_losses = torch.zeros(sched.density_steps, dtype=torch.float64, device=dev)
+    b = d.Batch([dens], [tf], views(), d.EMISSION_ABSORPTION, flags=d.LOSS_L1, d_volumes=[dg],
+                stream=stream)
+    ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+    try:
+        for t in range(1, sched.density_steps + 1):
+            loss = res.density_losses[t - 1:t]
+            b.run(d.PASS_FUSED, scale, loss, workspace=ws, stream=stream)
+            d.volume_prior(dens, sched.prior, dg, loss, stream)
+            d.adam_step(dens, dg, dm, dv, t, sched.density_lr, lo=0.0, hi=1.0, zero_grad=True,
+                        stream=stream)
+    finally:
+        b.close()
+    res.density = dens
+    return res
