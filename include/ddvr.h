@@ -370,7 +370,10 @@ int ddvr_volume_prior(const float* volume, int32_t nx, int32_t ny, int32_t nz, f
                       float* d_volume, double* loss_out, void* hip_stream);
 
 /* Opacity entropy of Sec. 5.1, OE = H(alpha) over the npix alphas of an
- * image, H(x) = 1/log2(N) sum p_i log2 p_i, p_i = x_i / sum x (0 log 0 = 0).
+ * image, with H the normalised entropy H(x) = -1/log2(N) sum p_i log2 p_i,
+ * p_i = x_i / sum x (0 log 0 = 0), in [0, 1].  (The paper prints H without
+ * the minus sign, yet reports positive entropies that viewpoint selection
+ * maximises; the sign is read as lost.)
  *   image     [npix][channels] float32, channels 4 (alpha = channel 3) or 1.
  *   work      two doubles of scratch (overwritten).
  *   value_out one double, written (or NULL).

@@ -12,10 +12,12 @@ What it computes (Weiss & Westermann, arXiv 2107.12672):
   * the same prior on the densities in 3D (Sec. 5.3: "computed on the
     reconstructed volume densities in 3D"), read as the mean over all pairs of
     grid neighbours along x, y and z of the squared difference;
-  * the opacity entropy of Sec. 5.1, OE(C) = H(C[:, :, 3]) with
-    H(x) = 1/log2(N) sum_i p_i log2 p_i, p_i = x_i / sum_j x_j (0 log 0 = 0),
-    and its gradient; pixels with zero alpha, where the derivative is
-    unbounded, get none;
+  * the opacity entropy of Sec. 5.1, OE(C) = H(C[:, :, 3]) with H the
+    normalised entropy H(x) = -1/log2(N) sum_i p_i log2 p_i,
+    p_i = x_i / sum_j x_j (0 log 0 = 0), in [0, 1] -- the paper prints H
+    without the minus sign but reports positive entropies, which viewpoint
+    selection maximises, so the sign is read as lost -- and its gradient;
+    pixels with zero alpha, where the derivative is unbounded, get none;
   * one Adam step (Kingma and Ba 2014, Algorithm 1), with an optional clamp of
     the parameters after the step;
   * trilinear resampling of a vertex grid onto a finer one spanning the same
@@ -74,7 +76,8 @@ def volume_prior(V, lam):
 
 
 def opacity_entropy(alpha):
-    """OE = H(alpha) over the linearised alpha channel, and dOE/dalpha."""
+    """OE = H(alpha) over the linearised alpha channel (normalised entropy,
+    in [0, 1]), and dOE/dalpha."""
     x = np.asarray(alpha, np.float64).ravel()
     N = x.size
     S = x.sum()
@@ -82,11 +85,11 @@ def opacity_entropy(alpha):
     pos = p > 0
     lp = np.zeros_like(p)
     lp[pos] = np.log2(p[pos])
-    H = (p * lp).sum() / np.log2(N)
-    # dH/dx_j = (log2 p_j - sum_i p_i log2 p_i) / (S log2 N), derived from
+    H = -(p * lp).sum() / np.log2(N)
+    # dH/dx_j = (sum_i p_i log2 p_i - log2 p_j) / (S log2 N), derived from
     # d p_i / d x_j = (delta_ij - p_i) / S; unbounded at p_j = 0 (none given)
     g = np.zeros_like(p)
-    g[pos] = (lp[pos] - (p * lp).sum()) / (S * np.log2(N))
+    g[pos] = ((p * lp).sum() - lp[pos]) / (S * np.log2(N))
     return H, g.reshape(np.shape(alpha))
 
 

@@ -100,19 +100,20 @@ __global__ __launch_bounds__(kNT) void k_entropy_sums(const float* img, int64_t 
   block_add(u, work + 1);
 }
 
-// pass 2: H = (U/S - log2 S)/log2 N; dH/dx_j = (log2 x_j - U/S)/(S log2 N)
-// (x_j > 0; the derivative is unbounded at 0, where none is added)
+// pass 2: OE = (log2 S - U/S)/log2 N, the normalised entropy -sum p log2 p /
+// log2 N with p = x/S; dOE/dx_j = (U/S - log2 x_j)/(S log2 N) (x_j > 0; the
+// derivative is unbounded at 0, where none is added)
 __global__ __launch_bounds__(kNT) void k_entropy_grad(const float* img, int64_t n, int stride,
                                                       int offset, const double* work,
                                                       double* value, float* dimg, float scale) {
   const double S = work[0], U = work[1];
   const double l2n = log2((double)n);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && value) *value = (U / S - log2(S)) / l2n;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && value) *value = (log2(S) - U / S) / l2n;
   if (!dimg) return;
   const double k = (double)scale / (S * l2n), US = U / S;
   for (int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x; j < n; j += (int64_t)gridDim.x * kNT) {
     const float x = img[j * stride + offset];
-    if (x > 0.0f) dimg[j * stride + offset] += (float)(k * (log2((double)x) - US));
+    if (x > 0.0f) dimg[j * stride + offset] += (float)(k * (US - log2((double)x)));
   }
 }
 

@@ -2,9 +2,8 @@
 
 The camera sits on a sphere around the volume, looking at its centre, and is
 parameterised by longitude (yaw) and latitude (pitch).  The objective is the
-opacity entropy OE(C) = H(C[:, :, 3]) of the emission-absorption image, with H
-as the paper prints it (1/log2 N sum p log2 p, i.e. minus the normalised
-entropy), so descending OE maximises the visual entropy.  Per iteration:
+opacity entropy OE(C) = H(C[:, :, 3]) of the emission-absorption image, H the
+normalised entropy, which the runs maximise.  Per iteration:
   1. render the view (``ddvr_render_forward``);
   2. OE and its image gradient (``ddvr_opacity_entropy``);
   3. d OE / d (yaw, pitch) by forward mode, forward-delayed: one tangent pass
@@ -14,9 +13,9 @@ The runs start from the paper's eight poses (longitudes 45, 135, 225, 315
 degrees, latitudes +-45 degrees) and take 20 iterations each.
 
 Reading (the paper gives neither the step rule nor its length): a step moves
-the pose by `step` radians against the normalised gradient; a step that does
-not lower OE is not taken and halves the step length, so every run's OE is
-non-increasing.  The latitude is kept `pole_margin` radians away from the
+the pose by `step` radians along the normalised gradient; a step that does
+not raise OE is not taken and halves the step length, so every run's OE is
+non-decreasing.  The latitude is kept `pole_margin` radians away from the
 poles, where the camera's up vector is undefined.
 """
 from __future__ import annotations
@@ -106,10 +105,10 @@ def optimize_viewpoint(volume, tf, step_world: float, sched: ViewpointSchedule =
             norm = math.hypot(gy, gp)
             if not norm > 0.0:
                 break
-            ny = yaw - length * gy / norm
-            npitch = min(max(pitch - length * gp / norm, -lat_max), lat_max)
+            ny = yaw + length * gy / norm
+            npitch = min(max(pitch + length * gp / norm, -lat_max), lat_max)
             new = obj.value(ny, npitch, with_grad=True)
-            if new < cur:
+            if new > cur:
                 yaw, pitch, cur = ny, npitch, new
             else:
                 length *= 0.5

@@ -668,12 +668,15 @@ def test_volume_prior_closed_forms_and_finite_differences():
 def test_opacity_entropy_closed_forms_invariance_and_finite_differences():
     N = 37
     H, g = OL.opacity_entropy(np.full(N, 0.3))
-    assert H == pytest.approx(-1.0, rel=1e-14)                # uniform: log2(1/N)/log2 N
+    assert H == pytest.approx(1.0, rel=1e-14)                 # uniform: -log2(1/N)/log2 N
     assert np.abs(g).max() < 1e-15                             # the uniform point is stationary
     one = np.zeros(N); one[5] = 0.7
     assert OL.opacity_entropy(one)[0] == 0.0                   # one-hot: 1 log 1 = 0
+    two = np.zeros(N); two[[3, 9]] = 0.2
+    assert OL.opacity_entropy(two)[0] == pytest.approx(1.0 / np.log2(N), rel=1e-14)  # 1 bit
     x = np.random.default_rng(62).uniform(0.05, 1.0, (5, 7))
     H, g = OL.opacity_entropy(x)
+    assert 0.0 < H < 1.0                                       # between one-hot and uniform
     assert OL.opacity_entropy(3.0 * x)[0] == pytest.approx(H, rel=1e-13)   # scale-free
     assert abs((x * g).sum()) < 1e-12                          # Euler: degree-0 homogeneous
     assert np.allclose(g, _fd(lambda a: OL.opacity_entropy(a)[0], x), atol=1e-8)
