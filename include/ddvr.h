@@ -401,6 +401,14 @@ int ddvr_adam_step(float* param, float* grad, float* m, float* v, int64_t n, int
 int ddvr_resample_volume(const float* src, int32_t sx, int32_t sy, int32_t sz, float* dst,
                          int32_t dx, int32_t dy, int32_t dz, void* hip_stream);
 
+/* The same on a grid of `channels` (1..4) interleaved float32 values per
+ * vertex, src [sz][sy][sx][channels], dst [dz][dy][dx][channels], each channel
+ * resampled on its own (the colour volume of Sec. 5.4 under the same
+ * multi-resolution schedule).  ddvr_resample_volume is channels = 1. */
+int ddvr_resample_channels(const float* src, int32_t channels, int32_t sx, int32_t sy,
+                           int32_t sz, float* dst, int32_t dx, int32_t dy, int32_t dz,
+                           void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many views of one or several grids in ONE launch.
  * ------------------------------------------------------------------------ */

@@ -755,20 +755,29 @@ int ddvr_adam_step(float* param, float* grad, float* m, float* v, int64_t n, int
   return e == hipSuccess ? DDVR_OK : hip_fail(e, "Adam launch");
 }
 
-int ddvr_resample_volume(const float* src, int32_t sx, int32_t sy, int32_t sz, float* dst,
-                         int32_t dx, int32_t dy, int32_t dz, void* hip_stream) {
+int ddvr_resample_channels(const float* src, int32_t channels, int32_t sx, int32_t sy,
+                           int32_t sz, float* dst, int32_t dx, int32_t dy, int32_t dz,
+                           void* hip_stream) {
   if (!src || !dst) return fail(DDVR_ERR_NULL, "src or dst is NULL");
+  if (channels < 1 || channels > 4) return fail(DDVR_ERR_VALUE, "channels=%d not in [1, 4]", channels);
   if (sx < 2 || sy < 2 || sz < 2 || dx < 2 || dy < 2 || dz < 2 ||
-      (int64_t)dx * dy * dz > ((int64_t)1 << 34) || (int64_t)sx * sy * sz > ((int64_t)1 << 34))
+      (int64_t)dx * dy * dz * channels > ((int64_t)1 << 34) ||
+      (int64_t)sx * sy * sz * channels > ((int64_t)1 << 34))
     return fail(DDVR_ERR_SHAPE, "resample %dx%dx%d -> %dx%dx%d", sx, sy, sz, dx, dy, dz);
   const char* a = reinterpret_cast<const char*>(src);
   const char* b = reinterpret_cast<const char*>(dst);
-  if (a < b + (int64_t)dx * dy * dz * 4 && b < a + (int64_t)sx * sy * sz * 4)
+  if (a < b + (int64_t)dx * dy * dz * channels * 4 && b < a + (int64_t)sx * sy * sz * channels * 4)
     return fail(DDVR_ERR_VALUE, "src and dst overlap");
   int rc;
   if ((rc = check_pending())) return rc;
-  const hipError_t e = (hipError_t)launch_resample(src, sx, sy, sz, dst, dx, dy, dz, hip_stream);
+  const hipError_t e =
+      (hipError_t)launch_resample(src, channels, sx, sy, sz, dst, dx, dy, dz, hip_stream);
   return e == hipSuccess ? DDVR_OK : hip_fail(e, "resample launch");
+}
+
+int ddvr_resample_volume(const float* src, int32_t sx, int32_t sy, int32_t sz, float* dst,
+                         int32_t dx, int32_t dy, int32_t dz, void* hip_stream) {
+  return ddvr_resample_channels(src, 1, sx, sy, sz, dst, dx, dy, dz, hip_stream);
 }
 
 int ddvr_adjoint_workspace_size(const ddvr_volume* vol, const ddvr_camera* cam, float step_world,

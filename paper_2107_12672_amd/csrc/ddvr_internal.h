@@ -119,8 +119,8 @@ int launch_opacity_entropy(const float* img, int64_t n, int stride, int offset, 
 int launch_adam(float* x, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                 float eps, float c1, float c2, float lo, float hi, void* store, int store_dtype,
                 int zero_grad, void* stream);
-int launch_resample(const float* src, int sx, int sy, int sz, float* dst, int dx, int dy,
-                    int dz, void* stream);
+int launch_resample(const float* src, int channels, int sx, int sy, int sz, float* dst, int dx,
+                    int dy, int dz, void* stream);
 // implemented in ddvr_dfc.hip
 int launch_density_from_color(const DfcParams& p, int dtype, void* stream);
 int launch_color_tau_max(const void* cv, int dtype, int64_t nvox, float* out, void* stream);

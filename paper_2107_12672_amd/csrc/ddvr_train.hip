@@ -195,8 +195,8 @@ __global__ __launch_bounds__(kNT) void k_adam(float* x, float* g, float* m, floa
 }
 
 // dst vertex (i, j, k) at source grid units (i (sx-1)/(dx-1), ...), trilinear
-__global__ __launch_bounds__(kNT) void k_resample(const float* src, int sx, int sy, int sz,
-                                                  float* dst, int dx, int dy, int dz) {
+__global__ __launch_bounds__(kNT) void k_resample(const float* src, int C, int sx, int sy,
+                                                  int sz, float* dst, int dx, int dy, int dz) {
   const int64_t dxy = (int64_t)dx * dy, n = dxy * dz;
   const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (i >= n) return;
@@ -215,15 +215,19 @@ __global__ __launch_bounds__(kNT) void k_resample(const float* src, int sx, int 
     k[a] = (int)kk;
     f[a] = (float)rem / (float)den;
   }
-  const int64_t sxy = (int64_t)sx * sy;
-  const float* b = src + (int64_t)k[2] * sxy + (int64_t)k[1] * sx + k[0];
-  const float c00 = fmaf(f[0], b[1] - b[0], b[0]);
-  const float c10 = fmaf(f[0], b[sx + 1] - b[sx], b[sx]);
-  const float c01 = fmaf(f[0], b[sxy + 1] - b[sxy], b[sxy]);
-  const float c11 = fmaf(f[0], b[sxy + sx + 1] - b[sxy + sx], b[sxy + sx]);
-  const float c0 = fmaf(f[1], c10 - c00, c00);
-  const float c1 = fmaf(f[1], c11 - c01, c01);
-  dst[i] = fmaf(f[2], c1 - c0, c0);
+  // C interleaved channels per vertex, each interpolated on its own
+  const int64_t ox = C, oy = (int64_t)C * sx, oz = (int64_t)C * sx * sy;
+  const float* b0 = src + k[2] * oz + k[1] * oy + k[0] * ox;
+  for (int c = 0; c < C; ++c) {
+    const float* b = b0 + c;
+    const float c00 = fmaf(f[0], b[ox] - b[0], b[0]);
+    const float c10 = fmaf(f[0], b[oy + ox] - b[oy], b[oy]);
+    const float c01 = fmaf(f[0], b[oz + ox] - b[oz], b[oz]);
+    const float c11 = fmaf(f[0], b[oz + oy + ox] - b[oz + oy], b[oz + oy]);
+    const float e0 = fmaf(f[1], c10 - c00, c00);
+    const float e1 = fmaf(f[1], c11 - c01, c01);
+    dst[i * C + c] = fmaf(f[2], e1 - e0, e0);
+  }
 }
 
 unsigned blocks_for(int64_t n, int64_t per_block) {
@@ -272,11 +276,12 @@ int launch_adam(float* x, float* g, float* m, float* v, int64_t n, float lr, flo
   return (int)hipGetLastError();
 }
 
-int launch_resample(const float* src, int sx, int sy, int sz, float* dst, int dx, int dy,
-                    int dz, void* stream) {
+int launch_resample(const float* src, int channels, int sx, int sy, int sz, float* dst, int dx,
+                    int dy, int dz, void* stream) {
   const int64_t n = (int64_t)dx * dy * dz;
   hipLaunchKernelGGL(k_resample, dim3(blocks_for(n, kNT)), dim3(kNT), 0,
-                     static_cast<hipStream_t>(stream), src, sx, sy, sz, dst, dx, dy, dz);
+                     static_cast<hipStream_t>(stream), src, channels, sx, sy, sz, dst, dx, dy,
+                     dz);
   return (int)hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "ddvr_batch_sample_count", "ddvr_cast_volume", "ddvr_set_tuning", "ddvr_get_tuning",
     "ddvr_render_tangent", "ddvr_camera_sphere_tangents", "ddvr_density_from_color",
     "ddvr_color_tau_max", "ddvr_tf_prior", "ddvr_volume_prior", "ddvr_opacity_entropy",
-    "ddvr_adam_step", "ddvr_resample_volume",
+    "ddvr_adam_step", "ddvr_resample_volume", "ddvr_resample_channels",
 ]
 MAX_DIRECTIONS = 4
 
@@ -125,6 +125,7 @@ def lib():
         "ddvr_adam_step": ([P, P, P, P, ctypes.c_int64, I32, F, F, F, F, F, F, P, I32, I32, P],
                            ctypes.c_int),
         "ddvr_resample_volume": ([P, I32, I32, I32, P, I32, I32, I32, P], ctypes.c_int),
+        "ddvr_resample_channels": ([P, I32, I32, I32, I32, P, I32, I32, I32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -419,7 +420,16 @@ def adam_step(param, grad, m, v, t: int, lr: float, beta1: float = 0.9, beta2: f
 
 
 def resample_volume(src, dst, stream=None):
-    """Trilinear resampling of src [sz][sy][sx] onto dst [dz][dy][dx] (float32)."""
+    """Trilinear resampling of src [sz][sy][sx] onto dst [dz][dy][dx] (float32),
+    or of [..][C] grids of C interleaved channels, each on its own."""
+    if src.dim() == 4:
+        if dst.dim() != 4 or dst.shape[3] != src.shape[3]:
+            raise ValueError("src and dst need the same channel count")
+        sz, sy, sx, C = src.shape
+        dz, dy, dx, _ = dst.shape
+        _check(lib().ddvr_resample_channels(_ptr(src), C, sx, sy, sz, _ptr(dst), dx, dy, dz,
+                                            _stream(stream)))
+        return
     sz, sy, sx = src.shape
     dz, dy, dx = dst.shape
     _check(lib().ddvr_resample_volume(_ptr(src), sx, sy, sz, _ptr(dst), dx, dy, dz,

@@ -198,7 +198,9 @@ class ColorPipelineSchedule:
     """The pipeline of Sec. 5.4: a pre-shaded colour volume reconstructed from
     the images, densities estimated from it through the TF, then the density
     optimisation with the TF from that start."""
-    color_steps: int = 200
+    color_start: int = 32      # colour volume: first level's grid edge, doubled per level
+    color_steps_per_level: int = 10
+    color_steps: int = 50      # at the final level
     color_lr: float = 0.05
     dfc_sweeps: int = 10
     dfc_stop: float = 1e-3     # stop once fewer than this fraction of voxels change
@@ -215,7 +217,7 @@ class ColorPipelineResult:
     color: object = None           # [n][n][n][4] float32: the reconstructed colour volume
     density_init: object = None    # [n][n][n] float32: the estimate from the colour volume
     density: object = None         # [n][n][n] float32: after the density optimisation
-    color_losses: object = None    # [color_steps] float64 (device)
+    color_losses: object = None    # [all colour steps] float64 (device)
     density_losses: object = None  # [density_steps] float64 (device): L1 + prior
     sweeps: int = 0
 
@@ -226,8 +228,9 @@ def reconstruct_via_color(targets, cams, tf, n: int, step_world: float,
     grid under the known TF `tf` ([R][4] float32, device); cams: their V
     cameras; n: edge of the grid to reconstruct (float32 throughout).
 
-    Readings (the paper is silent): the colour volume is reconstructed at the
-    final resolution only (the library's resampling is scalar) with the L1
+    Readings (the paper is silent): the colour volume follows the
+    multi-resolution schedule of the density reconstruction (each channel
+    resampled on its own between levels, Adam's moments restarted) with the L1
     loss alone, starting from zero and clamped to [0, inf); the densities are
     clamped to [0, 1], the range the TF covers; the TF stays fixed."""
     import torch
@@ -243,20 +246,32 @@ def reconstruct_via_color(targets, cams, tf, n: int, step_world: float,
         return [d.make_view(0, cams[i], step_world, images[i], transmittance=trans[i],
                             target=targets[i], tf_index=0) for i in range(nview)]
 
-    # 1. the colour volume from the images
-    color = torch.zeros((n, n, n, 4), device=dev)
-    cg, cm, cv = (torch.zeros_like(color) for _ in range(3))
-    res.color_losses = torch.zeros(sched.color_steps, dtype=torch.float64, device=dev)
-    b = d.Batch([color], None, views(), d.COLOR, flags=d.LOSS_L1, d_volumes=[cg], stream=stream)
-    try:
-        for t in range(1, sched.color_steps + 1):
-            b.run(d.PASS_FUSED, scale, res.color_losses[t - 1:t], stream=stream)
-            d.adam_step(color, cg, cm, cv, t, sched.color_lr, lo=0.0, zero_grad=True,
-                        stream=stream)
-    finally:
-        b.close()
+    # 1. the colour volume from the images, coarse to fine
+    levels, m = [], min(sched.color_start, n)
+    while m < n:
+        levels.append(m)
+        m *= 2
+    levels.append(n)
+    total = sched.color_steps_per_level * (len(levels) - 1) + sched.color_steps
+    res.color_losses = torch.zeros(total, dtype=torch.float64, device=dev)
+    color, k = None, 0
+    for m in levels:
+        prev, color = color, torch.zeros((m, m, m, 4), device=dev)
+        if prev is not None:
+            d.resample_volume(prev, color, stream)
+        cg, cm, cv = (torch.zeros_like(color) for _ in range(3))
+        b = d.Batch([color], None, views(), d.COLOR, flags=d.LOSS_L1, d_volumes=[cg],
+                    stream=stream)
+        try:
+            for t in range(1, (sched.color_steps if m == n else sched.color_steps_per_level) + 1):
+                b.run(d.PASS_FUSED, scale, res.color_losses[k:k + 1], stream=stream)
+                d.adam_step(color, cg, cm, cv, t, sched.color_lr, lo=0.0, zero_grad=True,
+                            stream=stream)
+                k += 1
+        finally:
+            b.close()
     res.color = color
-    del cg, cm, cv
+    del cg, cm, cv, prev
 
     # 2. densities from the colour volume (Jacobi sweeps, alpha = 1/max tau)
     a = torch.zeros((n, n, n), device=dev)

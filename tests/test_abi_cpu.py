@@ -323,6 +323,12 @@ def test_training_loop_validation():
     assert R(0x1000, 1, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_SHAPE
     assert R(0x1000, 4, 4, 4, 0x1010, 8, 8, 8, None) == d.ERR_VALUE       # overlap
     assert R(None, 4, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_NULL
+    RC = L.ddvr_resample_channels
+    assert RC(0x1000, 0, 4, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_VALUE
+    assert RC(0x1000, 5, 4, 4, 4, 0x9000000, 8, 8, 8, None) == d.ERR_VALUE
+    assert RC(0x1000, 4, 4, 4, 4, 0x1000 + 4 * 64 * 4 - 4, 8, 8, 8, None) == d.ERR_VALUE  # overlap
+    assert RC(0x1000, 4, 4, 1, 4, 0x9000000, 8, 8, 8, None) == d.ERR_SHAPE
+    assert RC(0x1000, 4, 4, 4, 4, None, 8, 8, 8, None) == d.ERR_NULL
     # the L1 loss bit is a valid flag of the fused pass
     vol, tf, cam = _descs(d)
     B = ctypes.byref

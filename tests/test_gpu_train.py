@@ -141,6 +141,16 @@ def test_resample_matches_reference():
         d.resample_volume(_t(V), out)
         torch.cuda.synchronize()
         assert np.allclose(out.cpu().numpy(), OL.resample(V, dst_shape), rtol=0, atol=1e-6)
+    # interleaved channels (the colour volume): each channel on its own
+    for C in (2, 4):
+        _say(f"resample {C} channels (9, 7, 12) -> (17, 13, 23)")
+        V = rng.uniform(0, 1, (9, 7, 12, C)).astype(np.float32)
+        out = torch.full((17, 13, 23, C), float("nan"), device="cuda")
+        d.resample_volume(_t(V), out)
+        torch.cuda.synchronize()
+        for c in range(C):
+            assert np.allclose(out[..., c].cpu().numpy(), OL.resample(V[..., c], (17, 13, 23)),
+                               rtol=0, atol=1e-6)
 
 
 def _fused_l1(p, offset_seed):
@@ -390,10 +400,10 @@ def test_viewpoint_selection_loop():
 
 def test_color_pipeline_reconstruction():
     """Sec. 5.4's pipeline through the library on a 32^3 grid under a random
-    (non-monotonic) TF, 8 views at 48^2: the colour-volume stage lowers its
-    loss, the densities estimated from the colour volume render closer to the
-    targets than an empty grid does, and the density optimisation from that
-    start lowers the loss further."""
+    (non-monotonic) TF, 8 views at 48^2: the colour-volume stage (8^3 -> 16^3
+    -> 32^3) lowers its loss, the densities estimated from the colour volume
+    render closer to the targets than an empty grid does, and the density
+    optimisation from that start lowers the loss further."""
     import torch
     from paper_2107_12672_amd import ddvr as d, recon
     _say("colour pipeline reconstruction 32^3")
@@ -408,7 +418,8 @@ def test_color_pipeline_reconstruction():
     targets = torch.empty((8, 48, 48, 4), device="cuda")
     for i in range(8):
         d.render_forward(_t(vol), tf, cams[i], step, d.EMISSION_ABSORPTION, targets[i])
-    sched = recon.ColorPipelineSchedule(color_steps=150, density_steps=60, dfc_sweeps=6)
+    sched = recon.ColorPipelineSchedule(color_start=8, color_steps_per_level=30,
+                                        color_steps=100, density_steps=60, dfc_sweeps=6)
     res = recon.reconstruct_via_color(targets, cams, tf, n, step, sched)
     torch.cuda.synchronize()
 
@@ -430,4 +441,5 @@ def test_color_pipeline_reconstruction():
     assert final < init
     assert ld[-5:].mean() < ld[:5].mean()
     assert float(res.density.min()) >= 0.0 and float(res.density.max()) <= 1.0
-    assert float(res.color.min()) >= 0.0
+    assert float(res.color.min()) >= 0.0 and res.color.shape == (n, n, n, 4)
+    assert len(lc) == 160
