@@ -217,8 +217,9 @@ def secondary(args):
       c2  emission-absorption 128^3 f32, R=16, one 256x256 view, fused L2 with
           gradients for density, TF, camera and step;
       c4  uneven batch of 16 grids (edges 64-384, f16/f32, R 8-64, images
-          128-1024 px) in one persistent launch, forward + adjoint for camera
-          and step gradients (seeded upstream gradients);
+          128-1024 px) in one persistent launch, forward, minus the opacity
+          entropy of each image as the loss, adjoint for camera and step
+          gradients;
       c5  emission-absorption 512^3 f16 sparse noise, R=32, 32 views at
           1024x1024, fused L2 with density, TF and step gradients: T-form
           inversion (AUTO) and segment checkpointing (CHECKPOINT);
@@ -566,16 +567,21 @@ def secondary(args):
         ws_ = synth.make_c4()
         vols = [stored(w.volume, w.storage) for w in ws_]
         tfs = [torch.from_numpy(w.tf).to(dev) for w in ws_]
-        rng = synth.rng_for(9, 4)
         imgs, trs, gs, views = [], [], [], []
         dcam = torch.zeros((len(ws_), 12), device=dev)
         dstep = torch.zeros(len(ws_), device=dev)
+        # the loss is minus the opacity entropy of each image; its image
+        # gradients live in one buffer, cleared once per step
+        gbuf = torch.zeros(sum(w.views[0].height * w.views[0].width * 4 for w in ws_), device=dev)
+        work = torch.zeros((len(ws_), 2), dtype=torch.float64, device=dev)
+        oe = torch.zeros(len(ws_), dtype=torch.float64, device=dev)
+        off = 0
         for i, w in enumerate(ws_):
             v = w.views[0]
             imgs.append(torch.empty((v.height, v.width, 4), device=dev))
             trs.append(torch.empty((v.height, v.width), device=dev))
-            gs.append(torch.from_numpy(rng.normal(size=(v.height, v.width, 4)).astype(np.float32)
-                                       / (v.width * v.height)).to(dev))
+            gs.append(gbuf[off:off + v.height * v.width * 4].view(v.height, v.width, 4))
+            off += v.height * v.width * 4
             cam = cams_of([v])[0]
             views.append(d.make_view(i, cam, w.step_world, imgs[i], transmittance=trs[i],
                                      d_image=gs[i], d_camera=dcam[i], d_step=dstep[i:i + 1],
@@ -586,15 +592,20 @@ def secondary(args):
 
         def step():
             b.run(d.PASS_FORWARD, graph=True)
+            gbuf.zero_()
+            for i in range(len(ws_)):
+                d.opacity_entropy(imgs[i], work[i], oe[i:i + 1], gs[i], scale=-1.0)
             b.run(d.PASS_ADJOINT, workspace=ws, graph=True)
 
         ms = _timed(step, args.steps, args.warmup, stream, torch)
-        log(f"c4: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s, {S} samples")
-        out.update({"metric": "fwd+adjoint ray-samples/s (forward, then adjoint)",
+        log(f"c4: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s, {S} samples; "
+            f"mean OE {float(oe.mean()):.4f}")
+        out.update({"metric": "fwd+adjoint ray-samples/s (forward, -OE loss, adjoint)",
                     "value": S / (ms * 1e-3), "ms_per_step": ms,
                     "config": {"workload": "uneven batch: 16 grids (edges 64-384, f16/f32, "
                                            "EA, R 8-64), one view each at 128-1024 px, "
-                                           "camera + step gradients, persistent launch",
+                                           "loss -OE per image, camera + step gradients, "
+                                           "persistent launch",
                                "samples_per_step": S, "tuning": d.get_tuning()}})
     print(json.dumps(out), flush=True)
 
