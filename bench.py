@@ -658,7 +658,16 @@ def main():
         for _ in range(3):
             d.cast_volume(src, dst)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        # achievable HBM bandwidth: the same copy timed with events (read + write)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            d.cast_volume(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 13,
+                          "copy_ms": ms, "copy_gbs": 8 * n / (ms * 1e-3) / 1e9}))
         return
     work = synth.make_c3(args.n, args.views, args.image, args.step_vox)
     W = H = args.image
