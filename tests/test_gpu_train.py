@@ -402,8 +402,10 @@ def test_color_pipeline_reconstruction():
     """Sec. 5.4's pipeline through the library on a 32^3 grid under a random
     (non-monotonic) TF, 8 views at 48^2: the colour-volume stage (8^3 -> 16^3
     -> 32^3) lowers its loss, the densities estimated from the colour volume
-    render closer to the targets than an empty grid does, and the density
-    optimisation from that start lowers the loss further."""
+    render far closer to the targets than an empty grid does, and the density
+    optimisation from that start lowers its objective (L1 + lambda prior; the
+    image L1 alone may rise slightly as the prior smooths the estimate) and
+    keeps the images close."""
     import torch
     from paper_2107_12672_amd import ddvr as d, recon
     _say("colour pipeline reconstruction 32^3")
@@ -437,9 +439,9 @@ def test_color_pipeline_reconstruction():
           f"empty {empty:.4g}, estimate {init:.4g}, optimised {final:.4g}", flush=True)
     assert lc[-5:].mean() < 0.5 * lc[:5].mean(), lc
     assert 1 <= res.sweeps <= 6
-    assert init < empty
-    assert final < init
+    assert init < 0.1 * empty
     assert ld[-5:].mean() < ld[:5].mean()
+    assert final < 0.1 * empty
     assert float(res.density.min()) >= 0.0 and float(res.density.max()) <= 1.0
     assert float(res.color.min()) >= 0.0 and res.color.shape == (n, n, n, 4)
     assert len(lc) == 160
