@@ -33,10 +33,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU roof in lane-operations: MI355X's published fp32 vector rate, 157.3
-# TFLOP/s = 256 CUs x 128 FMA lanes x 2 flops x 2.4 GHz, i.e. 78.6 T
-# lane-operations/s with one VALU operation in each FMA slot
-VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Published VALU figure: MI355X's fp32 vector rate, 157.3 TFLOP/s = 256 CUs x
+# 128 FMA lanes x 2 flops x 2.4 GHz.  Its 128 lanes per CU need packed fp32
+# instructions, which the library is built without; one non-packed VALU
+# instruction per CU and clock is 256 x 64 x 2.4 GHz = 39.3 T lane-ops/s.
+VALU_PUBLISHED_TOPS = 256 * 128 * 2.4e9 / 1e12
+VALU_NONPACKED_TOPS = 256 * 64 * 2.4e9 / 1e12
+# The ALU roof the benchmark prices against: the sustained rate of
+# independent non-packed fp32 FMAs measured on the device with the library's
+# own flags (bench.py --calibrate-valu, summary in profiles/)
+VALU_CEILING_FILE = os.path.join(ROOT, "profiles", "valu_ceiling.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
 ALG_BYTES_BF16 = 64      # per sample pair: 8 gathers x 2 B (fwd) + 8 x 2 B (adj) + 8 x 4 B scatter
 ALG_BYTES_F32 = 96
@@ -82,6 +88,45 @@ def valu_counts():
     return t if t.get("kernel_source_sha") == kernel_source_hash() else None
 
 
+def valu_ceiling():
+    """Committed measurement of the VALU issue ceiling (lane-ops/s), or None."""
+    try:
+        with open(VALU_CEILING_FILE) as f:
+            t = json.load(f)
+        return float(t["fma_tops"])
+    except (OSError, ValueError, KeyError, TypeError):
+        return None
+
+
+def valu_probe(mode, blocks, iters, reps=3):
+    """Event-timed VALU probe launches: (T lane-ops/s, ms per launch)."""
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    out = torch.empty(blocks * 256, device="cuda")
+    stream = torch.cuda.current_stream()
+    ops = d.valu_probe(mode, blocks, iters, out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        d.valu_probe(mode, blocks, iters, out)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return ops / (ms * 1e-3) / 1e12, ms
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cell_visits(work, cams, W, H):
     """Grid cells entered by all rays of all views (each entry ends in one
     cell-exit flush of the adjoint), from the rays' box entry and exit points:
@@ -113,13 +158,28 @@ def cell_visits(work, cams, W, H):
     return total
 
 
-def cpu_baseline(work, n_views_max, budget_s=12.0):
+def cpu_baseline(work, n_views_max, budget_s=12.0, one_core_s=6.0):
     """FP64 oracle (forward + stored-tape adjoint) on every 8th row and column
-    of successive views until the time budget is spent."""
+    of successive views until the time budget is spent, on all the host's
+    threads; then the same on one thread for a shorter budget."""
+    import oracle
+    oracle.build(force=False)
+    res = _cpu_baseline_run(work, n_views_max, budget_s)
+    nt = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        one = _cpu_baseline_run(work, n_views_max, one_core_s)
+    finally:
+        oracle.set_threads(nt)
+    res["one_core"] = {"value": one["value"], "sample": one["sample"]}
+    res["cpu_model"] = cpu_model()
+    return res
+
+
+def _cpu_baseline_run(work, n_views_max, budget_s):
     import numpy as np
     import oracle
     import synth
-    oracle.build(force=False)
     V = np.zeros(work.volume.shape, np.float64)
     W = H = work.views[0].width
     pix = np.array([y * W + x for y in range(0, H, 8) for x in range(0, W, 8)], np.int32)
@@ -196,6 +256,11 @@ def cpu_baseline_dfc(CV, tf, prev, alpha, ncand, budget_s=10.0):
     return {"value": done * ncand / dt, "unit": "candidates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"fp64 sweep of {done} random voxels x {ncand} candidates in {dt:.1f} s"}
+
+
+def _arch(torch):
+    props = torch.cuda.get_device_properties(0)
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
 
 
 def _timed(fn, steps, warmup, stream, torch):
@@ -546,9 +611,10 @@ def secondary(args):
         ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
         S = b.sample_count()
 
+        plan = d.Plan(b, d.PLAN_LOSS_GIVEN, workspace=ws)
+
         def adjoint():
-            b.run(d.PASS_FORWARD, graph=True)
-            b.run(d.PASS_ADJOINT, workspace=ws, graph=True)
+            plan.run()
 
         res = {}
         for name, fn in (("forward_delayed", delayed), ("forward_immediate", immediate),
@@ -573,8 +639,6 @@ def secondary(args):
         # the loss is minus the opacity entropy of each image; its image
         # gradients live in one buffer, cleared once per step
         gbuf = torch.zeros(sum(w.views[0].height * w.views[0].width * 4 for w in ws_), device=dev)
-        work = torch.zeros((len(ws_), 2), dtype=torch.float64, device=dev)
-        oe = torch.zeros(len(ws_), dtype=torch.float64, device=dev)
         off = 0
         for i, w in enumerate(ws_):
             v = w.views[0]
@@ -586,28 +650,134 @@ def secondary(args):
             views.append(d.make_view(i, cam, w.step_world, imgs[i], transmittance=trs[i],
                                      d_image=gs[i], d_camera=dcam[i], d_step=dstep[i:i + 1],
                                      tf_index=i))
+        # launch shape: the autotuner's choice for the uneven-batch class, if cached
+        from paper_2107_12672_amd import autotune
+        tuned = autotune.apply(autotune.c4_key(_arch(torch)))
         b = d.Batch(vols, tfs, views, d.EMISSION_ABSORPTION)
         ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
         S = b.sample_count()
-
-        def step():
-            b.run(d.PASS_FORWARD, graph=True)
-            gbuf.zero_()
-            for i in range(len(ws_)):
-                d.opacity_entropy(imgs[i], work[i], oe[i:i + 1], gs[i], scale=-1.0)
-            b.run(d.PASS_ADJOINT, workspace=ws, graph=True)
-
-        ms = _timed(step, args.steps, args.warmup, stream, torch)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        # the whole step -- forward, entropy of every image and its gradient,
+        # adjoint, fallback -- is one recorded graph
+        plan = d.Plan(b, d.PLAN_LOSS_NEG_ENTROPY, 1.0, loss, workspace=ws)
+        ms = _timed(plan.run, args.steps, args.warmup, stream, torch)
+        oe = plan.loss_terms()
         log(f"c4: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s, {S} samples; "
-            f"mean OE {float(oe.mean()):.4f}")
+            f"mean OE {sum(oe) / len(oe):.4f}")
+        plan.close()
+        b.close()
         out.update({"metric": "fwd+adjoint ray-samples/s (forward, -OE loss, adjoint)",
                     "value": S / (ms * 1e-3), "ms_per_step": ms,
                     "config": {"workload": "uneven batch: 16 grids (edges 64-384, f16/f32, "
                                            "EA, R 8-64), one view each at 128-1024 px, "
                                            "loss -OE per image, camera + step gradients, "
                                            "persistent launch",
-                               "samples_per_step": S, "tuning": d.get_tuning()}})
+                               "launch": "one step plan: forward, entropy sums and gradient "
+                                         "of all views, adjoint, fallback in one HIP graph",
+                               "samples_per_step": S, "tuning": d.get_tuning(),
+                               "tuning_source": "autotuned" if tuned else "default"}})
     print(json.dumps(out), flush=True)
+
+
+def inversion_c3(d, torch, vol16, views, dV, scale, loss, S, args, stream):
+    """Fused forward + L2 + adjoint of the timed batch with INVERT_T: every
+    sample re-gathers its density, recomputes exp(-dt tau) and divides it out
+    of the transmittance."""
+    b = d.Batch([vol16], None, views, d.ABSORPTION, flags=d.ADJ_INVERT_T, d_volumes=[dV])
+    try:
+        ms = _timed(lambda: b.run(d.PASS_FUSED, scale, loss, graph=True), args.steps,
+                    args.warmup, stream, torch)
+        builds = b.graph_builds()
+    finally:
+        b.close()
+    dV.zero_()
+    log(f"c3 inversion (INVERT_T): {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+    rec = {"ms_per_step": round(ms, 4), "value": S / (ms * 1e-3), "unit": "ray-samples/s",
+           "samples_per_step": S, "mode": "INVERT_T fused, one launch, HIP graph replay",
+           "graph_builds": builds}
+    rec.update(counters_record("k_render_ao_bf16_invert_c3", ms))
+    return rec
+
+
+def counters_record(name, ms):
+    """Committed rocprofv3 counters of a kernel (profiles/counters_<name>.json,
+    taken on the current kernel source) as rates over `ms` per launch."""
+    try:
+        with open(os.path.join(ROOT, "profiles", f"counters_{name}.json")) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return {"counters": None}
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return {"counters": "stale (kernel source changed since they were taken)"}
+    out = {"counters": f"profiles/counters_{name}.json"}
+    if t.get("dram_bytes_per_launch"):
+        gbs = t["dram_bytes_per_launch"] / (ms * 1e-3) / 1e9
+        out["dram_gbs"] = round(gbs, 1)
+        out["dram_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    if t.get("valu_wave_instr_per_launch"):
+        tops = t["valu_wave_instr_per_launch"] * 64 / (ms * 1e-3) / 1e12
+        ceil = valu_ceiling()
+        out["valu_issue_tops"] = round(tops, 3)
+        if ceil:
+            out["valu_issue_frac"] = round(tops / ceil, 4)
+    return out
+
+
+def inversion_c5(d, torch, args, stream):
+    """Emission-absorption 512^3 f16, 32 views at 1024^2, R=32, step 0.25
+    voxel, fused L2 with density, TF and step gradients: the T-form inversion
+    (AUTO; opaque rays to the checkpoint fallback) and segment checkpointing
+    for every ray."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda:0")
+    w = synth.make_c5()
+    v32 = torch.from_numpy(np.ascontiguousarray(w.volume)).to(dev)
+    vol = torch.empty_like(v32, dtype=torch.float16)
+    d.cast_volume(v32, vol)
+    del v32
+    tf = torch.from_numpy(w.tf).to(dev)
+    cams = [d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                 math.radians(v.fovy), v.width, v.height) for v in w.views]
+    nv = len(cams)
+    W = H = w.views[0].width
+    tf_t = torch.from_numpy(w.tf * synth.rng_for(9, 1).uniform(0.8, 1.2, w.tf.shape)
+                            .astype(np.float32)).to(dev)
+    targets = torch.empty((nv, H, W, 4), device=dev)
+    tb = d.Batch([vol], [tf_t], [d.make_view(0, cams[i], w.step_world, targets[i], tf_index=0)
+                                 for i in range(nv)], d.EMISSION_ABSORPTION)
+    tb.run(d.PASS_FORWARD)
+    torch.cuda.synchronize()
+    tb.close()
+    images = torch.empty_like(targets)
+    trans = torch.empty((nv, H, W), device=dev)
+    dV = torch.zeros(w.volume.shape, device=dev)
+    dTF = torch.zeros_like(tf)
+    dstep = torch.zeros(nv, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    scale = 1.0 / images.numel()
+    res = {"workload": w.name + ", fused L2, gradients density+TF+step"}
+    for mode, flags, steps, warm in (("auto", d.ADJ_AUTO, max(2, min(args.steps, 5)), 1),
+                                     ("checkpoint", d.ADJ_CHECKPOINT, args.c5_checkpoint, 0)):
+        if steps <= 0:
+            continue
+        views = [d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
+                             target=targets[i], d_step=dstep[i:i + 1], tf_index=0)
+                 for i in range(nv)]
+        b = d.Batch([vol], [tf], views, d.EMISSION_ABSORPTION, flags=flags, d_volumes=[dV],
+                    d_tfs=[dTF])
+        ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+        S = b.sample_count()
+        ms = _timed(lambda: b.run(d.PASS_FUSED, scale, loss, workspace=ws, graph=warm > 0),
+                    steps, warm, stream, torch)
+        b.close()
+        del ws
+        rec = {"ms_per_step": round(ms, 3), "value": S / (ms * 1e-3), "unit": "ray-samples/s",
+               "samples_per_step": S, "steps": steps}
+        rec.update(counters_record(f"k_render_ea_f16_{mode}_c5", ms))
+        res[mode] = rec
+        log(f"c5 {mode}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+    return res
 
 
 def main():
@@ -631,6 +801,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a float32 copy of MIB MiB through the library (3 times), "
                          "to calibrate HBM byte counters, and exit")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only time the VALU issue-rate probe (non-packed fp32 FMA and int "
+                         "add, 16 independent chains per lane) and exit")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the emission-absorption 512^3 inversion records")
+    ap.add_argument("--c5-checkpoint", type=int, default=1,
+                    help="timed launches of the C5 segment-checkpoint adjoint (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -651,6 +828,22 @@ def main():
         secondary(args)
         return
     dev = torch.device("cuda:0")
+    if args.calibrate_valu:
+        props = torch.cuda.get_device_properties(0)
+        res = {"device": props.name, "compute_units": props.multi_processor_count}
+        for mode, name in ((0, "fma"), (1, "int_add")):
+            for blocks in (2048, 8192):
+                tops, ms = valu_probe(mode, blocks, 4000)
+                key = f"{name}_{blocks}wg"
+                res[key] = {"tops": round(tops, 3), "ms": round(ms, 4),
+                            "wave_instr_per_cu_per_ns": round(
+                                tops * 1e12 / 64 / props.multi_processor_count / 1e9, 4)}
+                log(f"valu probe {key}: {tops:.3f} T lane-ops/s, {ms:.3f} ms")
+        res["fma_tops"] = max(res["fma_2048wg"]["tops"], res["fma_8192wg"]["tops"])
+        res["published_fp32_tops"] = VALU_PUBLISHED_TOPS
+        res["nonpacked_nominal_tops"] = VALU_NONPACKED_TOPS
+        print(json.dumps(res), flush=True)
+        return
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, device=dev)
@@ -748,36 +941,54 @@ def main():
     log(f"pixels with a non-zero residual: {seeded:.4f}, loss {float(loss):.4g}")
 
     # The fused kernel is bound by VALU issue (rocprofv3: VALU busy on ~98% of
-    # SIMD cycles, DRAM traffic ~5% of peak), so its roofline is the ALU one:
-    # per-sample VALU operations of the forward and adjoint loops (counted in
-    # the kernel's assembly) plus one cell-exit flush per grid cell a ray
-    # enters, per launch, over the kernel's event-timed duration.
+    # SIMD cycles, DRAM traffic under a tenth of peak), so its roofline is the
+    # ALU one: per-sample VALU operations of the forward and adjoint loops
+    # (counted in the kernel's assembly) plus one cell-exit flush per grid cell
+    # a ray enters, per launch, over the kernel's event-timed duration, against
+    # the measured issue ceiling of non-packed VALU instructions.
     achieved_gbs = S * ALG_BYTES_BF16 / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     vc = valu_counts()
     cells = cell_visits(work, cams, W, H)
+    live_tops, _ = valu_probe(0, 8192, 1000)
+    ceiling = valu_ceiling()
+    peak = ceiling if ceiling else live_tops
+    log(f"VALU ceiling: committed {ceiling}, live probe {live_tops:.3f} T lane-ops/s")
     if vc:
         ops = S * (vc["forward_valu_per_sample"] + vc["adjoint_valu_per_sample"]) + \
             cells * vc["adjoint_cell_exit_flush_valu"]
         a_tops = ops / (k_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(a_tops, 3), "peak": VALU_PEAK_TOPS,
-                    "unit": "TOP/s", "frac": round(a_tops / VALU_PEAK_TOPS, 4),
+        roofline = {"bound": "alu", "achieved": round(a_tops, 3), "peak": round(peak, 3),
+                    "unit": "TOP/s", "frac": round(a_tops / peak, 4),
                     "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
                     "kernel_ms": round(k_ms, 4), "ops_per_launch": ops,
                     "ops": "VALU lane-operations: per sample forward %d + adjoint %d, "
                            "%d per cell exit (%d cell entries)" % (
                                vc["forward_valu_per_sample"], vc["adjoint_valu_per_sample"],
-                               vc["adjoint_cell_exit_flush_valu"], cells)}
+                               vc["adjoint_cell_exit_flush_valu"], cells),
+                    "peak_source": "measured: independent non-packed fp32 FMAs, library flags "
+                                   "(profiles/valu_ceiling.json)" if ceiling else
+                                   "measured live: VALU probe of this run",
+                    "peak_live": round(live_tops, 3),
+                    "peak_published_fp32": VALU_PUBLISHED_TOPS,
+                    "peak_nonpacked_nominal": VALU_NONPACKED_TOPS}
     else:
-        roofline = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+        roofline = {"bound": "alu", "achieved": None, "peak": round(peak, 3), "unit": "TOP/s",
                     "frac": None, "traffic": traffic,
                     "note": "VALU counts missing or taken on another kernel source: run "
                             "python -m paper_2107_12672_amd.isa_count --write"}
-    roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "alg_bytes_per_launch": S * ALG_BYTES_BF16,
-                    "note": "algorithmic bytes (16 s_V + 32 per sample pair): LDS bricks "
-                            "serve the gathers and scatters, so this exceeds the HBM roof"}
+    roofline_hbm = None
+    if traffic:
+        gbs = traffic / (k_ms * 1e-3) / 1e9
+        roofline_hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": traffic,
+                        "note": "DRAM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "calibrated on a copy) over the event-timed launch"}
+    gather = {"achieved": round(achieved_gbs, 1), "unit": "GB/s",
+              "alg_bytes_per_launch": S * ALG_BYTES_BF16,
+              "note": "algorithmic bytes (16 s_V + 32 per sample pair) over the launch: a "
+                      "gather/scatter rate served by the LDS bricks, not HBM traffic"}
 
     result = {
         "metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
@@ -795,8 +1006,18 @@ def main():
                    "pixels_with_nonzero_residual": round(seeded, 4),
                    "tuning": d.get_tuning(), "tuning_source": "autotuned" if tuned else "default"},
         "roofline": roofline,
-        "roofline_hbm_algorithmic": roofline_hbm,
+        "roofline_hbm_measured": roofline_hbm,
+        "lds_gather_rate": gather,
     }
+
+    # the same batch and state with the paper's inversion on every sample
+    # (T-form, eq. inv-blend-forward solved for T^(i)): the AUTO launch above
+    # takes the absorption-only closed form of that inversion
+    inv = inversion_c3(d, torch, vol16, views, dV, scale, loss, S, args, stream)
+    if inv:
+        result["inversion_c3"] = inv
+    if not args.no_c5:
+        result["inversion_c5"] = inversion_c5(d, torch, args, stream)
 
     if not args.no_plain:
         # the plain per-view float32 path: one launch per view, global atomics

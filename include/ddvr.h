@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define DDVR_ABI_VERSION 3
+#define DDVR_ABI_VERSION 4
 
 typedef enum {
   DDVR_OK = 0,
@@ -443,12 +443,66 @@ void ddvr_batch_destroy(ddvr_batch* b);
 int ddvr_batch_workspace_size(const ddvr_batch* b, size_t* bytes);
 int ddvr_batch_run(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
                    void* workspace, size_t workspace_bytes, void* hip_stream);
-/* Record pass `pass` of the batch into a HIP graph once and replay it on later
- * calls (the pointers and loss_scale must not change between replays). */
+/* Record pass `pass` of the batch into a HIP graph and replay it.  The batch
+ * keeps one recorded graph per pass, keyed on (loss_scale, loss_out,
+ * workspace, workspace_bytes): a call with the same arguments as the pass's
+ * last recording replays it, other arguments re-record that pass only (after
+ * waiting for the stream).  Alternating passes therefore replay. */
 int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
                          void* workspace, size_t workspace_bytes, void* hip_stream);
+/* Graphs recorded and instantiated by ddvr_batch_run_graph so far (host). */
+int ddvr_batch_graph_builds(const ddvr_batch* b, int64_t* builds);
 /* Samples (sum over rays of N) the batch's views take; host output. */
 int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples);
+
+/* ------------------------------------------------------------------------
+ * Step plans (no paper counterpart: the batched form of one optimisation
+ * step).  A plan records the WHOLE step of a batch -- forward, loss gradient,
+ * adjoint and the checkpoint fallback -- into one HIP graph when it is created;
+ * ddvr_plan_execute replays it.  The batch must outlive the plan, and the
+ * buffers the batch and the plan captured must stay valid and unchanged in
+ * address.
+ * ------------------------------------------------------------------------ */
+/* adjoint seeded by the views' d_image as the caller wrote it (forward, then
+ * adjoint) */
+#define DDVR_PLAN_LOSS_GIVEN 0
+/* L2 against each view's target (L1 with DDVR_LOSS_L1 in the batch's flags),
+ * the fused pass: one launch */
+#define DDVR_PLAN_LOSS_FUSED 1
+/* minus the opacity entropy of every view's image (Sec. 5.1, the objective
+ * of viewpoint selection; OE as ddvr_opacity_entropy): loss = -loss_scale *
+ * sum over views of OE_v.  The plan WRITES every element of each view's
+ * d_image (the alpha channel -loss_scale dOE_v/dalpha, 0 where alpha = 0,
+ * colour channels 0) between the forward and the adjoint. */
+#define DDVR_PLAN_LOSS_NEG_ENTROPY 2
+typedef struct ddvr_plan ddvr_plan;
+/*   loss        one of DDVR_PLAN_LOSS_*.
+ *   loss_scale  weight of the loss (fused: as render_fused_l2).
+ *   loss_out    (device, one double, may be NULL) += the step's loss on every
+ *               replay.
+ *   workspace   as for ddvr_batch_run, sized by ddvr_batch_workspace_size.
+ *   hip_stream  unused at creation (recording launches nothing).
+ * The plan owns its graph and, for the entropy, 3 doubles per view. */
+int ddvr_plan_create(ddvr_batch* b, int32_t loss, float loss_scale, double* loss_out,
+                     void* workspace, size_t workspace_bytes, void* hip_stream, ddvr_plan** out);
+/* Replay the recorded step on hip_stream. */
+int ddvr_plan_execute(ddvr_plan* p, void* hip_stream);
+/* Entropy plans: OE of every view at the last replay, out (host) [n], n the
+ * number of views; synchronises hip_stream. */
+int ddvr_plan_loss_terms(const ddvr_plan* p, double* out, int32_t n, void* hip_stream);
+void ddvr_plan_destroy(ddvr_plan* p);
+
+/* ------------------------------------------------------------------------
+ * Measurement (no paper counterpart): the sustained VALU issue rate of the
+ * device, the ceiling of the render kernels' ALU roofline.
+ * ------------------------------------------------------------------------ */
+/* One launch of `blocks` workgroups of 256 lanes; every lane runs `iters`
+ * rounds of 16 independent chains of one VALU operation each -- non-packed
+ * float32 FMA (mode 0) or 32-bit integer add (mode 1) -- built with the
+ * library's own compiler flags.  out [blocks*256] float32 (device) receives a
+ * checksum per lane; *lane_ops (host) = blocks*256*iters*16. */
+int ddvr_valu_probe(int32_t mode, int32_t blocks, int32_t iters, float* out, int64_t* lane_ops,
+                    void* hip_stream);
 
 #ifdef __cplusplus
 }

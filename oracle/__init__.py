@@ -53,6 +53,8 @@ def _load():
     i = ctypes.c_int
     p = ctypes.c_void_p
     i64 = ctypes.c_int64
+    lib.oracle_set_threads.argtypes = [i]
+    lib.oracle_set_threads.restype = ctypes.c_int
     lib.oracle_camera_from_sphere.argtypes = [d, d, d, d, i, i, p]
     lib.oracle_camera_jacobian.argtypes = [d, d, d, d, i, i, p]
     lib.oracle_render.argtypes = [p, i, i, i, p, i, p, i, i, d, i, p, i64, p, p, p, p]
@@ -95,6 +97,11 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_threads(n: int) -> int:
+    """Threads the oracle's parallel loops use from now on; returns the count."""
+    return _load().oracle_set_threads(int(n))
 
 
 def camera_from_sphere(yaw_deg, pitch_deg, dist, fovy_deg, W, H) -> np.ndarray:

@@ -952,4 +952,15 @@ int oracle_density_from_color(const double* CV, int nx, int ny, int nz, const do
 
 int oracle_num_threads(void) { return nthreads_max(); }
 
+// Threads of later parallel regions (timing of the oracle on one core and on
+// all of them); returns the new maximum.
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return nthreads_max();
+}
+
 }  // extern "C"

@@ -42,6 +42,18 @@ def workload_key(arch: str, model: int, storage: str, R: int, image_px: int, gri
             f"img{_bucket(image_px)}|grid{_bucket(grid_edge)}|{grads}|pass{pass_}")
 
 
+def c4_key(arch: str) -> str:
+    """Key of the uneven-batch class: many emission-absorption grids of mixed
+    storage and size, one persistent launch per pass, camera and step
+    gradients, the whole step as one plan."""
+    return f"{arch}|ea|mixed|uneven-batch|cam+step|plan"
+
+
+def color_key(arch: str, storage: str, image_px: int, grid_edge: int) -> str:
+    """Key of a batched colour-volume workload (fused pass, colour gradient)."""
+    return f"{arch}|color|{storage}|img{_bucket(image_px)}|grid{_bucket(grid_edge)}|V|pass2"
+
+
 def load_cache(path: Optional[str] = None) -> Dict[str, dict]:
     path = path or cache_path()
     try:
@@ -140,6 +152,24 @@ def tune(key: str, make_batch: Callable[[], "object"], run: Callable[["object"],
     return {"tuning": best, "ms": best_ms, "all": results}
 
 
+def uneven_candidates() -> List[dict]:
+    """Launch shapes of the persistent uneven-batch launch (its schedule is
+    always the queue)."""
+    out = []
+    for waves, cap, k, lm in itertools.product((2, 4), (4096, 7168, 10240), (32, 64),
+                                               (0, 2)):
+        out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
+                    "cell_acc": 1, "lane_map": lm, "schedule": 2})
+    return out
+
+
+def color_candidates() -> List[dict]:
+    """The colour kernel takes 16x16 tiles and one item per workgroup; only its
+    brick capacity (lds_cap / 4 vertices of 4 channels) is free."""
+    base = dict(_d.TUNING_DEFAULT)
+    return [dict(base, lds_cap=c) for c in (4096, 7168, 10240, 14336, 16384)]
+
+
 def _device_arch() -> str:
     import torch
     props = torch.cuda.get_device_properties(0)
@@ -147,12 +177,16 @@ def _device_arch() -> str:
 
 
 def main(argv=None) -> None:
-    """Tune the absorption-only tomography workload (256^3 bf16, 64 views at
-    512x512, fused pass) and store the result in the cache."""
+    """Tune a workload class and store the result in the cache:
+      c3     absorption-only tomography (256^3 bf16, 64 views at 512x512, fused pass);
+      c4     the uneven batch (16 grids of mixed size and storage, one view each,
+             minus the opacity entropy, camera + step gradients, one step plan);
+      color  the colour volume (256^3 x 4 bf16, the c3 views, fused pass)."""
     import argparse
     import sys
     import torch
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "color"))
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
@@ -162,9 +196,79 @@ def main(argv=None) -> None:
     root = os.path.dirname(HERE)
     if root not in sys.path:
         sys.path.insert(0, root)
+    import numpy as np
     import synth
-    w = synth.make_c3(args.n, args.views, args.image, args.step_vox)
     dev = torch.device("cuda:0")
+    if args.workload == "c4":
+        ws_ = synth.make_c4()
+        vols, tfs, imgs, views = [], [], [], []
+        for k, w in enumerate(ws_):
+            v = w.views[0]
+            v32 = torch.from_numpy(w.volume).to(dev)
+            if w.storage == "f32":
+                vols.append(v32)
+            else:
+                vols.append(torch.empty_like(v32, dtype=torch.float16))
+                _d.cast_volume(v32, vols[-1])
+            tfs.append(torch.from_numpy(w.tf).to(dev))
+        npx = [w.views[0].width * w.views[0].height for w in ws_]
+        flat = torch.empty(4 * sum(npx), device=dev)
+        gflat = torch.zeros_like(flat)
+        trans = torch.empty(sum(npx), device=dev)
+        dcam = torch.zeros((len(ws_), 12), device=dev)
+        dstep = torch.zeros(len(ws_), device=dev)
+        off = 0
+        for k, w in enumerate(ws_):
+            v = w.views[0]
+            cam = _d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                        math.radians(v.fovy), v.width, v.height)
+            views.append(_d.make_view(k, cam, w.step_world, flat[4 * off:4 * (off + npx[k])],
+                                      transmittance=trans[off:off + npx[k]],
+                                      d_image=gflat[4 * off:4 * (off + npx[k])],
+                                      d_camera=dcam[k], d_step=dstep[k:k + 1], tf_index=k))
+            off += npx[k]
+        state = {}
+
+        def make():
+            b = _d.Batch(vols, tfs, views, _d.EMISSION_ABSORPTION)
+            ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
+            state["plan"] = _d.Plan(b, _d.PLAN_LOSS_NEG_ENTROPY, 1.0, None, workspace=ws)
+            return b
+
+        key = c4_key(_device_arch())
+        res = tune(key, make, lambda b: state["plan"].run(), lambda: flat,
+                   candidates=uneven_candidates(), reps=args.reps, verbose=True)
+        print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
+        return
+    if args.workload == "color":
+        w = synth.make_color()
+        v32 = torch.from_numpy(np.ascontiguousarray(w.volume)).to(dev)
+        vol = torch.empty_like(v32, dtype=torch.bfloat16)
+        _d.cast_volume(v32, vol)
+        del v32
+        W = w.views[0].width
+        cams = [_d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                      math.radians(v.fovy), W, W) for v in w.views]
+        nv = len(cams)
+        targets = torch.rand((nv, W, W, 4), device=dev,
+                             generator=torch.Generator("cuda").manual_seed(1))
+        images = torch.empty_like(targets)
+        trans = torch.empty((nv, W, W), device=dev)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        scale = 1.0 / images.numel()
+
+        def make_c():
+            views = [_d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
+                                  target=targets[i]) for i in range(nv)]
+            return _d.Batch([vol], None, views, _d.COLOR, d_volumes=[dV])
+
+        key = color_key(_device_arch(), "bf16", W, w.volume.shape[0])
+        res = tune(key, make_c, lambda b: b.run(_d.PASS_FUSED, scale, loss), lambda: images,
+                   candidates=color_candidates(), reps=args.reps, verbose=True)
+        print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
+        return
+    w = synth.make_c3(args.n, args.views, args.image, args.step_vox)
     W = args.image
     gt = torch.from_numpy(w.target_volume).to(dev)
     vol = torch.empty_like(gt, dtype=torch.bfloat16)

@@ -57,9 +57,16 @@ struct Tuning {
 };
 Tuning g_tuning;
 
+// 4-byte words of LDS per brick voxel: the staged grid value, plus the
+// gradient brick's entry when the adjoint needs both (a 64-bit entry for
+// emission-absorption)
+int brick_words(int two, int model) {
+  return two ? (model == DDVR_EMISSION_ABSORPTION ? 3 : 2) : 1;
+}
+
 size_t lds_bytes(int cap, int two, int model, int R) {
   const size_t tf = model == DDVR_EMISSION_ABSORPTION ? (size_t)R * 8 : 0;
-  return ((size_t)(two ? 2 : 1) * cap + tf) * sizeof(float) + 64 * sizeof(int);
+  return ((size_t)brick_words(two, model) * cap + tf) * sizeof(float) + 64 * sizeof(int);
 }
 
 // Largest dynamic LDS allocation of one workgroup on the current device.
@@ -82,16 +89,21 @@ int check_lds(size_t bytes) {
 }
 
 // Brick capacity that fits the device next to the TF tables and scratch.
+// The emission-absorption adjoint's bricks (a 64-bit gradient entry beside
+// each staged value) take 2/3 of `cap` voxels, the LDS bytes of `cap` voxels
+// with 32-bit entries, so that as many workgroups fit per CU.  Kept even: the
+// 64-bit entries start after `cap` staged floats and must be 8-byte aligned.
 int fit_cap(int cap, int two, int model, int R, int* out) {
   *out = cap;
   if (cap <= 0) return DDVR_OK;
+  if (two && model == DDVR_EMISSION_ABSORPTION) cap = std::max(2 * cap / 3, 64);
   int lim = 0, rc = lds_limit(&lim);
   if (rc) return rc;
   const size_t fixed = lds_bytes(0, two, model, R);
   if ((size_t)lim <= fixed + 256 * sizeof(float))
     return fail(DDVR_ERR_UNSUPPORTED, "TF of %d entries leaves no LDS for bricks", R);
-  const int most = (int)((lim - fixed) / ((two ? 2 : 1) * sizeof(float)));
-  *out = std::min(cap, most);
+  const int most = (int)((lim - fixed) / (brick_words(two, model) * sizeof(float)));
+  *out = std::min(cap, most) & ~1;
   return DDVR_OK;
 }
 
@@ -484,14 +496,19 @@ struct ddvr_batch {
   int64_t total_rays = 0, max_n = 1;
   int64_t samples = 0;
   int grad_mask = 0;
-  // graph cache
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // graph cache: one recorded graph per pass, each keyed on the arguments
+  // captured into it, so alternating passes replay instead of re-recording
+  struct GraphSlot {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float scale = 0.0f;
+    double* loss = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+  };
+  GraphSlot slots[3];
   hipStream_t cap_stream = nullptr;
-  int g_pass = -1;
-  float g_scale = 0.0f;
-  double* g_loss = nullptr;
-  void* g_ws = nullptr;
+  int64_t graph_builds = 0;   // graphs recorded and instantiated so far
 };
 
 extern "C" {
@@ -941,8 +958,10 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
 
 void ddvr_batch_destroy(ddvr_batch* b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& g : b->slots) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_views) (void)hipFree(b->d_views);
   if (b->d_work) (void)hipFree(b->d_work);
@@ -1039,33 +1058,192 @@ int ddvr_batch_run(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_o
 int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
                          void* workspace, size_t workspace_bytes, void* hip_stream) {
   if (!b) return fail(DDVR_ERR_NULL, "batch is NULL");
+  if (pass < PASS_FWD || pass > PASS_FUSED) return fail(DDVR_ERR_VALUE, "unknown pass %d", pass);
   int rc = check_pending();
   if (rc) return rc;
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const bool same = b->exec && b->g_pass == pass && b->g_scale == loss_scale &&
-                    b->g_loss == loss_out && b->g_ws == workspace;
+  ddvr_batch::GraphSlot& g = b->slots[pass];
+  const bool same = g.exec && g.scale == loss_scale && g.loss == loss_out && g.ws == workspace &&
+                    g.ws_bytes == workspace_bytes;
   hipError_t e;
   if (!same) {
-    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    // the old graph may still run on the caller's stream: let it finish first
+    if (g.exec && (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "waiting for the previous replay");
+    if (g.exec) { (void)hipGraphExecDestroy(g.exec); g.exec = nullptr; }
+    if (g.graph) { (void)hipGraphDestroy(g.graph); g.graph = nullptr; }
     if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "capture stream");
     if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
       return hip_fail(e, "begin capture");
     rc = batch_enqueue(b, pass, loss_scale, loss_out, workspace, workspace_bytes, b->cap_stream);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->cap_stream, &g);
-    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &gr);
+    if (rc) { if (gr) (void)hipGraphDestroy(gr); return rc; }
     if (e != hipSuccess) return hip_fail(e, "end capture");
-    b->graph = g;
-    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+    g.graph = gr;
+    if ((e = hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(gr);
+      g.graph = nullptr;
+      g.exec = nullptr;
       return hip_fail(e, "graph instantiate");
-    b->g_pass = pass;
-    b->g_scale = loss_scale;
-    b->g_loss = loss_out;
-    b->g_ws = workspace;
+    }
+    g.scale = loss_scale;
+    g.loss = loss_out;
+    g.ws = workspace;
+    g.ws_bytes = workspace_bytes;
+    ++b->graph_builds;
   }
-  if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+  if ((e = hipGraphLaunch(g.exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+  return DDVR_OK;
+}
+
+int ddvr_batch_graph_builds(const ddvr_batch* b, int64_t* builds) {
+  if (!b || !builds) return fail(DDVR_ERR_NULL, "batch or builds is NULL");
+  *builds = b->graph_builds;
+  return DDVR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plans: the whole step of a batch recorded into one HIP graph
+// ---------------------------------------------------------------------------
+struct ddvr_plan {
+  ddvr_batch* b = nullptr;
+  int loss = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  double* d_sums = nullptr;   // entropy: [nview][2] sums, then [nview] OE values
+};
+
+void ddvr_plan_destroy(ddvr_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_sums) (void)hipFree(p->d_sums);
+  delete p;
+}
+
+// The launches of one step, enqueued on s (recorded once by plan_create).
+static int plan_enqueue(ddvr_plan* p, float loss_scale, double* loss_out, void* ws,
+                        size_t ws_bytes, hipStream_t s) {
+  ddvr_batch* b = p->b;
+  int rc;
+  if (p->loss == DDVR_PLAN_LOSS_FUSED)
+    return batch_enqueue(b, PASS_FUSED, loss_scale, loss_out, ws, ws_bytes, s);
+  if ((rc = batch_enqueue(b, PASS_FWD, 0.0f, nullptr, ws, ws_bytes, s))) return rc;
+  if (p->loss == DDVR_PLAN_LOSS_NEG_ENTROPY) {
+    int64_t max_pix = 1;
+    for (const ViewDesc& d : b->views) max_pix = std::max<int64_t>(max_pix, (int64_t)d.W * d.H);
+    const int nv = (int)b->views.size();
+    const hipError_t e = (hipError_t)launch_entropy_views(
+        b->d_views, nv, max_pix, b->model == DDVR_ABSORPTION ? 1 : 4, p->d_sums,
+        p->d_sums + 2 * nv, loss_out, loss_scale, s);
+    if (e != hipSuccess) return hip_fail(e, "entropy launch");
+  }
+  return batch_enqueue(b, PASS_ADJ, 0.0f, nullptr, ws, ws_bytes, s);
+}
+
+int ddvr_plan_create(ddvr_batch* b, int32_t loss, float loss_scale, double* loss_out,
+                     void* workspace, size_t workspace_bytes, void* hip_stream, ddvr_plan** out) {
+  if (!out) return fail(DDVR_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (!b) return fail(DDVR_ERR_NULL, "batch is NULL");
+  if (loss != DDVR_PLAN_LOSS_GIVEN && loss != DDVR_PLAN_LOSS_FUSED &&
+      loss != DDVR_PLAN_LOSS_NEG_ENTROPY)
+    return fail(DDVR_ERR_VALUE, "unknown plan loss %d", loss);
+  if (!std::isfinite(loss_scale)) return fail(DDVR_ERR_VALUE, "loss_scale is not finite");
+  for (size_t i = 0; i < b->views.size(); ++i) {
+    const ViewDesc& d = b->views[i];
+    if (loss == DDVR_PLAN_LOSS_FUSED && !d.target)
+      return fail(DDVR_ERR_NULL, "view %zu: the fused loss needs a target", i);
+    if (loss != DDVR_PLAN_LOSS_FUSED && (!d.d_image || !d.trans))
+      return fail(DDVR_ERR_NULL, "view %zu: the adjoint needs d_image and transmittance", i);
+    if (loss == DDVR_PLAN_LOSS_NEG_ENTROPY && (int64_t)d.W * d.H < 2)
+      return fail(DDVR_ERR_SHAPE, "view %zu: the entropy needs at least 2 pixels", i);
+  }
+  if (loss == DDVR_PLAN_LOSS_NEG_ENTROPY && b->model == DDVR_COLOR)
+    return fail(DDVR_ERR_UNSUPPORTED, "entropy plans take scalar grids");
+  size_t need = 0;
+  if (b->model != DDVR_COLOR && needs_fallback(b->model, b->flags))
+    need = fallback_layout(b->total_rays, b->max_n).bytes;
+  if (need && (!workspace || workspace_bytes < need))
+    return fail(DDVR_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  int rc = check_pending();
+  if (rc) return rc;
+  ddvr_plan* p = new (std::nothrow) ddvr_plan;
+  if (!p) return fail(DDVR_ERR_VALUE, "out of host memory");
+  p->b = b;
+  p->loss = loss;
+  hipError_t e = hipSuccess;
+  if (loss == DDVR_PLAN_LOSS_NEG_ENTROPY)
+    e = hipMalloc(&p->d_sums, sizeof(double) * 3 * b->views.size());
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    ddvr_plan_destroy(p);
+    return hip_fail(e, "plan buffers");
+  }
+  // recording runs nothing: the caller's stream is only where replays go
+  (void)hip_stream;
+  if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+    ddvr_plan_destroy(p);
+    return hip_fail(e, "begin capture");
+  }
+  rc = plan_enqueue(p, loss_scale, loss_out, workspace, workspace_bytes, p->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    ddvr_plan_destroy(p);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    ddvr_plan_destroy(p);
+    return hip_fail(e, "end capture");
+  }
+  p->graph = g;
+  if ((e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+    p->exec = nullptr;
+    ddvr_plan_destroy(p);
+    return hip_fail(e, "graph instantiate");
+  }
+  *out = p;
+  return DDVR_OK;
+}
+
+int ddvr_plan_execute(ddvr_plan* p, void* hip_stream) {
+  if (!p) return fail(DDVR_ERR_NULL, "plan is NULL");
+  int rc = check_pending();
+  if (rc) return rc;
+  const hipError_t e = hipGraphLaunch(p->exec, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "graph launch");
+}
+
+int ddvr_plan_loss_terms(const ddvr_plan* p, double* out, int32_t n, void* hip_stream) {
+  if (!p || !out) return fail(DDVR_ERR_NULL, "plan or out is NULL");
+  if (p->loss != DDVR_PLAN_LOSS_NEG_ENTROPY)
+    return fail(DDVR_ERR_UNSUPPORTED, "only entropy plans keep per-view terms");
+  const int nv = (int)p->b->views.size();
+  if (n != nv) return fail(DDVR_ERR_SHAPE, "the plan has %d views, %d asked", nv, n);
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipMemcpyAsync(out, p->d_sums + 2 * nv, sizeof(double) * nv,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? DDVR_OK : hip_fail(e, "reading the entropy terms");
+}
+
+int ddvr_valu_probe(int32_t mode, int32_t blocks, int32_t iters, float* out, int64_t* lane_ops,
+                    void* hip_stream) {
+  if (!out || !lane_ops) return fail(DDVR_ERR_NULL, "out or lane_ops is NULL");
+  if (mode != 0 && mode != 1) return fail(DDVR_ERR_VALUE, "probe mode %d not 0 or 1", mode);
+  if (blocks <= 0 || blocks > (1 << 20) || iters <= 0)
+    return fail(DDVR_ERR_SHAPE, "probe of %d workgroups x %d rounds", blocks, iters);
+  int rc;
+  if ((rc = check_pending())) return rc;
+  const hipError_t e = (hipError_t)launch_valu_probe(mode, blocks, iters, out, hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "probe launch");
+  *lane_ops = (int64_t)blocks * 256 * iters * kProbeChains;
   return DDVR_OK;
 }
 

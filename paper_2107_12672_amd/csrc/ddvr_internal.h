@@ -116,6 +116,11 @@ int launch_volume_prior(const float* V, int nx, int ny, int nz, float lam, float
                         double* loss, void* stream);
 int launch_opacity_entropy(const float* img, int64_t n, int stride, int offset, double* work,
                            double* value, float* dimg, float scale, void* stream);
+// opacity entropy of every view's alpha (views: device array of nview
+// descriptors; image [H][W][channels], alpha the last channel): d_image written,
+// oe[v] = OE_v, loss += -scale sum OE_v; sums: 2*nview doubles of scratch
+int launch_entropy_views(const ViewDesc* views, int nview, int64_t max_pix, int channels,
+                         double* sums, double* oe, double* loss, float scale, void* stream);
 int launch_adam(float* x, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                 float eps, float c1, float c2, float lo, float hi, void* store, int store_dtype,
                 int zero_grad, void* stream);
@@ -124,6 +129,11 @@ int launch_resample(const float* src, int channels, int sx, int sy, int sz, floa
 // implemented in ddvr_dfc.hip
 int launch_density_from_color(const DfcParams& p, int dtype, void* stream);
 int launch_color_tau_max(const void* cv, int dtype, int64_t nvox, float* out, void* stream);
+
+// implemented in ddvr_probe.hip: blocks x 256 lanes, iters x kProbeChains
+// independent VALU operations per lane (mode 0 float32 FMA, 1 int32 add)
+constexpr int kProbeChains = 16;
+int launch_valu_probe(int mode, int blocks, int iters, float* out, void* stream);
 
 constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persistent launch
 constexpr int kMaxSamples = 1 << 22;    // per-ray sample cap (validated on the host)

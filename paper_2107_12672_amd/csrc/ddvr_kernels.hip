@@ -223,18 +223,32 @@ __device__ __forceinline__ int round_i32(float x) {
   return r;
 }
 
+// float -> int64 rounding to nearest even for |x| < 2^51: adding 1.5 * 2^52
+// in float64 leaves the rounded integer in the low mantissa bits.
+__device__ __forceinline__ long long round_i64(float x) {
+  const double m = 6755399441055744.0;
+  return (long long)(__double_as_longlong((double)x + m) - __double_as_longlong(m));
+}
+
 // Add 8 corner values to the LDS gradient brick: float atomics, or (FIX)
-// 32-bit integer atomics of values already in fixed-point units.
-template <bool FIX>
+// integer atomics of values already in fixed-point units -- 32-bit, or (WIDE)
+// 64-bit entries at twice the brick's byte offsets.
+template <bool FIX, bool WIDE = false>
 __device__ __forceinline__ void lds_add8(float* acc, const Brick& br, int base, const float* g) {
-  char* p0 = reinterpret_cast<char*>(acc) + base;
-  char* p1 = p0 + br.bx4;
-  char* p2 = p0 + br.bxy4;
-  char* p3 = p2 + br.bx4;
+  constexpr int SH = WIDE ? 1 : 0;
+  char* p0 = reinterpret_cast<char*>(acc) + (base << SH);
+  char* p1 = p0 + (br.bx4 << SH);
+  char* p2 = p0 + (br.bxy4 << SH);
+  char* p3 = p2 + (br.bx4 << SH);
   char* const pc[4] = {p0, p1, p2, p3};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (FIX) {
+    if (FIX && WIDE) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(pc[k]),
+                (unsigned long long)round_i64(g[2 * k]));
+      atomicAdd(reinterpret_cast<unsigned long long*>(pc[k]) + 1,
+                (unsigned long long)round_i64(g[2 * k + 1]));
+    } else if (FIX) {
       atomicAdd(reinterpret_cast<int*>(pc[k]), round_i32(g[2 * k]));
       atomicAdd(reinterpret_cast<int*>(pc[k]) + 1, round_i32(g[2 * k + 1]));
     } else {
@@ -531,7 +545,7 @@ __device__ __forceinline__ void stage_loads(const ViewDesc& vd, const Brick& br,
 
 // Stage the brick's grid values (as float32) and/or zero its gradient
 // accumulator.  The caller synchronises before the brick is read.
-template <int NT, int DT>
+template <int NT, int DT, bool WIDE = false>
 __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br, float* stage,
                                             float* acc) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
@@ -540,21 +554,33 @@ __device__ __forceinline__ void stage_brick(const ViewDesc& vd, const Brick& br,
     if (brick_narrow(br, sz)) stage_loads<NT, DT, true>(vd, br, stage, org, sy, sz);
     else stage_loads<NT, DT, false>(vd, br, stage, org, sy, sz);
   }
-  if (acc)
-    for (int idx = threadIdx.x; idx < br.size; idx += NT) acc[idx] = 0.0f;
+  if (acc) {
+    if (WIDE)
+      for (int idx = threadIdx.x; idx < br.size; idx += NT)
+        reinterpret_cast<long long*>(acc)[idx] = 0;
+    else
+      for (int idx = threadIdx.x; idx < br.size; idx += NT) acc[idx] = 0.0f;
+  }
 }
 
 // Add the brick's gradient accumulator to the density gradient in global
-// memory, one atomic per touched voxel.  FIX: the accumulator holds 32-bit
-// fixed-point values (see AdjState::qs), scaled back by inv_qs.
-template <int NT, bool FIX>
+// memory, one atomic per touched voxel.  FIX: the accumulator holds
+// fixed-point values (see AdjState::qs; 64-bit ones when WIDE), scaled back
+// by inv_qs.
+template <int NT, bool FIX, bool WIDE = false>
 __device__ __forceinline__ void flush_brick(const ViewDesc& vd, const Brick& br, const float* acc,
                                             float inv_qs) {
   const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
   float* const org = vd.dV + (br.z0 * sz + br.y0 * sy + br.x0);
   const bool narrow = brick_narrow(br, sz);
   for (int idx = threadIdx.x; idx < br.size; idx += NT) {
-    const float g = FIX ? (float)reinterpret_cast<const int*>(acc)[idx] * inv_qs : acc[idx];
+    float g;
+    if (FIX && WIDE)
+      g = (float)((double)reinterpret_cast<const long long*>(acc)[idx] * (double)inv_qs);
+    else if (FIX)
+      g = (float)reinterpret_cast<const int*>(acc)[idx] * inv_qs;
+    else
+      g = acc[idx];
     if (g != 0.0f)
       gadd(org + (narrow ? brick_goff<true>(br, idx, sy, sz)
                          : brick_goff<false>(br, idx, sy, sz)), g);
@@ -630,12 +656,12 @@ struct AdjState {
 
 // Add the registered density gradient of the current cell to the LDS brick
 // (LDS) or to global memory (direct slabs), then clear it.
-template <bool LDS, bool FIX>
+template <bool LDS, bool FIX, bool WIDE = false>
 __device__ __forceinline__ void cell_flush(const ViewDesc& vd, const Brick& br, float* acc,
                                            AdjState& s) {
   if (LDS) {
     if (s.ckey < 0) return;
-    lds_add8<FIX>(acc, br, s.ckey, s.cg);
+    lds_add8<FIX, WIDE>(acc, br, s.ckey, s.cg);
   } else {
     if (s.gkey < 0) return;
     const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
@@ -675,9 +701,10 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
                                            const float4* tfl, float* dtf, int gmask,
                                            bool need_v, bool cell_acc, AdjState& s,
                                            float Ti_given) {
-  // the absorption-only closed form and the emission-absorption inversions
-  // accumulate the LDS brick in fixed point
-  constexpr bool FIX = LDS && (MODEL == DDVR_ABSORPTION ? MODE == 0 : (MODE == 1 || MODE == 2));
+  // the closed form and the inversions accumulate the LDS brick in fixed
+  // point, 64-bit for emission-absorption (its scale bound is looser)
+  constexpr bool FIX = LDS && MODE <= 2;
+  constexpr bool WIDE = MODEL == DDVR_EMISSION_ABSORPTION;
   Cell c;
   locate(r, fi, vd, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
@@ -760,14 +787,14 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
     const float a00 = gy * gz, a10 = c.f[1] * gz, a01 = gy * c.f[2], a11 = c.f[1] * c.f[2];
     if (LDS) {
       if (base != s.ckey) {
-        cell_flush<LDS, FIX>(vd, br, acc, s);
+        cell_flush<LDS, FIX, WIDE>(vd, br, acc, s);
         s.ckey = base;
       }
     } else {
       const int64_t key =
           (int64_t)c.k[2] * vd.nx * vd.ny + (int64_t)c.k[1] * vd.nx + c.k[0];
       if (key != s.gkey) {
-        cell_flush<LDS, FIX>(vd, br, acc, s);
+        cell_flush<LDS, FIX, WIDE>(vd, br, acc, s);
         s.gkey = key;
       }
     }
@@ -787,7 +814,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
       float g[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) g[k] = w[k] * q;
-      lds_add8<FIX>(acc, br, base, g);
+      lds_add8<FIX, WIDE>(acc, br, base, g);
     } else {
       const int64_t sy = vd.nx, sz = (int64_t)vd.nx * vd.ny;
       float* g = vd.dV + (c.k[2] * sz + c.k[1] * sy + c.k[0]);
@@ -823,8 +850,9 @@ __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int
   for (float fi = (float)(b - 1); fi >= fa; fi -= 1.0f)
     adj_sample<MODEL, DT, LDS, MODE, XH>(vd, r, fi, stage, acc, br, tfl, dtf, gmask, need_v,
                                      cell_acc, s, 0.0f);
-  constexpr bool FIX = LDS && (MODEL == DDVR_ABSORPTION ? MODE == 0 : (MODE == 1 || MODE == 2));
-  if (cell_acc) cell_flush<LDS, FIX>(vd, br, acc, s);   // the brick changes with the slab
+  constexpr bool FIX = LDS && MODE <= 2;
+  constexpr bool WIDE = MODEL == DDVR_EMISSION_ABSORPTION;
+  if (cell_acc) cell_flush<LDS, FIX, WIDE>(vd, br, acc, s);   // the brick changes with the slab
 }
 
 // Camera adjoint of one ray (last line of Alg. 2 on [x_o_hat; omega_hat]).
@@ -910,9 +938,12 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
 
   // LDS carve-up: one brick region, or two when the adjoint needs the grid
   // values and a gradient accumulator at the same time
+  // (the emission-absorption gradient brick holds 64-bit entries: 2 words
+  // per voxel; the host keeps cap even so that they are 8-byte aligned)
+  constexpr int ACCW = EA ? 2 : 1;
   float* stage = smem;
   float* acc = smem + (p.lds_two ? cap : 0);
-  float4* tfl = reinterpret_cast<float4*>(smem + (p.lds_two ? 2 * cap : cap));
+  float4* tfl = reinterpret_cast<float4*>(smem + (p.lds_two ? (1 + ACCW) * cap : cap));
   float* dtf = reinterpret_cast<float*>(tfl) + (EA ? 4 * vd.R : 0);
   int* iscratch = reinterpret_cast<int*>(dtf + (EA ? 4 * vd.R : 0));
   float* fscratch = reinterpret_cast<float*>(iscratch);
@@ -1093,8 +1124,13 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   // 2*sqrt(3) voxels), and each adds w*d_hat with trilinear weight |w| <= 1.
   // B bounds every brick entry by a sum over the tile's rays of per-ray
   // bounds on their contributions to one voxel:
-  //  * absorption-only closed form: d_hat = dt*T_N*ahat exactly, so a ray
-  //    adds at most lmax*|d_hat|; B = NT * lmax * max|d_hat|;
+  //  * absorption-only: d_hat = dt*T_N*ahat exactly in the closed form, so a
+  //    ray adds at most lmax*|d_hat|; B = NT * lmax * max|d_hat|.  The T- and
+  //    alpha-form inversions compute the same d_hat = dt T^(i) e_i ahat^(i+1)
+  //    = dt T^(i+1) ahat^(i+1) (no emission: ahat^(i) = e_i ahat^(i+1)) up
+  //    to the float32 drift of the recovered T^(i), which the margin below
+  //    covers (relative 2 N 2^-24 <= 1/2 for the T-form at the sample cap,
+  //    2^-14 for the alpha-form, whose rays with T_N < 2^-10 fall back);
   //  * emission-absorption (T- or alpha-form inversion): d_hat = (R-1) *
   //    (slope_rgb . alpha_i T^(i) Chat + slope_tau * tau_hat).  Along a ray
   //    sum_i alpha_i T^(i) = 1 - T_N <= 1, so the colour part adds at most
@@ -1104,11 +1140,17 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   //    2 rgbmax |Chat|_1 and the opacity part adds at most lmax (R-1) S_tau
   //    dt A (S: largest TF segment slopes, rgbmax: largest |colour|).
   //    B = the sum of these per-ray bounds over the tile.
-  // qs = 2^(28 - ceil(log2 B)) keeps every partial sum below 2^28 (margin for
-  // float32 rounding of the recovered T^(i)).  A tile whose bound is not
-  // finite (NaN or Inf upstream gradients or TF) takes the float32 route
-  // without LDS bricks, which propagates them.
+  // qs = 2^(28 - ceil(log2 B)) keeps every partial sum below 2^28 in the
+  // 32-bit brick (margin 8 for float32 rounding of the recovered T^(i)).  The
+  // emission-absorption bound is looser (a sum over the tile of per-ray
+  // worst cases), so its brick holds 64-bit entries and qs = 2^(50 - ceil(
+  // log2 B)): every value stays below 2^51, the range of the float64
+  // rounding of round_i64, and sums below 2^50 (margin 2^13 to overflow).
+  // A tile whose bound is not finite (NaN or Inf upstream gradients or TF)
+  // takes the float32 route without LDS bricks, which propagates them.
   const bool closed_form = !EA && mode == DDVR_ADJ_AUTO;
+  const bool ao_bound = !EA && (mode == DDVR_ADJ_AUTO || mode == DDVR_ADJ_INVERT_T ||
+                                mode == DDVR_ADJ_INVERT_ALPHA);
   s.qs = 1.0f;
   float inv_qs = 1.0f;
   bool fix_ok = true;
@@ -1120,7 +1162,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     int v[NV];
     v[0] = Nadj > 0 ? off + Nadj : 0;
     if (!EA) {
-      v[1] = __float_as_int((closed_form && lane_dv) ? fabsf(vd.step * s.P) : 0.0f);
+      v[1] = __float_as_int((ao_bound && lane_dv) ? fabsf(vd.step * s.P) : 0.0f);
     } else {
       float srgb = 0.0f, stau = 0.0f, rgbmax = 0.0f;
       if (want_dv) {
@@ -1156,7 +1198,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     } else if (B > 0.0f) {
       int ex;
       (void)frexpf(B, &ex);          // B < 2^ex
-      const int e = 28 - ex;
+      const int e = (EA ? 50 : 28) - ex;
       if (e > 120) {
         fix_ok = false;              // subnormal-scale gradients: float32 route
       } else {
@@ -1166,9 +1208,9 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     }
   }
   const bool use_fix = closed_form && fix_ok;
-  // the brick holds fixed point on the closed form and on every
-  // emission-absorption route (the others add float32)
-  const bool lds_fix = (closed_form || EA) && fix_ok;
+  // the brick holds fixed point on every route that stages it (a tile
+  // without a finite bound stages nothing: acap = 0 below)
+  const bool lds_fix = (ao_bound || EA) && fix_ok;
   s.dh = vd.step * s.P;
   s.dhq = s.dh * s.qs;
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || !use_fix;
@@ -1184,7 +1226,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     int a, b;
     slab_range(lo, hi, off, Nadj, a, b);
     if (st == 1) {
-      stage_brick<NT, DT>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
+      stage_brick<NT, DT, EA>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
       if (use_fix)
         march_adj<MODEL, DT, true, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
@@ -1197,7 +1239,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
                                       p.cell_acc, s);
       __syncthreads();
       if (want_dv) {
-        if (lds_fix) flush_brick<NT, true>(vd, br, acc, inv_qs);
+        if (lds_fix) flush_brick<NT, true, EA>(vd, br, acc, inv_qs);
         else flush_brick<NT, false>(vd, br, acc, 1.0f);
       }
     } else {

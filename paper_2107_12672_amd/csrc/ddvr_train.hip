@@ -117,6 +117,53 @@ __global__ __launch_bounds__(kNT) void k_entropy_grad(const float* img, int64_t 
   }
 }
 
+// The same two passes over every view of a batch in one launch each (the
+// loss of a step plan): work item b = view * chunks + chunk, the chunks of a
+// view striding over its pixels.  sums[2v], sums[2v+1] += S_v, U_v.
+__global__ __launch_bounds__(kNT) void k_entropy_sums_views(const ViewDesc* views, int chunks,
+                                                            int channels, double* sums) {
+  const int v = blockIdx.x / chunks, c = blockIdx.x % chunks;
+  const ViewDesc& vd = views[v];
+  const int64_t n = (int64_t)vd.W * vd.H;
+  const int off = channels - 1;
+  double s = 0.0, u = 0.0;
+  for (int64_t j = (int64_t)c * kNT + threadIdx.x; j < n; j += (int64_t)chunks * kNT) {
+    const double x = (double)vd.image[j * channels + off];
+    s += x;
+    if (x > 0.0) u += x * log2(x);
+  }
+  block_add(s, sums + 2 * v);
+  __syncthreads();
+  block_add(u, sums + 2 * v + 1);
+}
+
+// pass 2: the view's d_image is WRITTEN (every channel): -scale dOE_v/dalpha
+// on the alpha channel (0 where alpha = 0), 0 on the colour channels;
+// oe[v] = OE_v and loss += -scale OE_v (chunk 0, thread 0).
+__global__ __launch_bounds__(kNT) void k_entropy_grad_views(const ViewDesc* views, int chunks,
+                                                            int channels, const double* sums,
+                                                            double* oe, double* loss,
+                                                            float scale) {
+  const int v = blockIdx.x / chunks, c = blockIdx.x % chunks;
+  const ViewDesc& vd = views[v];
+  const int64_t n = (int64_t)vd.W * vd.H;
+  const double S = sums[2 * v], U = sums[2 * v + 1];
+  const double l2n = log2((double)n);
+  if (c == 0 && threadIdx.x == 0) {
+    const double val = (log2(S) - U / S) / l2n;
+    oe[v] = val;
+    if (loss) atomicAdd(loss, -(double)scale * val);
+  }
+  float* dimg = const_cast<float*>(vd.d_image);
+  const double k = -(double)scale / (S * l2n), US = U / S;
+  const int off = channels - 1;
+  for (int64_t j = (int64_t)c * kNT + threadIdx.x; j < n; j += (int64_t)chunks * kNT) {
+    const float x = vd.image[j * channels + off];
+    for (int ch = 0; ch < off; ++ch) dimg[j * channels + ch] = 0.0f;
+    dimg[j * channels + off] = x > 0.0f ? (float)(k * (US - log2((double)x))) : 0.0f;
+  }
+}
+
 __device__ __forceinline__ unsigned short to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);   // NaN
@@ -263,6 +310,19 @@ int launch_opacity_entropy(const float* img, int64_t n, int stride, int offset, 
   hipLaunchKernelGGL(k_entropy_sums, dim3(blocks), dim3(kNT), 0, s, img, n, stride, offset, work);
   hipLaunchKernelGGL(k_entropy_grad, dim3(blocks), dim3(kNT), 0, s, img, n, stride, offset,
                      (const double*)work, value, dimg, scale);
+  return (int)hipGetLastError();
+}
+
+int launch_entropy_views(const ViewDesc* views, int nview, int64_t max_pix, int channels,
+                         double* sums, double* oe, double* loss, float scale, void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t chunks = blocks_for(max_pix, kNT);
+  if (chunks > 256) chunks = 256;
+  hipLaunchKernelGGL(k_zero_f64, dim3((2 * nview + 63) / 64), dim3(64), 0, s, sums, 2 * nview);
+  hipLaunchKernelGGL(k_entropy_sums_views, dim3((unsigned)(nview * chunks)), dim3(kNT), 0, s,
+                     views, (int)chunks, channels, sums);
+  hipLaunchKernelGGL(k_entropy_grad_views, dim3((unsigned)(nview * chunks)), dim3(kNT), 0, s,
+                     views, (int)chunks, channels, (const double*)sums, oe, loss, scale);
   return (int)hipGetLastError();
 }
 

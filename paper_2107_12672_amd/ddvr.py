@@ -24,6 +24,7 @@ ADJ_AUTO, ADJ_INVERT_T, ADJ_INVERT_ALPHA, ADJ_CHECKPOINT, ADJ_RESIDUAL = 0, 1, 2
 LAUNCH_PLAIN = 0x10
 LOSS_L1 = 0x20
 PASS_FORWARD, PASS_ADJOINT, PASS_FUSED = 0, 1, 2
+PLAN_LOSS_GIVEN, PLAN_LOSS_FUSED, PLAN_LOSS_NEG_ENTROPY = 0, 1, 2
 
 EXPORTED = [
     "ddvr_abi_version", "ddvr_last_error", "ddvr_camera_from_sphere",
@@ -34,6 +35,8 @@ EXPORTED = [
     "ddvr_render_tangent", "ddvr_camera_sphere_tangents", "ddvr_density_from_color",
     "ddvr_color_tau_max", "ddvr_tf_prior", "ddvr_volume_prior", "ddvr_opacity_entropy",
     "ddvr_adam_step", "ddvr_resample_volume", "ddvr_resample_channels",
+    "ddvr_batch_graph_builds", "ddvr_plan_create", "ddvr_plan_execute", "ddvr_plan_loss_terms",
+    "ddvr_plan_destroy", "ddvr_valu_probe",
 ]
 MAX_DIRECTIONS = 4
 
@@ -126,6 +129,12 @@ def lib():
                            ctypes.c_int),
         "ddvr_resample_volume": ([P, I32, I32, I32, P, I32, I32, I32, P], ctypes.c_int),
         "ddvr_resample_channels": ([P, I32, I32, I32, I32, P, I32, I32, I32, P], ctypes.c_int),
+        "ddvr_batch_graph_builds": ([P, P], ctypes.c_int),
+        "ddvr_plan_create": ([P, I32, F, P, P, SZ, P, P], ctypes.c_int),
+        "ddvr_plan_execute": ([P, P], ctypes.c_int),
+        "ddvr_plan_loss_terms": ([P, P, I32, P], ctypes.c_int),
+        "ddvr_plan_destroy": ([P], None),
+        "ddvr_valu_probe": ([I32, I32, I32, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -338,6 +347,12 @@ class Batch:
         _check(fn(self.handle, pass_, loss_scale, _ptr(loss_out), _ptr(workspace), ws_bytes,
                   _stream(stream)))
 
+    def graph_builds(self) -> int:
+        """Graphs recorded by run(graph=True) so far."""
+        n = ctypes.c_int64(0)
+        _check(lib().ddvr_batch_graph_builds(self.handle, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib().ddvr_batch_destroy(self.handle)
@@ -348,6 +363,51 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Plan:
+    """The whole step of a batch (forward, loss gradient, adjoint, fallback)
+    recorded once into one HIP graph; run() replays it."""
+
+    def __init__(self, batch: Batch, loss: int, loss_scale: float = 1.0, loss_out=None,
+                 workspace=None, stream=None):
+        self._keep = (batch, loss_out, workspace)
+        self.n_views = len(batch._keep[2])
+        ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        h = ctypes.c_void_p()
+        _check(lib().ddvr_plan_create(batch.handle, loss, loss_scale, _ptr(loss_out),
+                                      _ptr(workspace), ws_bytes, _stream(stream),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(lib().ddvr_plan_execute(self.handle, _stream(stream)))
+
+    def loss_terms(self, stream=None) -> List[float]:
+        """Entropy plans: OE of every view at the last replay (synchronises)."""
+        out = (ctypes.c_double * self.n_views)()
+        _check(lib().ddvr_plan_loss_terms(self.handle, out, self.n_views, _stream(stream)))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ddvr_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def valu_probe(mode: int, blocks: int, iters: int, out, stream=None) -> int:
+    """One launch of the VALU issue-rate probe (mode 0 float32 FMA, 1 int add);
+    returns the lane-operations it executes."""
+    n = ctypes.c_int64(0)
+    _check(lib().ddvr_valu_probe(mode, blocks, iters, _ptr(out), ctypes.byref(n),
+                                 _stream(stream)))
+    return n.value
 
 
 def make_view(volume_index: int, cam: Camera, step: float, image, transmittance=None,

@@ -9,7 +9,8 @@ assembly and counts, for the absorption-only bf16 4-wave kernels:
   * forward: every VALU instruction of the innermost loop that gathers the
     8 corners from the LDS brick (four ds_read2_b32) -- one sample;
   * adjoint (closed form, fixed-point brick): every VALU instruction of the
-    innermost loop that adds to the LDS brick (ds_add_u32), except the basic
+    innermost loop that adds to the LDS brick (ds_add_u32) without an
+    exponential (the inversion loops have one), except the basic
     blocks that do the adding (the cell-exit flush, taken only when a ray
     leaves its cell) -- one sample, plus the flush block counted separately.
 It also counts, in ``csrc/ddvr_dfc.hip``, the VALU instructions of the
@@ -118,6 +119,10 @@ def count(asm: str) -> dict:
     for blocks in _inner(_kernel(asm, FUSED)).values():
         adders = [blk for _, blk in blocks if "ds_add_u32" in blk]
         if not adders:
+            continue
+        # the closed form's loop: the inversion loops of the same kernel (T-
+        # and alpha-form) also add to the brick but recompute exp(-dt tau)
+        if any(x.startswith("v_exp_f32") for _, blk in blocks for x in blk):
             continue
         common = [x for _, blk in blocks if "ds_add_u32" not in blk for x in blk]
         adj = sum(1 for x in common if x.startswith("v_"))

@@ -38,6 +38,12 @@ IMG_ATOL = 1e-4
 GRAD_RTOL = 1e-3
 TIE_TOL = 1e-3
 
+# Storage rounding (round to nearest even): |V_q - V| <= U_Q |V| + ETA_Q, with
+# U_Q the unit roundoff of the format and ETA_Q half the spacing of its
+# subnormals (the relative bound fails below the normal range).
+U_Q = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+ETA_Q = {"f32": 2.0 ** -150, "f16": 2.0 ** -25, "bf16": 2.0 ** -134}
+
 
 def torch_mod():
     import torch
@@ -63,6 +69,10 @@ class Problem:
     H: int
     step: float                # world units
 
+    def __post_init__(self):
+        # both sides take the step the kernels see: float32
+        self.step = float(np.float32(self.step))
+
     @property
     def C(self):
         return 1 if self.model == 0 else 4
@@ -86,14 +96,30 @@ def dequantized(p: Problem) -> np.ndarray:
     return v.to(torch.float64).numpy()
 
 
-def gpu_camera(p: Problem):
+def frame32(yaw, pitch, dist, fovy, W, H) -> np.ndarray:
+    """The camera frame both sides take: the oracle's frame of the pose,
+    rounded to float32 (the kernels' precision), so that the GPU and the
+    oracle render exactly the same input."""
+    return oracle.camera_from_sphere(yaw, pitch, dist, fovy, W, H).astype(np.float32)
+
+
+def camera_of_frame(f32, W, H):
+    """ddvr.Camera holding a float32 frame [eye, fwd, right, up]."""
     d = ddvr_mod()
-    return d.camera_from_sphere(math.radians(p.yaw), math.radians(p.pitch), p.dist,
-                                math.radians(p.fovy), p.W, p.H)
+    cam = d.Camera()
+    for a in range(3):
+        cam.eye[a], cam.fwd[a] = float(f32[a]), float(f32[3 + a])
+        cam.right[a], cam.up[a] = float(f32[6 + a]), float(f32[9 + a])
+    cam.width, cam.height = W, H
+    return cam
+
+
+def gpu_camera(p: Problem):
+    return camera_of_frame(frame32(p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H), p.W, p.H)
 
 
 def oracle_camera(p: Problem):
-    return oracle.camera_from_sphere(p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H)
+    return frame32(p.yaw, p.pitch, p.dist, p.fovy, p.W, p.H).astype(np.float64)
 
 
 def gpu_forward(p: Problem, flags=0, vol=None):
@@ -194,22 +220,72 @@ def sensitive_mask(p: Problem, pix, g, rel=1e-7, thresh=1e-3, trials=3, seed=0):
     return out
 
 
+def screen_camera_rays(p: Problem, pix, g, rel=1e-7, trials=3, frac=0.1, seed=0):
+    """Rays to leave out of an element-wise camera / step comparison.
+
+    Each ray's float64 camera-frame and step gradients are recomputed at
+    frames and steps perturbed by `rel` relative (the size of float32 rounding
+    of the inputs); a ray is screened when its own movement on any entry
+    exceeds `frac` of the element-wise bound of the SUM over the kept rays
+    (1e-3 max(|o_k|, 1e-2 max|o_cam|); 1e-3 |o_step| for the step).  The bound
+    depends on the kept set, so the screen is repeated until it is stable.
+    Returns (mask of screened rays, per-ray sensitivities [n][13])."""
+    V = dequantized(p)
+    cam = oracle_camera(p)
+    rng = np.random.default_rng(seed)
+    n = len(pix)
+    base = np.zeros((n, 13))
+    sens = np.zeros((n, 13))
+    pert = [(cam * (1.0 + rel * rng.normal(size=12)), p.step * (1.0 + rel * rng.normal()))
+            for _ in range(trials)]
+    for q in range(n):
+        gq = g[q:q + 1]
+        if not np.any(gq):
+            continue
+        a = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, gq, pix=pix[q:q + 1],
+                           want_dV=False)
+        base[q] = np.r_[a["dcam"], a["dstep"]]
+        for pc, ps in pert:
+            b = oracle.adjoint(V, p.tf, pc, p.W, p.H, ps, p.model, gq, pix=pix[q:q + 1],
+                               want_dV=False)
+            sens[q] = np.maximum(sens[q], np.abs(np.r_[b["dcam"], b["dstep"]] - base[q]))
+    screened = np.zeros(n, dtype=bool)
+    for _ in range(10):
+        o = base[~screened].sum(axis=0)
+        bound = np.empty(13)
+        bound[:12] = 1e-3 * np.maximum(np.abs(o[:12]), 1e-2 * np.abs(o[:12]).max())
+        bound[12] = 1e-3 * abs(o[12])
+        new = screened | np.any(sens > frac * bound[None, :], axis=1)
+        if np.array_equal(new, screened):
+            break
+        screened = new
+    return screened, sens
+
+
 def oracle_spread(p: Problem, pix, g, rel=1e-7, trials=3, seed=1):
     """Relative spread of the oracle's camera (norm-wise) and step gradients
     when the camera frame and the step are perturbed by `rel` relative (float32
-    rounding of the inputs).  Returns (cam_spread, step_spread)."""
+    rounding of the inputs).  Returns (cam_spread, step_spread, elem): elem is
+    the largest movement of any of the 13 entries (frame, step) as a fraction
+    of its element-wise bound (1e-3 max(|o_k|, 1e-2 max|o_cam|); 1e-3 |o_step|)."""
     V = dequantized(p)
     cam = oracle_camera(p)
     rng = np.random.default_rng(seed)
     base = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, g, pix=pix, want_dV=False)
-    cs = ss = 0.0
+    o = np.r_[base["dcam"], base["dstep"]]
+    bound = np.empty(13)
+    bound[:12] = 1e-3 * np.maximum(np.abs(o[:12]), 1e-2 * np.abs(o[:12]).max())
+    bound[12] = 1e-3 * abs(o[12])
+    cs = ss = el = 0.0
     for _ in range(trials):
         a = oracle.adjoint(V, p.tf, cam * (1.0 + rel * rng.normal(size=12)), p.W, p.H,
                            p.step * (1.0 + rel * rng.normal()), p.model, g, pix=pix,
                            want_dV=False)
         cs = max(cs, rel_norm_err(a["dcam"], base["dcam"]))
         ss = max(ss, abs(a["dstep"] - base["dstep"]) / max(abs(base["dstep"]), 1e-300))
-    return cs, ss
+        el = max(el, float((np.abs(np.r_[a["dcam"], a["dstep"]] - o) /
+                            np.maximum(bound, 1e-300)).max()))
+    return cs, ss, el
 
 
 def tie_mask(ratio: np.ndarray) -> np.ndarray:
@@ -247,3 +323,58 @@ def assert_dv_close(g, o, what, rtol=GRAD_RTOL):
     e = rel_norm_err(g, o)
     assert e <= rtol, f"{what}: norm-wise relative dV error {e:.3g} > {rtol}"
     return e
+
+
+def assert_dv_elementwise(g, o, what, rtol=GRAD_RTOL, floor_frac=1e-2):
+    """Density gradient voxel by voxel: |g - o| <= rtol * max(|o|, floor_frac *
+    max|o|).  Returns the worst ratio of error to bound."""
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    scale = float(np.abs(o).max())
+    bound = rtol * np.maximum(np.abs(o), floor_frac * scale)
+    ratio = np.abs(g - o) / np.maximum(bound, 1e-300)
+    worst = float(ratio.max())
+    bad = int((ratio > 1.0).sum())
+    assert bad == 0, f"{what}: {bad} of {ratio.size} voxels off element-wise; worst " \
+                     f"{worst:.3g} x the bound (scale {scale:.3g})"
+    return worst
+
+
+def quantisation_image_bound(V, tf, cam, W, H, step, storage, pix, model):
+    """A-priori bound, per sampled pixel, on |image(V_q) - image(V)| for a
+    non-negative float32 master grid V stored as V_q (RNE cast to `storage`).
+
+    Every vertex moves by at most u|V| + eta, so every sample's density by at
+    most u d_i + eta, and the ray's density integral D = dt sum d_i (the
+    absorption-only optical depth, -log T_N of the AO render of V) by at most
+    u D + eta L, L = N dt the ray's length.
+      * absorption-only: |alpha_q - alpha| = |T_N - T_N'| <= T_N (e^E - 1),
+        E = u D + eta L;
+      * emission-absorption: the optical depth moves by at most E = L_tau (u D
+        + eta L), L_tau = (R-1) max |tau_(j+1) - tau_j| the TF's slope bound, so
+        |alpha_q - alpha| <= T_N (e^E - 1) with the EA transmittance T_N; the
+        blend weights w_i = T_i alpha_i move by at most 2E in total (their
+        derivatives: -dt w_i per earlier tau_j, dt T_i e_i for their own), the
+        colours by at most L_rgb (u + eta) (density clamped to [0, 1]), so
+        |C_q - C|_c <= 2 E max|rgb| + L_rgb (u + eta).
+    Returns [npix][C] bounds (C = 1 AO, 4 EA: r, g, b, alpha)."""
+    u, eta = U_Q[storage], ETA_Q[storage]
+    assert np.all(np.asarray(V) >= 0.0), "the bound assumes a non-negative grid"
+    ao = oracle.render(V, None, cam, W, H, step, oracle.AO, pix=pix)
+    Tn = ao["trans"]
+    with np.errstate(divide="ignore"):
+        D = np.where(Tn > 0.0, -np.log(np.maximum(Tn, 1e-300)), np.inf)
+    L = ao["nsamp"] * step
+    if model == oracle.AO:
+        E = u * D + eta * L
+        return (Tn * np.expm1(E))[:, None]
+    tf = np.asarray(tf, np.float64)
+    R = tf.shape[0]
+    L_tau = (R - 1) * float(np.abs(np.diff(tf[:, 3])).max())
+    L_rgb = (R - 1) * float(np.abs(np.diff(tf[:, :3], axis=0)).max())
+    m = float(np.abs(tf[:, :3]).max())
+    ea = oracle.render(V, tf, cam, W, H, step, oracle.EA, pix=pix)
+    E = L_tau * (u * D + eta * L)
+    b_alpha = ea["trans"] * np.expm1(E)
+    b_rgb = 2.0 * E * m + L_rgb * (u + eta)
+    return np.stack([b_rgb, b_rgb, b_rgb, b_alpha], axis=1)

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     d = _ddvr()
-    assert d.abi_version() == 3
+    assert d.abi_version() == 4
     assert isinstance(d.last_error(), str)
 
 
@@ -336,3 +336,23 @@ def test_training_loop_validation():
     assert L.ddvr_render_fused_l2(B(vol), B(tf), B(cam), 0.1, 1, 0x3000, 1.0, 0x4000, 0x4100,
                                   B(g), d.LOSS_L1 | 0x100, None, 0, None, None,
                                   None) == d.ERR_VALUE
+
+
+def test_plan_and_probe_reject_bad_arguments_before_launch():
+    """Step plans, the VALU probe and the graph-build counter validate on the
+    host (no GPU needed)."""
+    import ctypes
+    d = _ddvr()
+    L = d.lib()
+    out = ctypes.c_void_p()
+    assert L.ddvr_plan_create(None, 0, 1.0, None, None, 0, None, ctypes.byref(out)) == d.ERR_NULL
+    assert L.ddvr_plan_create(None, 0, 1.0, None, None, 0, None, None) == d.ERR_NULL
+    assert L.ddvr_plan_execute(None, None) == d.ERR_NULL
+    assert L.ddvr_plan_loss_terms(None, None, 0, None) == d.ERR_NULL
+    L.ddvr_plan_destroy(None)
+    n = ctypes.c_int64(0)
+    assert L.ddvr_batch_graph_builds(None, ctypes.byref(n)) == d.ERR_NULL
+    buf = ctypes.c_void_p(16)                      # never dereferenced: rejected first
+    assert L.ddvr_valu_probe(2, 1, 1, buf, ctypes.byref(n), None) == d.ERR_VALUE
+    assert L.ddvr_valu_probe(0, 0, 1, buf, ctypes.byref(n), None) == d.ERR_SHAPE
+    assert L.ddvr_valu_probe(0, 1, 1, None, ctypes.byref(n), None) == d.ERR_NULL
