@@ -263,6 +263,26 @@ int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
                         const ddvr_grads* grads, int32_t flags, void* workspace,
                         size_t workspace_bytes, int32_t* n_fallback_rays, void* hip_stream);
 
+/* ddvr_render_adjoint without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Nothing is allocated: the
+ * checkpoint fallback's ray queue and slots live in a static 64 MiB device
+ * array of the library, one per device, held until the process ends (its
+ * address is looked up once per device on the first call there).  Same
+ * arguments, results and errors as ddvr_render_adjoint otherwise; fewer
+ * concurrent checkpoint slots may run when the view is large.
+ *   - DDVR_ERR_WORKSPACE if the view's queue (8 bytes per pixel) and at least
+ *     256 checkpoint slots (4 (2 ceil(sqrt(samples per ray)) + 4) bytes each,
+ *     rounded up to 256) exceed 64 MiB, e.g. above ~2800x2800 pixels.
+ *   - Calls on one device share the array: calls that overlap on one device
+ *     (other streams, other threads) race and must be serialised by the
+ *     caller.  Each call clears what it needs (the queue length) itself. */
+int ddvr_render_adjoint_noalloc(const ddvr_volume* vol, const ddvr_tf* tf,
+                                const ddvr_camera* cam, float step_world, int32_t model,
+                                const float* image, const float* transmittance,
+                                const float* d_image, const ddvr_grads* grads, int32_t flags,
+                                int32_t* n_fallback_rays, void* hip_stream);
+
 /* Fused forward -> loss gradient -> adjoint of one view, one launch
  * (pixel-local loss only).  loss = loss_scale * sum((image - target)^2), or
  * loss_scale * sum |image - target| with DDVR_LOSS_L1 in flags.

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,6 +16,14 @@
 #include "ddvr_internal.h"
 
 using namespace ddvr;
+
+// Scratch of the allocation-free adjoint (ddvr_render_adjoint_noalloc): the
+// checkpoint fallback's ray queue and per-slot storage.  One copy per device,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device (static_scratch).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -36,6 +45,29 @@ int hip_fail(hipError_t e, const char* what) {
 int check_pending() {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "pending HIP error");
+  return DDVR_OK;
+}
+
+// Device address of the current device's `scratch`, looked up on the first
+// call on that device (with it current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "querying the current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DDVR_ERR_UNSUPPORTED, "device %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+    if (!p) return fail(DDVR_ERR_HIP, "address of the static scratch is NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return DDVR_OK;
 }
 
@@ -237,7 +269,10 @@ struct FbLayout {
   size_t bytes = 0;
 };
 
-FbLayout fallback_layout(int64_t rays, int64_t nmax_samples) {
+// budget > 0: at most `budget` bytes (fewer slots, down to one workgroup's
+// 256; the queue always holds every ray); L.bytes > budget when even that
+// does not fit.
+FbLayout fallback_layout(int64_t rays, int64_t nmax_samples, size_t budget = 0) {
   FbLayout L;
   L.cap = rays;
   int K = (int)std::ceil(std::sqrt((double)nmax_samples));
@@ -247,7 +282,13 @@ FbLayout fallback_layout(int64_t rays, int64_t nmax_samples) {
   L.slots = (int)std::min<int64_t>(kFallbackSlots, std::max<int64_t>(rays, 1));
   L.bytes = 256 + (size_t)8 * rays;
   L.bytes = (L.bytes + 255) / 256 * 256;
-  L.bytes += (size_t)L.slots * L.slot_floats * sizeof(float);
+  const size_t slot_bytes = (size_t)L.slot_floats * sizeof(float);
+  if (budget > 0) {
+    const size_t room = budget > L.bytes ? budget - L.bytes : 0;
+    const int64_t fit = (int64_t)(room / slot_bytes);
+    L.slots = (int)std::max<int64_t>(std::min<int64_t>(L.slots, fit), std::min(256, L.slots));
+  }
+  L.bytes += (size_t)L.slots * slot_bytes;
   return L;
 }
 
@@ -295,7 +336,8 @@ int read_fallback_count(const LaunchParams& p, hipStream_t s, int32_t* out) {
 int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,
                float step, int model, float* image, float* trans, const float* d_image,
                const float* target, float loss_scale, const ddvr_grads* grads, int flags,
-               void* ws, size_t ws_bytes, int32_t* n_fb, double* loss_out, void* stream) {
+               void* ws, size_t ws_bytes, int32_t* n_fb, double* loss_out, void* stream,
+               bool ws_budget = false) {
   int rc;
   if ((rc = validate_model(model)) || (rc = validate_volume(vol)) || (rc = validate_tf(tf, model)) ||
       (rc = validate_camera(cam)) || (rc = validate_step(vol, step)) || (rc = validate_flags(flags)) ||
@@ -316,7 +358,12 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
         model == DDVR_EMISSION_ABSORPTION) {
       // the fallback kernel recomputes the loss gradient from the written image
     }
-    L = fallback_layout((int64_t)cam->width * cam->height, max_samples(vol, step));
+    L = fallback_layout((int64_t)cam->width * cam->height, max_samples(vol, step),
+                        ws_budget ? ws_bytes : 0);
+    if (ws_budget && L.bytes > ws_bytes)
+      return fail(DDVR_ERR_WORKSPACE, "a %dx%d view with up to %lld samples per ray needs %zu "
+                  "bytes of scratch, the library's static scratch holds %zu", cam->width,
+                  cam->height, (long long)max_samples(vol, step), L.bytes, ws_bytes);
     if (!ws || ws_bytes < L.bytes)
       return fail(DDVR_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.bytes,
                   ws ? ws_bytes : (size_t)0);
@@ -820,6 +867,23 @@ int ddvr_render_adjoint(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
   return run_single(PASS_ADJ, vol, tf, cam, step_world, model, const_cast<float*>(image),
                     const_cast<float*>(transmittance), d_image, nullptr, 0.0f, grads, flags,
                     workspace, workspace_bytes, n_fallback_rays, nullptr, hip_stream);
+}
+
+int ddvr_render_adjoint_noalloc(const ddvr_volume* vol, const ddvr_tf* tf,
+                                const ddvr_camera* cam, float step_world, int32_t model,
+                                const float* image, const float* transmittance,
+                                const float* d_image, const ddvr_grads* grads, int32_t flags,
+                                int32_t* n_fallback_rays, void* hip_stream) {
+  if (!grads) return fail(DDVR_ERR_NULL, "grads is NULL");
+  int rc;
+  if ((rc = validate_model(model)) || (rc = validate_flags(flags))) return rc;
+  void* ws = nullptr;
+  if (model != DDVR_COLOR && needs_fallback(model, flags) && (rc = static_scratch(&ws)))
+    return rc;
+  return run_single(PASS_ADJ, vol, tf, cam, step_world, model, const_cast<float*>(image),
+                    const_cast<float*>(transmittance), d_image, nullptr, 0.0f, grads, flags,
+                    ws, ws ? kStaticScratchBytes : 0, n_fallback_rays, nullptr, hip_stream,
+                    true);
 }
 
 int ddvr_render_fused_l2(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_camera* cam,

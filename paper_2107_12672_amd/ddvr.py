@@ -36,7 +36,7 @@ EXPORTED = [
     "ddvr_color_tau_max", "ddvr_tf_prior", "ddvr_volume_prior", "ddvr_opacity_entropy",
     "ddvr_adam_step", "ddvr_resample_volume", "ddvr_resample_channels",
     "ddvr_batch_graph_builds", "ddvr_plan_create", "ddvr_plan_execute", "ddvr_plan_loss_terms",
-    "ddvr_plan_destroy", "ddvr_valu_probe",
+    "ddvr_plan_destroy", "ddvr_valu_probe", "ddvr_render_adjoint_noalloc",
 ]
 MAX_DIRECTIONS = 4
 
@@ -135,6 +135,7 @@ def lib():
         "ddvr_plan_loss_terms": ([P, P, I32, P], ctypes.c_int),
         "ddvr_plan_destroy": ([P], None),
         "ddvr_valu_probe": ([I32, I32, I32, P, P, P], ctypes.c_int),
+        "ddvr_render_adjoint_noalloc": ([P, P, P, F, I32, P, P, P, P, I32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -291,6 +292,20 @@ def render_adjoint(volume, tf, cam: Camera, step: float, model: int, image, tran
         ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step, model, _ptr(image),
         _ptr(transmittance), _ptr(d_image), ctypes.byref(grads), flags, _ptr(workspace),
         ws_bytes, ctypes.byref(nfb) if count_fallback else None, _stream(stream)))
+    return nfb.value
+
+
+def render_adjoint_noalloc(volume, tf, cam: Camera, step: float, model: int, image,
+                           transmittance, d_image, grads: Grads, flags: int = 0,
+                           count_fallback: bool = False, stream=None) -> int:
+    """render_adjoint with the fallback's scratch in the library's static
+    device array (no workspace, no allocation)."""
+    v, t = volume_desc(volume), tf_desc(tf)
+    nfb = ctypes.c_int32(0)
+    _check(lib().ddvr_render_adjoint_noalloc(
+        ctypes.byref(v), ctypes.byref(t), ctypes.byref(cam), step, model, _ptr(image),
+        _ptr(transmittance), _ptr(d_image), ctypes.byref(grads), flags,
+        ctypes.byref(nfb) if count_fallback else None, _stream(stream)))
     return nfb.value
 
 

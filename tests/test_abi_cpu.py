@@ -338,9 +338,9 @@ def test_training_loop_validation():
                                   None) == d.ERR_VALUE
 
 
-def test_plan_and_probe_reject_bad_arguments_before_launch():
-    """Step plans, the VALU probe and the graph-build counter validate on the
-    host (no GPU needed)."""
+def test_plan_probe_and_noalloc_reject_bad_arguments_before_launch():
+    """Step plans, the VALU probe, the graph-build counter and the
+    allocation-free adjoint validate on the host (no GPU needed)."""
     import ctypes
     d = _ddvr()
     L = d.lib()
@@ -356,3 +356,15 @@ def test_plan_and_probe_reject_bad_arguments_before_launch():
     assert L.ddvr_valu_probe(2, 1, 1, buf, ctypes.byref(n), None) == d.ERR_VALUE
     assert L.ddvr_valu_probe(0, 0, 1, buf, ctypes.byref(n), None) == d.ERR_SHAPE
     assert L.ddvr_valu_probe(0, 1, 1, None, ctypes.byref(n), None) == d.ERR_NULL
+    vol = d.Volume(16, d.F32, 8, 8, 8)
+    tf = d.TF(None, 0)
+    cam = d.camera_from_sphere(0.3, 0.2, 2.5, 1.0, 16, 16)
+    g = d.grads_desc()
+    assert L.ddvr_render_adjoint_noalloc(ctypes.byref(vol), ctypes.byref(tf), ctypes.byref(cam),
+                                         0.1, 0, buf, buf, buf, None, 0, None, None) == d.ERR_NULL
+    assert L.ddvr_render_adjoint_noalloc(ctypes.byref(vol), ctypes.byref(tf), ctypes.byref(cam),
+                                         0.1, 7, buf, buf, buf, ctypes.byref(g), 0, None,
+                                         None) == d.ERR_VALUE
+    assert L.ddvr_render_adjoint_noalloc(ctypes.byref(vol), ctypes.byref(tf), ctypes.byref(cam),
+                                         -1.0, 0, buf, buf, buf, ctypes.byref(g), 0, None,
+                                         None) == d.ERR_VALUE
