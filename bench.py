@@ -43,7 +43,6 @@ VALU_NONPACKED_TOPS = 256 * 64 * 2.4e9 / 1e12
 # independent non-packed fp32 FMAs measured on the device with the library's
 # own flags (bench.py --calibrate-valu, summary in profiles/)
 VALU_CEILING_FILE = os.path.join(ROOT, "profiles", "valu_ceiling.json")
-VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
 ALG_BYTES_BF16 = 64      # per sample pair: 8 gathers x 2 B (fwd) + 8 x 2 B (adj) + 8 x 4 B scatter
 ALG_BYTES_F32 = 96
 KERNEL_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_kernels.hip",
@@ -74,18 +73,6 @@ def measured_traffic():
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
-
-
-def valu_counts():
-    """Per-sample VALU instruction counts of the fused kernel's loops (from
-    ``python -m paper_2107_12672_amd.isa_count --write``), if they were taken
-    on the current kernel source."""
-    try:
-        with open(VALU_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    return t if t.get("kernel_source_sha") == kernel_source_hash() else None
 
 
 def valu_ceiling():
@@ -125,37 +112,6 @@ def cpu_model():
     except OSError:
         pass
     return None
-
-
-def cell_visits(work, cams, W, H):
-    """Grid cells entered by all rays of all views (each entry ends in one
-    cell-exit flush of the adjoint), from the rays' box entry and exit points:
-    a ray's cell index is monotone per axis, so it visits 1 + sum_a |k_a(exit)
-    - k_a(entry)| cells (up to simultaneous crossings)."""
-    import numpy as np
-    n = np.array(work.volume.shape[::-1], np.float64)          # nx, ny, nz
-    h = 2.0 / (n.max() - 1)
-    bmin, bmax = -0.5 * (n - 1) * h, 0.5 * (n - 1) * h
-    u = (2.0 * (np.arange(W) + 0.5) / W - 1.0)[None, :]
-    v = (1.0 - 2.0 * (np.arange(H) + 0.5) / H)[:, None]
-    total = 0
-    for c in cams:
-        cam = np.array(c.frame(), np.float64)                 # the library's camera frame
-        e, f, r, up = cam[0:3], cam[3:6], cam[6:9], cam[9:12]
-        w = f[None, None, :] + u[..., None] * r + v[..., None] * up
-        om = w / np.linalg.norm(w, axis=-1, keepdims=True)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            ta = (bmin - e) / om
-            tb = (bmax - e) / om
-        t0 = np.maximum(np.nanmax(np.minimum(ta, tb), axis=-1), 0.0)
-        t1 = np.nanmin(np.maximum(ta, tb), axis=-1)
-        hit = t1 > t0
-        q0 = (e + t0[..., None] * om - bmin) / h
-        q1 = (e + t1[..., None] * om - bmin) / h
-        k0 = np.clip(np.floor(q0), 0, n - 2)
-        k1 = np.clip(np.floor(q1), 0, n - 2)
-        total += int((1 + np.abs(k1 - k0).sum(-1))[hit].sum())
-    return total
 
 
 def cpu_baseline(work, n_views_max, budget_s=12.0, one_core_s=6.0):
@@ -279,6 +235,8 @@ def _timed(fn, steps, warmup, stream, torch):
 
 def secondary(args):
     """The other workloads, one JSON line each (not the headline figure):
+      c1  absorption-only 32^3 f32, one 64x64 view, step 0.5 voxel, fused L2
+          (launch-bound: timed as a single-view call and as a graph replay);
       c2  emission-absorption 128^3 f32, R=16, one 256x256 view, fused L2 with
           gradients for density, TF, camera and step;
       c4  uneven batch of 16 grids (edges 64-384, f16/f32, R 8-64, images
@@ -321,7 +279,39 @@ def secondary(args):
     out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "unit": "ray-samples/s"}
-    if args.workload in ("c2", "c5"):
+    if args.workload == "c1":
+        # one small view: the launch and its synchronisation dominate
+        w = synth.make_c1()
+        v = w.views[0]
+        vol = stored(w.volume, "f32")
+        cam = cams_of([v])[0]
+        # target: the render of the second blob grid (the workload's recipe)
+        tgt = torch.from_numpy(np.ascontiguousarray(w.target_volume)).to(dev)
+        targets = torch.empty((v.height, v.width), device=dev)
+        d.render_forward(tgt, None, cam, w.step_world, d.ABSORPTION, targets)
+        image = torch.empty_like(targets)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        g = d.grads_desc(dV)
+        scale = 1.0 / image.numel()
+        b = d.Batch([vol], None, [d.make_view(0, cam, w.step_world, image, target=targets)],
+                    d.ABSORPTION, d_volumes=[dV])
+        S = b.sample_count()
+        ms_single = _timed(lambda: d.render_fused_l2(vol, None, cam, w.step_world, d.ABSORPTION,
+                                                     targets, scale, image, None, g,
+                                                     loss_out=loss),
+                           max(args.steps, 50), args.warmup, stream, torch)
+        ms_graph = _timed(lambda: b.run(d.PASS_FUSED, scale, loss, graph=True),
+                          max(args.steps, 50), args.warmup, stream, torch)
+        b.close()
+        log(f"c1: single-view call {ms_single * 1e3:.1f} us, graph replay {ms_graph * 1e3:.1f} us, "
+            f"{S} samples")
+        out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
+                    "value": S / (ms_graph * 1e-3), "ms_per_step": ms_graph,
+                    "config": {"workload": w.name + ", fused L2, density gradient",
+                               "samples_per_step": S, "single_call_ms": ms_single,
+                               "launch": "one fused launch, HIP graph replay"}})
+    elif args.workload in ("c2", "c5"):
         w = synth.make_c2() if args.workload == "c2" else synth.make_c5()
         vol = stored(w.volume, w.storage)
         tf = torch.from_numpy(w.tf).to(dev)
@@ -348,7 +338,7 @@ def secondary(args):
         scale = 1.0 / images.numel()
         res = {}
         for mode, flags in (("auto", 0), ("checkpoint", 3)):
-            if args.workload == "c2" and flags:
+            if flags and (args.workload == "c2" or args.c5_checkpoint <= 0):
                 continue
             views = [d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
                                  target=targets[i], d_step=dstep[i:i + 1], tf_index=0,
@@ -699,6 +689,17 @@ def inversion_c3(d, torch, vol16, views, dV, scale, loss, S, args, stream):
     return rec
 
 
+def load_counters(name):
+    """Committed rocprofv3 counters of a kernel (profiles/counters_<name>.json),
+    if taken on the current kernel source."""
+    try:
+        with open(os.path.join(ROOT, "profiles", f"counters_{name}.json")) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return t if t.get("kernel_source_sha") == kernel_source_hash() else None
+
+
 def counters_record(name, ms):
     """Committed rocprofv3 counters of a kernel (profiles/counters_<name>.json,
     taken on the current kernel source) as rates over `ms` per launch."""
@@ -714,12 +715,12 @@ def counters_record(name, ms):
         gbs = t["dram_bytes_per_launch"] / (ms * 1e-3) / 1e9
         out["dram_gbs"] = round(gbs, 1)
         out["dram_frac"] = round(gbs / HBM_PEAK_GBS, 4)
-    if t.get("valu_wave_instr_per_launch"):
-        tops = t["valu_wave_instr_per_launch"] * 64 / (ms * 1e-3) / 1e12
+    if t.get("valu_thread_cycles_per_launch"):
+        tops = t["valu_thread_cycles_per_launch"] / (ms * 1e-3) / 1e12
         ceil = valu_ceiling()
-        out["valu_issue_tops"] = round(tops, 3)
+        out["valu_active_lane_tops"] = round(tops, 3)
         if ceil:
-            out["valu_issue_frac"] = round(tops / ceil, 4)
+            out["valu_frac"] = round(tops / ceil, 4)
     return out
 
 
@@ -757,6 +758,13 @@ def inversion_c5(d, torch, args, stream):
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     scale = 1.0 / images.numel()
     res = {"workload": w.name + ", fused L2, gradients density+TF+step"}
+    # launch shape: the autotuner's choice for this class, if cached
+    from paper_2107_12672_amd import autotune
+    old_tuning = d.get_tuning()
+    res["tuning_source"] = "autotuned" if autotune.apply(autotune.workload_key(
+        _arch(torch), d.EMISSION_ABSORPTION, "f16", w.tf.shape[0], W, w.volume.shape[0],
+        "V+TF+step", d.PASS_FUSED)) else "default"
+    res["tuning"] = d.get_tuning()
     for mode, flags, steps, warm in (("auto", d.ADJ_AUTO, max(2, min(args.steps, 5)), 1),
                                      ("checkpoint", d.ADJ_CHECKPOINT, args.c5_checkpoint, 0)):
         if steps <= 0:
@@ -777,6 +785,7 @@ def inversion_c5(d, torch, args, stream):
         rec.update(counters_record(f"k_render_ea_f16_{mode}_c5", ms))
         res[mode] = rec
         log(f"c5 {mode}: {ms:.3f} ms, {S / (ms * 1e-3):.4g} ray-samples/s")
+    d.set_tuning(**old_tuning)
     return res
 
 
@@ -789,7 +798,8 @@ def main():
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
     ap.add_argument("--step-vox", type=float, default=0.2)
-    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c4", "c5", "viewpoint", "color", "dfc", "recon"),
+    ap.add_argument("--workload", default="c3",
+                    choices=("c3", "c1", "c2", "c4", "c5", "viewpoint", "color", "dfc", "recon"),
                     help="c3 (default) is the headline tomography step; the others print "
                          "their own line")
     ap.add_argument("--burn-in", type=int, default=4,
@@ -833,7 +843,7 @@ def main():
         res = {"device": props.name, "compute_units": props.multi_processor_count}
         for mode, name in ((0, "fma"), (1, "int_add")):
             for blocks in (2048, 8192):
-                tops, ms = valu_probe(mode, blocks, 4000)
+                tops, ms = valu_probe(mode, blocks, 16000)
                 key = f"{name}_{blocks}wg"
                 res[key] = {"tops": round(tops, 3), "ms": round(ms, 4),
                             "wave_instr_per_cu_per_ns": round(
@@ -940,43 +950,41 @@ def main():
     seeded = float((images != targets).float().mean())
     log(f"pixels with a non-zero residual: {seeded:.4f}, loss {float(loss):.4g}")
 
-    # The fused kernel is bound by VALU issue (rocprofv3: VALU busy on ~98% of
-    # SIMD cycles, DRAM traffic under a tenth of peak), so its roofline is the
-    # ALU one: per-sample VALU operations of the forward and adjoint loops
-    # (counted in the kernel's assembly) plus one cell-exit flush per grid cell
-    # a ray enters, per launch, over the kernel's event-timed duration, against
-    # the measured issue ceiling of non-packed VALU instructions.
+    # The fused kernel is bound by VALU throughput: rocprofv3's count of
+    # active-lane VALU cycles per launch (SQ_THREAD_CYCLES_VALU, committed with
+    # the kernel source's hash) over the kernel's event-timed duration, against
+    # the measured ceiling of the same quantity (independent non-packed fp32
+    # FMAs, all lanes active).  Without committed counters for this source the
+    # estimate is the per-run VALU count of the assembly times the runs.
     achieved_gbs = S * ALG_BYTES_BF16 / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic()
-    vc = valu_counts()
-    cells = cell_visits(work, cams, W, H)
-    live_tops, _ = valu_probe(0, 8192, 1000)
+    counters = load_counters("k_render_ao_bf16_fused_c3")
+    live_tops, _ = valu_probe(0, 8192, 4000)
     ceiling = valu_ceiling()
     peak = ceiling if ceiling else live_tops
     log(f"VALU ceiling: committed {ceiling}, live probe {live_tops:.3f} T lane-ops/s")
-    if vc:
-        ops = S * (vc["forward_valu_per_sample"] + vc["adjoint_valu_per_sample"]) + \
-            cells * vc["adjoint_cell_exit_flush_valu"]
+    roofline = {"bound": "alu", "achieved": None, "peak": round(peak, 3), "unit": "TOP/s",
+                "frac": None, "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
+                "kernel_ms": round(k_ms, 4),
+                "peak_source": "measured: independent non-packed fp32 FMAs, all lanes active, "
+                               "library flags (profiles/valu_ceiling.json)" if ceiling else
+                               "measured live: VALU probe of this run",
+                "peak_live": round(live_tops, 3),
+                "peak_published_fp32": VALU_PUBLISHED_TOPS,
+                "peak_nonpacked_nominal": VALU_NONPACKED_TOPS}
+    if counters and counters.get("valu_thread_cycles_per_launch"):
+        ops = counters["valu_thread_cycles_per_launch"]
         a_tops = ops / (k_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(a_tops, 3), "peak": round(peak, 3),
-                    "unit": "TOP/s", "frac": round(a_tops / peak, 4),
-                    "traffic": traffic, "kernel": "k_render<AO,bf16,4 waves,fused>",
-                    "kernel_ms": round(k_ms, 4), "ops_per_launch": ops,
-                    "ops": "VALU lane-operations: per sample forward %d + adjoint %d, "
-                           "%d per cell exit (%d cell entries)" % (
-                               vc["forward_valu_per_sample"], vc["adjoint_valu_per_sample"],
-                               vc["adjoint_cell_exit_flush_valu"], cells),
-                    "peak_source": "measured: independent non-packed fp32 FMAs, library flags "
-                                   "(profiles/valu_ceiling.json)" if ceiling else
-                                   "measured live: VALU probe of this run",
-                    "peak_live": round(live_tops, 3),
-                    "peak_published_fp32": VALU_PUBLISHED_TOPS,
-                    "peak_nonpacked_nominal": VALU_NONPACKED_TOPS}
+        roofline.update({"achieved": round(a_tops, 3), "frac": round(a_tops / peak, 4),
+                         "ops_per_launch": ops,
+                         "ops": "active-lane VALU cycles per launch (rocprofv3 "
+                                "SQ_THREAD_CYCLES_VALU, profiles/counters_"
+                                "k_render_ao_bf16_fused_c3.json)",
+                         "valu_wave_instr_per_launch":
+                             counters.get("valu_wave_instr_per_launch")})
     else:
-        roofline = {"bound": "alu", "achieved": None, "peak": round(peak, 3), "unit": "TOP/s",
-                    "frac": None, "traffic": traffic,
-                    "note": "VALU counts missing or taken on another kernel source: run "
-                            "python -m paper_2107_12672_amd.isa_count --write"}
+        roofline["note"] = ("counters missing or taken on another kernel source: "
+                            "profiles/counters_k_render_ao_bf16_fused_c3.json")
     roofline_hbm = None
     if traffic:
         gbs = traffic / (k_ms * 1e-3) / 1e9

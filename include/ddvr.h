@@ -237,7 +237,10 @@ int ddvr_render_forward(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
                         float step_world, int32_t model, float* image, float* transmittance,
                         int32_t flags, void* hip_stream);
 
-/* Bytes of workspace render_adjoint / render_fused_l2 need for `flags`
+/* Storage of the segment-checkpoint fallback (Sec. 4.4: the inversion needs
+ * none, but it fails as alpha -> 1; the fallback stores the transmittance at
+ * segment starts, a square-root share of the tape of Sec. 4.3).
+ * Bytes of workspace render_adjoint / render_fused_l2 need for `flags`
  * (0 unless a checkpoint path can run: emission-absorption AUTO,
  * INVERT_ALPHA and CHECKPOINT).  The size depends on the pixel count and on
  * sqrt(samples per ray), not on the samples themselves.  bytes (host). */
@@ -283,7 +286,10 @@ int ddvr_render_adjoint_noalloc(const ddvr_volume* vol, const ddvr_tf* tf,
                                 const float* d_image, const ddvr_grads* grads, int32_t flags,
                                 int32_t* n_fallback_rays, void* hip_stream);
 
-/* Fused forward -> loss gradient -> adjoint of one view, one launch
+/* Alg. 1, then Alg. 2 seeded by the image loss's gradient (its first line,
+ * here computed in the kernel from the L2 loss, or the L1 image loss of eq.
+ * (tf-loss)), in one launch: the forward's state stays in registers.
+ * Fused forward -> loss gradient -> adjoint of one view, one launch
  * (pixel-local loss only).  loss = loss_scale * sum((image - target)^2), or
  * loss_scale * sum |image - target| with DDVR_LOSS_L1 in flags.
  *   target      layout of `image`.
@@ -430,7 +436,9 @@ int ddvr_resample_channels(const float* src, int32_t channels, int32_t sx, int32
                            void* hip_stream);
 
 /* ------------------------------------------------------------------------
- * Batches: many views of one or several grids in ONE launch.
+ * Batches: many views of one or several grids in ONE launch (no paper
+ * counterpart: the paper renders its views one after another, Sec. 5; the
+ * per-view work is Alg. 1 / Alg. 2 as above).
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t volume;          /* index into the batch's volume array */

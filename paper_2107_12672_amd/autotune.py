@@ -181,12 +181,14 @@ def main(argv=None) -> None:
       c3     absorption-only tomography (256^3 bf16, 64 views at 512x512, fused pass);
       c4     the uneven batch (16 grids of mixed size and storage, one view each,
              minus the opacity entropy, camera + step gradients, one step plan);
+      c5     emission-absorption 512^3 f16, 32 views at 1024x1024, R=32, fused pass
+             with density, TF and step gradients (T-form inversion, AUTO);
       color  the colour volume (256^3 x 4 bf16, the c3 views, fused pass)."""
     import argparse
     import sys
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "color"))
+    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "color"))
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
@@ -238,6 +240,49 @@ def main(argv=None) -> None:
         key = c4_key(_device_arch())
         res = tune(key, make, lambda b: state["plan"].run(), lambda: flat,
                    candidates=uneven_candidates(), reps=args.reps, verbose=True)
+        print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
+        return
+    if args.workload == "c5":
+        w = synth.make_c5()
+        v32 = torch.from_numpy(np.ascontiguousarray(w.volume)).to(dev)
+        vol = torch.empty_like(v32, dtype=torch.float16)
+        _d.cast_volume(v32, vol)
+        del v32
+        tf = torch.from_numpy(w.tf).to(dev)
+        W = w.views[0].width
+        cams = [_d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                      math.radians(v.fovy), W, W) for v in w.views]
+        nv = len(cams)
+        targets = torch.rand((nv, W, W, 4), device=dev,
+                             generator=torch.Generator("cuda").manual_seed(1))
+        images = torch.empty_like(targets)
+        trans = torch.empty((nv, W, W), device=dev)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        dTF = torch.zeros_like(tf)
+        dstep = torch.zeros(nv, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        scale = 1.0 / images.numel()
+        ws_ = {}
+
+        def make5():
+            views = [_d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
+                                  target=targets[i], d_step=dstep[i:i + 1], tf_index=0)
+                     for i in range(nv)]
+            b = _d.Batch([vol], [tf], views, _d.EMISSION_ABSORPTION, d_volumes=[dV],
+                         d_tfs=[dTF])
+            ws_["ws"] = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32,
+                                    device=dev)
+            return b
+
+        key = workload_key(_device_arch(), _d.EMISSION_ABSORPTION, "f16", w.tf.shape[0], W,
+                           w.volume.shape[0], "V+TF+step", _d.PASS_FUSED)
+        cands = []
+        for waves, cap, k, lm in itertools.product((2, 4), (4096, 5120, 6144, 7168), (32, 64),
+                                                   (0, 2)):
+            cands.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
+                          "cell_acc": 1, "lane_map": lm, "schedule": 0})
+        res = tune(key, make5, lambda b: b.run(_d.PASS_FUSED, scale, loss, workspace=ws_["ws"]),
+                   lambda: images, candidates=cands, reps=args.reps, verbose=True)
         print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
         return
     if args.workload == "color":

@@ -497,34 +497,41 @@ int validate_sphere(float yaw, float pitch, float dist, float fovy, int W, int H
 // ===========================================================================
 // C ABI
 // ===========================================================================
-// Samples of every tile of a view (host replay of the kernels' float32 ray
+// Samples of every tile of a view (host replay of the kernels' float64 ray
 // setup): the cost model of the longest-first tile queue and the exact sample
 // count of a batch.
 static std::vector<int64_t> tile_samples(const ViewDesc& d, int tw, int th) {
   std::vector<int64_t> cost((size_t)d.tiles_x * d.tiles_y, 0);
+  const int n3[3] = {d.nx, d.ny, d.nz};
+  const int nmax = std::max(d.nx, std::max(d.ny, d.nz));
+  double bmin[3];
+  for (int a = 0; a < 3; ++a) bmin[a] = -(double)(n3[a] - 1) / (double)(nmax - 1);
   for (int py = 0; py < d.H; ++py)
     for (int px = 0; px < d.W; ++px) {
-      const float u = 2.0f * ((float)px + 0.5f) / (float)d.W - 1.0f;
-      const float v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)d.H;
-      float w[3], om[3];
-      for (int a = 0; a < 3; ++a) w[a] = d.fwd[a] + u * d.right[a] + v * d.up[a];
-      const float wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-      if (!(wl > 0.0f)) continue;
+      const double u = 2.0 * ((double)px + 0.5) / (double)d.W - 1.0;
+      const double v = 1.0 - 2.0 * ((double)py + 0.5) / (double)d.H;
+      double w[3], om[3];
+      for (int a = 0; a < 3; ++a)
+        w[a] = (double)d.fwd[a] + u * (double)d.right[a] + v * (double)d.up[a];
+      const double wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+      if (!(wl > 0.0) || !(wl < INFINITY)) continue;
       for (int a = 0; a < 3; ++a) om[a] = w[a] / wl;
-      float tn = -INFINITY, tf = INFINITY;
+      double tn = -INFINITY, tf = INFINITY;
       bool ok = true;
       for (int a = 0; a < 3; ++a) {
-        if (om[a] == 0.0f) {
-          if (d.eye[a] < d.bmin[a] || d.eye[a] > d.bmax[a]) ok = false;
+        const double e = (double)d.eye[a];
+        if (om[a] == 0.0) {
+          if (e < bmin[a] || e > -bmin[a]) ok = false;
           continue;
         }
-        const float ta = (d.bmin[a] - d.eye[a]) / om[a], tb = (d.bmax[a] - d.eye[a]) / om[a];
+        const double ta = (bmin[a] - e) / om[a], tb = (-bmin[a] - e) / om[a];
         tn = std::max(tn, std::min(ta, tb));
         tf = std::min(tf, std::max(ta, tb));
       }
-      const float t0 = tn > 0.0f ? tn : 0.0f;
-      if (ok && tf > t0)
-        cost[(size_t)(py / th) * d.tiles_x + px / tw] += (int64_t)std::ceil((tf - t0) / d.step);
+      const double t0 = tn > 0.0 ? tn : 0.0;
+      if (ok && tf > t0 && (tf - t0) < 1e30)
+        cost[(size_t)(py / th) * d.tiles_x + px / tw] +=
+            (int64_t)std::min(std::ceil((tf - t0) / (double)d.step), (double)kMaxSamples);
     }
   return cost;
 }

@@ -11,10 +11,12 @@
 //     workgroup computes the bounding box of the grid cells its samples touch,
 //     stages that brick of the density grid into LDS (converted to float32)
 //     and, in the adjoint, accumulates the density gradient of the slab in an
-//     LDS brick with ds_add_f32 that is flushed once per slab with one global
-//     atomic per touched voxel (the paper accumulates per ray "on exit of the
-//     current cell", Sec. 4.4 implementation paragraph; the brick is the same
-//     idea at workgroup granularity);
+//     LDS brick of fixed-point integers (ds_add_u32; ds_add_u64 for
+//     emission-absorption), with a power-of-two scale per tile from a bound
+//     on every entry, flushed once per slab with one global float atomic per
+//     touched voxel (the paper accumulates per ray "on exit of the current
+//     cell", Sec. 4.4 implementation paragraph; the brick is the same idea at
+//     workgroup granularity);
 //   * the transfer function lives in LDS; its gradient is accumulated per ray
 //     in registers while the ray stays on one TF segment and flushed to an
 //     LDS table on segment change (Sec. 5.2 "adjoint-delayed"), then to global
@@ -98,47 +100,67 @@ struct RayG {
   int axis;      // slab plane that defines t0 (-1: t0 = 0)
 };
 
+// The ray's setup runs in float64 (a few dozen operations per ray, against
+// hundreds of samples): pixel coordinates, direction, box clip, entry point
+// and step in grid units are rounded to float32 once, so that a sample's
+// position carries ~1 ulp of error plus the march's own fmaf rounding.  In
+// float32 the entry point alone (eye ~300 voxels away, t0 from a division)
+// and the direction accumulated over the march lost ~1e-4 voxels, which
+// moves trilinear weights by as much.  The grid box is exact in float64:
+// h = 2/(nmax-1), b_min = -(n-1)/(nmax-1).
 __device__ __forceinline__ void setup_ray(const ViewDesc& vd, int px, int py, bool valid,
                                           RayG& r) {
-  r.u = 2.0f * ((float)px + 0.5f) / (float)vd.W - 1.0f;
-  r.v = 1.0f - 2.0f * ((float)py + 0.5f) / (float)vd.H;
-  float w[3];
+  const double u = 2.0 * ((double)px + 0.5) / (double)vd.W - 1.0;
+  const double v = 1.0 - 2.0 * ((double)py + 0.5) / (double)vd.H;
+  r.u = (float)u;
+  r.v = (float)v;
+  double w[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) w[a] = vd.fwd[a] + r.u * vd.right[a] + r.v * vd.up[a];
-  r.wlen = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  for (int a = 0; a < 3; ++a)
+    w[a] = (double)vd.fwd[a] + u * (double)vd.right[a] + v * (double)vd.up[a];
+  const double wl = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  r.wlen = (float)wl;
+  double om[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) r.om[a] = w[a] / r.wlen;
-  float tn = -INFINITY, tf = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    om[a] = w[a] / wl;
+    r.om[a] = (float)om[a];
+  }
+  const int n3[3] = {vd.nx, vd.ny, vd.nz};
+  const int nmax = max(vd.nx, max(vd.ny, vd.nz));
+  const double inv_h = 0.5 * (double)(nmax - 1);
+  double bmin[3];
+  double tn = -INFINITY, tf = INFINITY;
   int ax = -1;
   bool ok = valid;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float o = r.om[a], e = vd.eye[a];
-    if (o == 0.0f) {
-      if (e < vd.bmin[a] || e > vd.bmax[a]) ok = false;
+    bmin[a] = -(double)(n3[a] - 1) / (double)(nmax - 1);
+    const double e = (double)vd.eye[a], o = om[a];
+    if (o == 0.0) {
+      if (e < bmin[a] || e > -bmin[a]) ok = false;
       continue;
     }
-    const float ta = (vd.bmin[a] - e) / o, tb = (vd.bmax[a] - e) / o;
-    const float lo = fminf(ta, tb), hi = fmaxf(ta, tb);
+    const double ta = (bmin[a] - e) / o, tb = (-bmin[a] - e) / o;
+    const double lo = fmin(ta, tb), hi = fmax(ta, tb);
     if (lo > tn) { tn = lo; ax = a; }
-    tf = fminf(tf, hi);
+    tf = fmin(tf, hi);
   }
-  float t0 = tn;
-  if (!(tn > 0.0f)) { t0 = 0.0f; ax = -1; }
-  r.t0 = t0;
+  double t0 = tn;
+  if (!(tn > 0.0)) { t0 = 0.0; ax = -1; }
+  r.t0 = (float)t0;
   r.axis = ax;
   r.N = 0;
   // a degenerate frame (zero or non-finite direction) yields no samples
-  if (!(r.wlen > 0.0f) || !(r.wlen < INFINITY)) ok = false;
-  if (ok && tf > t0 && (tf - t0) < 1e30f) {
-    const float n = ceilf((tf - t0) / vd.step);
-    r.N = (int)fminf(n, (float)kMaxSamples);
+  if (!(wl > 0.0) || !(wl < INFINITY)) ok = false;
+  if (ok && tf > t0 && (tf - t0) < 1e30) {
+    const double n = ceil((tf - t0) / (double)vd.step);
+    r.N = (int)fmin(n, (double)kMaxSamples);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float x = vd.eye[a] + t0 * r.om[a];
-    r.qo[a] = (x - vd.bmin[a]) * vd.inv_h;
-    r.dq[a] = vd.step * r.om[a] * vd.inv_h;
+    r.qo[a] = (float)(((double)vd.eye[a] + t0 * om[a] - bmin[a]) * inv_h);
+    r.dq[a] = (float)((double)vd.step * om[a] * inv_h);
   }
 }
 
@@ -625,6 +647,143 @@ __device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int
 }
 
 // ---------------------------------------------------------------------------
+// Absorption-only runs.  The samples of a ray inside one grid cell, x_i =
+// x_o + i dt omega for i in [i0, i1), see one trilinear polynomial: along
+// them the density, and every corner's trilinear weight, is a cubic in i
+// whose odd central moments about the run's midpoint mu = (i0 + i1 - 1)/2
+// vanish.  So the run's sum of densities, the sum Alg. 1 accumulates for
+// tau = d, is m (d(mu) + (s2/2) d''), with m = i1 - i0, s2 = (m^2 - 1)/12 the
+// mean squared distance of the indices from mu and d'' the second derivative
+// along the ray per sample; the same holds for the sum of each corner's
+// weight that the adjoint scatters (its d_hat is the same for every sample of
+// a ray).  The numbers are the per-sample sums of Alg. 1 / Alg. 2, computed
+// once per cell instead of once per sample.
+// ---------------------------------------------------------------------------
+struct RunGeo {
+  float inv_dq[3];       // 1/dq per axis (1e30 where dq = 0: no boundary)
+  float up[3];           // 1 if the ray moves up the axis (or not at all), else 0
+  float dxy, dxz, dyz;   // products of the per-sample steps of two axes
+};
+
+__device__ __forceinline__ void run_geo(const ViewDesc& vd, const RayG& r, RunGeo& g) {
+  (void)vd;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g.inv_dq[a] = r.dq[a] != 0.0f ? 1.0f / r.dq[a] : 1e30f;
+    g.up[a] = r.dq[a] >= 0.0f ? 1.0f : 0.0f;
+  }
+  g.dxy = r.dq[0] * r.dq[1];
+  g.dxz = r.dq[0] * r.dq[2];
+  g.dyz = r.dq[1] * r.dq[2];
+}
+
+// Cell of sample fi (k as float and as int): the clamp of locate, without the
+// fraction.
+__device__ __forceinline__ void locate_cell(const RayG& r, float fi, const ViewDesc& vd,
+                                            Cell& c, float* kf) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = __builtin_amdgcn_fmed3f(fmaf(fi, r.dq[a], r.qo[a]), 0.0f, vd.qhi[a]);
+    kf[a] = floorf(q);
+    c.k[a] = (int)kf[a];
+  }
+}
+
+// One past the last sample of [fi, fb) in the cell kf of sample fi, at least
+// fi + 1: the first index at or past the next cell face along each axis,
+// ceil((k + up - q_o)/dq).  Float rounding can move a boundary by one sample
+// (that sample is then evaluated with the neighbouring cell's polynomial a
+// hair outside [0, 1], where the trilinear interpolant is continuous, or
+// starts a run of its own); the box faces end the ray anyway.
+__device__ __forceinline__ float run_end(const RayG& r, const RunGeo& g, const float* kf,
+                                         float fi, float fb) {
+  float e = fb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) e = fminf(e, ceilf((kf[a] + g.up[a] - r.qo[a]) * g.inv_dq[a]));
+  return fmaxf(e, fi + 1.0f);
+}
+
+// Cell-local coordinates of the run's midpoint (not clamped: within rounding
+// of [0, 1]).  The fma rounds mu dq + (q_o - k) once at the scale of the
+// result (<= 1) instead of at the scale of the position (up to n); q_o - k is
+// exact when k <= q_o (Sterbenz) and otherwise rounds at the scale of k.
+__device__ __forceinline__ void run_mid(const RayG& r, const float* kf, float mu, float* f) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f[a] = fmaf(mu, r.dq[a], r.qo[a] - kf[a]);
+}
+
+// Sum of the densities of an absorption-only run: m (d(mu) + s2/2 d''), with
+// d'' = 2 (dxy d_xy + dxz d_xz + dyz d_yz), d_ab the mixed derivatives of the
+// trilinear interpolant at the midpoint.
+__device__ __forceinline__ float run_density_sum(const float* v, const float* f, float m,
+                                                 const RunGeo& g) {
+  const float x0 = v[1] - v[0], x1 = v[3] - v[2], x2 = v[5] - v[4], x3 = v[7] - v[6];
+  const float c00 = fmaf(f[0], x0, v[0]);
+  const float c10 = fmaf(f[0], x1, v[2]);
+  const float c01 = fmaf(f[0], x2, v[4]);
+  const float c11 = fmaf(f[0], x3, v[6]);
+  const float c0 = fmaf(f[1], c10 - c00, c00);
+  const float c1 = fmaf(f[1], c11 - c01, c01);
+  const float d = fmaf(f[2], c1 - c0, c0);
+  const float dxy0 = x1 - x0, dxy1 = x3 - x2;
+  const float d_xy = fmaf(f[2], dxy1 - dxy0, dxy0);
+  const float dxz0 = x2 - x0, dxz1 = x3 - x1;
+  const float d_xz = fmaf(f[1], dxz1 - dxz0, dxz0);
+  const float d_yz = (c11 - c01) - (c10 - c00);
+  const float curv = fmaf(g.dxy, d_xy, fmaf(g.dxz, d_xz, g.dyz * d_yz));
+  const float s2 = (m * m - 1.0f) * (1.0f / 12.0f);
+  return m * fmaf(s2, curv, d);
+}
+
+// Sums over an absorption-only run of the 8 corner weights, w (index cx + 2cy
+// + 4cz) = m (w_c(mu) + s2 (sx sy dxy z_c + sx sz dxz y_c + sy sz dyz x_c)),
+// with x_c, y_c, z_c the corner's linear factors at mu and s = +1 for the
+// upper corner of an axis, -1 for the lower; times `scale`.
+__device__ __forceinline__ void run_weight_sums(const float* f, float m, const RunGeo& g,
+                                                float scale, float* w) {
+  const float s2 = (m * m - 1.0f) * (1.0f / 12.0f);
+  const float exy = s2 * g.dxy, exz = s2 * g.dxz, eyz = s2 * g.dyz;
+  const float X[2] = {1.0f - f[0], f[0]}, Y[2] = {1.0f - f[1], f[1]}, Z[2] = {1.0f - f[2], f[2]};
+  const float sc = m * scale;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int cx = k & 1, cy = (k >> 1) & 1, cz = k >> 2;
+    const float sxy = (cx == cy) ? 1.0f : -1.0f, sxz = (cx == cz) ? 1.0f : -1.0f,
+                syz = (cy == cz) ? 1.0f : -1.0f;
+    const float yz = Y[cy] * Z[cz];
+    float t = X[cx] * yz;
+    t = fmaf(sxy * exy, Z[cz], t);
+    t = fmaf(sxz * exz, Y[cy], t);
+    t = fmaf(syz * eyz, X[cx], t);
+    w[k] = t * sc;
+  }
+}
+
+// Forward of samples [a, b) of an absorption-only ray, one cell run at a time
+// (LDS: corners from the staged brick; else gathered from the grid).
+template <int DT, bool LDS>
+__device__ __forceinline__ void march_fwd_ao_runs(const ViewDesc& vd, const RayG& r,
+                                                  const RunGeo& g, int a, int b,
+                                                  const float* stage, const Brick& br,
+                                                  FwdState& s) {
+  const float fb = (float)b;
+  for (float fi = (float)a; fi < fb;) {
+    Cell c;
+    float kf[3];
+    locate_cell(r, fi, vd, c, kf);
+    const float fe = run_end(r, g, kf, fi, fb);
+    const float m = fe - fi;
+    float f[3];
+    run_mid(r, kf, fmaf(0.5f, m - 1.0f, fi), f);
+    float v[8];
+    if (LDS) fetch_lds(stage, br, brick_base(br, c), v);
+    else fetch_global<DT>(vd, c, v);
+    s.sigma += run_density_sum(v, f, m, g);
+    fi = fe;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-ray adjoint state and per-sample adjoint (Alg. 2 body)
 // ---------------------------------------------------------------------------
 struct AdjState {
@@ -855,6 +1014,29 @@ __device__ __forceinline__ void march_adj(const ViewDesc& vd, const RayG& r, int
   if (cell_acc) cell_flush<LDS, FIX, WIDE>(vd, br, acc, s);   // the brick changes with the slab
 }
 
+// Absorption-only closed form (d_hat = dt T_N ahat for every sample) of
+// samples [a, b) with the density gradient only: one cell run at a time, its 8
+// corner weight sums times d_hat added to the LDS brick in fixed point (dhq =
+// d_hat qs).  The order of the runs does not matter: they march front to back.
+__device__ __forceinline__ void march_adj_ao_runs(const ViewDesc& vd, const RayG& r,
+                                                  const RunGeo& g, int a, int b, float* acc,
+                                                  const Brick& br, const AdjState& s) {
+  const float fb = (float)b;
+  for (float fi = (float)a; fi < fb;) {
+    Cell c;
+    float kf[3];
+    locate_cell(r, fi, vd, c, kf);
+    const float fe = run_end(r, g, kf, fi, fb);
+    const float m = fe - fi;
+    float f[3];
+    run_mid(r, kf, fmaf(0.5f, m - 1.0f, fi), f);
+    float w[8];
+    run_weight_sums(f, m, g, s.dhq, w);
+    lds_add8<true>(acc, br, brick_base(br, c), w);
+    fi = fe;
+  }
+}
+
 // Camera adjoint of one ray (last line of Alg. 2 on [x_o_hat; omega_hat]).
 // out[0..11] = d frame, out[12] = d step.
 __device__ __forceinline__ void camera_adjoint(const ViewDesc& vd, const RayG& r,
@@ -971,6 +1153,8 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   RayG r;
   setup_ray(vd, px, py, valid, r);
   bool hit = r.N > 0;
+  RunGeo rg;
+  if (MODEL == DDVR_ABSORPTION) run_geo(vd, r, rg);
 
   // slab bookkeeping (shared by both passes): sample offsets relative to the
   // earliest entry point of the tile
@@ -1008,9 +1192,15 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
       if (st == 1) {
         stage_brick<NT, DT>(vd, br, stage, nullptr);
         __syncthreads();
-        march_fwd<MODEL, DT, true>(vd, r, a, b, stage, br, tfl, fs);
+        if (MODEL == DDVR_ABSORPTION) march_fwd_ao_runs<DT, true>(vd, r, rg, a, b, stage, br, fs);
+        else march_fwd<MODEL, DT, true>(vd, r, a, b, stage, br, tfl, fs);
       } else if (st == 2) {
-        march_fwd<MODEL, DT, false>(vd, r, a, b, stage, br, tfl, fs);
+        // (a launch without bricks -- PLAIN, the per-sample baseline -- keeps
+        // the per-sample march)
+        if (MODEL == DDVR_ABSORPTION && cap > 0)
+          march_fwd_ao_runs<DT, false>(vd, r, rg, a, b, stage, br, fs);
+        else
+          march_fwd<MODEL, DT, false>(vd, r, a, b, stage, br, tfl, fs);
       }
       pos = hi;
     }
@@ -1047,21 +1237,37 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   // Fused pass with different lane maps: hand each ray's T_N and upstream
   // gradient over to the lane that runs its adjoint, through the (now idle)
   // staging region, and set that lane's ray up again.
-  if (PASS == PASS_FUSED && il_adj != il_fwd && cap >= (C + 1) * NT) {
+  // The ray itself travels along: its float64 setup is not repeated (that
+  // would keep float64 temporaries live next to the forward's results).  The
+  // hand-over needs (C + 1 + RAYW) words per lane of the (idle) brick regions;
+  // with less, the adjoint keeps the forward's lane map.
+  constexpr int RAYW = (int)(sizeof(RayG) / sizeof(float));
+  const int hand_words = (p.lds_two ? 1 + ACCW : 1) * cap;
+  if (PASS == PASS_FUSED && il_adj != il_fwd && hand_words >= (C + 1 + RAYW) * NT) {
     __syncthreads();                       // the forward's last brick reads are done
     const int lp = ly * TW + lx;
     stage[lp] = TN;
     for (int ch = 0; ch < C; ++ch) stage[(ch + 1) * NT + lp] = gimg[ch];
+    {
+      const float* rw = reinterpret_cast<const float*>(&r);
+#pragma unroll
+      for (int k = 0; k < RAYW; ++k) stage[(C + 1 + k) * NT + lp] = rw[k];
+    }
     __syncthreads();
     tile_pixel<WAVES>(il_adj, wid, lane, lx, ly);
     const int lq = ly * TW + lx;
     TN = stage[lq];
     for (int ch = 0; ch < C; ++ch) gimg[ch] = stage[(ch + 1) * NT + lq];
+    {
+      float* rw = reinterpret_cast<float*>(&r);
+#pragma unroll
+      for (int k = 0; k < RAYW; ++k) rw[k] = stage[(C + 1 + k) * NT + lq];
+    }
     px = tx * TW + lx;
     py = ty * TH + ly;
     valid = px < vd.W && py < vd.H;
     pix = (int64_t)py * vd.W + px;
-    setup_ray(vd, px, py, valid, r);
+    if (MODEL == DDVR_ABSORPTION) run_geo(vd, r, rg);
     hit = r.N > 0;
     off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
     // the staging region is next written after the adjoint's first brick
@@ -1228,7 +1434,9 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     if (st == 1) {
       stage_brick<NT, DT, EA>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
-      if (use_fix)
+      if (use_fix && !EA && !XH && want_dv)
+        march_adj_ao_runs(vd, r, rg, a, b, acc, br, s);
+      else if (use_fix)
         march_adj<MODEL, DT, true, 0, XH>(vd, r, a, b, stage, acc, br, tfl, dtf, gmask, need_v,
                                       p.cell_acc, s);
       else if (mode == DDVR_ADJ_INVERT_ALPHA)

@@ -1,18 +1,13 @@
-"""Per-sample VALU instruction counts of the render kernels' inner loops, read
-from the gfx950 assembly of the current source (the ALU-roofline figure of
-the benchmark).
+"""VALU instruction counts of the render kernels' inner loops, read from the
+gfx950 assembly of the current source (a cross-check of the measured
+counters).
 
     python -m paper_2107_12672_amd.isa_count [--write]
 
 Compiles ``csrc/ddvr_kernels.hip`` with the library's flags to device
-assembly and counts, for the absorption-only bf16 4-wave kernels:
-  * forward: every VALU instruction of the innermost loop that gathers the
-    8 corners from the LDS brick (four ds_read2_b32) -- one sample;
-  * adjoint (closed form, fixed-point brick): every VALU instruction of the
-    innermost loop that adds to the LDS brick (ds_add_u32) without an
-    exponential (the inversion loops have one), except the basic
-    blocks that do the adding (the cell-exit flush, taken only when a ray
-    leaves its cell) -- one sample, plus the flush block counted separately.
+assembly and counts, for the absorption-only bf16 4-wave kernels, the VALU
+instructions of one iteration of the forward's and of the closed-form
+adjoint's cell-run loops (one run = the samples of a ray inside one cell).
 It also counts, in ``csrc/ddvr_dfc.hip``, the VALU instructions of the
 density-from-colour candidate loop (bf16 colour volume): one candidate.
 ``--write`` stores the counts with the source hashes in
@@ -109,31 +104,29 @@ def _inner(lines):
 
 
 def count(asm: str) -> dict:
-    fwd = None
+    """Absorption-only bf16 kernels: the forward marches one cell run per
+    iteration (the innermost loop with the four ds_read2_b32 of a cell's
+    corners from the brick), the fused kernel's closed-form adjoint one run per
+    iteration (the innermost loop that adds 8 corner sums to the brick,
+    ds_add_u32, and finds the run's end with ceil/floor, without an
+    exponential: the inversion loops have one)."""
+    fwd = adj = None
     for blocks in _inner(_kernel(asm, FWD)).values():
         ins = [x for _, blk in blocks for x in blk]
         if ins.count("ds_read2_b32") == 4:
             fwd = sum(1 for x in ins if x.startswith("v_"))
             break
-    adj = flush = None
     for blocks in _inner(_kernel(asm, FUSED)).values():
-        adders = [blk for _, blk in blocks if "ds_add_u32" in blk]
-        if not adders:
+        ins = [x for _, blk in blocks for x in blk]
+        if ins.count("ds_add_u32") != 8 or any(x.startswith("v_exp_f32") for x in ins):
             continue
-        # the closed form's loop: the inversion loops of the same kernel (T-
-        # and alpha-form) also add to the brick but recompute exp(-dt tau)
-        if any(x.startswith("v_exp_f32") for _, blk in blocks for x in blk):
+        if not any(x.startswith(("v_ceil_f32", "v_floor_f32")) for x in ins):
             continue
-        common = [x for _, blk in blocks if "ds_add_u32" not in blk for x in blk]
-        adj = sum(1 for x in common if x.startswith("v_"))
-        # the cell-exit flush is the smaller adding block (the per-sample
-        # variant, not taken with per-cell accumulation, computes weights too)
-        flush = min(sum(1 for x in blk if x.startswith("v_")) for blk in adders)
+        adj = sum(1 for x in ins if x.startswith("v_"))
         break
     if fwd is None or adj is None:
-        raise RuntimeError("inner loops not found in the assembly")
-    return {"forward_valu_per_sample": fwd, "adjoint_valu_per_sample": adj,
-            "adjoint_cell_exit_flush_valu": flush}
+        raise RuntimeError("run loops not found in the assembly")
+    return {"forward_valu_per_run": fwd, "adjoint_valu_per_run": adj}
 
 
 def count_dfc(asm: str) -> dict:

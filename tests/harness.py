@@ -220,28 +220,40 @@ def sensitive_mask(p: Problem, pix, g, rel=1e-7, thresh=1e-3, trials=3, seed=0):
     return out
 
 
-def screen_camera_rays(p: Problem, pix, g, rel=1e-7, trials=3, frac=0.1, seed=0):
+def camera_bounds(per_ray):
+    """Element-wise bounds of a sum over rays of camera-frame (12) and step (1)
+    gradients, per_ray [n][13]: 1e-3 max(|o_k|, 1e-2 max_j |o_j|) for the frame
+    entries (the floor: a hundredth of the gradient's scale), and for the step
+    1e-3 max(|o_step|, 1e-2 sum_r |b_r,step|) -- a scalar's scale is the size of
+    the terms it sums, which cancel in the sum."""
+    o = per_ray.sum(axis=0)
+    bound = np.empty(13)
+    bound[:12] = 1e-3 * np.maximum(np.abs(o[:12]), 1e-2 * np.abs(o[:12]).max())
+    bound[12] = 1e-3 * max(abs(o[12]), 1e-2 * float(np.abs(per_ray[:, 12]).sum()))
+    return bound
+
+
+def screen_camera_rays(p: Problem, pix, g, rel=1e-7, trials=3, seed=0):
     """Rays to leave out of an element-wise camera / step comparison.
 
     Each ray's float64 camera-frame and step gradients are recomputed at
     frames and steps perturbed by `rel` relative (the size of float32 rounding
-    of the inputs); a ray is screened when its own movement on any entry
-    exceeds `frac` of the element-wise bound of the SUM over the kept rays
-    (1e-3 max(|o_k|, 1e-2 max|o_cam|); 1e-3 |o_step| for the step).  The bound
-    depends on the kept set, so the screen is repeated until it is stable.
-    Returns (mask of screened rays, per-ray sensitivities [n][13])."""
+    of the inputs); a ray is screened when its own movement on the entries
+    would push the kept rays' summed movements past 0.3 of an entry's bound
+    for the sum over the kept rays (camera_bounds): the most sensitive ray is
+    dropped until they fit (at least a fifth of the seeded rays are kept).
+    Returns (mask of screened rays, per-ray gradients [n][13])."""
     V = dequantized(p)
     cam = oracle_camera(p)
     rng = np.random.default_rng(seed)
     n = len(pix)
     base = np.zeros((n, 13))
     sens = np.zeros((n, 13))
+    seeded = np.array([bool(np.any(g[q])) for q in range(n)])
     pert = [(cam * (1.0 + rel * rng.normal(size=12)), p.step * (1.0 + rel * rng.normal()))
             for _ in range(trials)]
-    for q in range(n):
+    for q in np.nonzero(seeded)[0]:
         gq = g[q:q + 1]
-        if not np.any(gq):
-            continue
         a = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, gq, pix=pix[q:q + 1],
                            want_dV=False)
         base[q] = np.r_[a["dcam"], a["dstep"]]
@@ -249,33 +261,34 @@ def screen_camera_rays(p: Problem, pix, g, rel=1e-7, trials=3, frac=0.1, seed=0)
             b = oracle.adjoint(V, p.tf, pc, p.W, p.H, ps, p.model, gq, pix=pix[q:q + 1],
                                want_dV=False)
             sens[q] = np.maximum(sens[q], np.abs(np.r_[b["dcam"], b["dstep"]] - base[q]))
-    screened = np.zeros(n, dtype=bool)
-    for _ in range(10):
-        o = base[~screened].sum(axis=0)
-        bound = np.empty(13)
-        bound[:12] = 1e-3 * np.maximum(np.abs(o[:12]), 1e-2 * np.abs(o[:12]).max())
-        bound[12] = 1e-3 * abs(o[12])
-        new = screened | np.any(sens > frac * bound[None, :], axis=1)
-        if np.array_equal(new, screened):
+    # drop the most sensitive ray until the kept rays' sensitivities, added up,
+    # stay inside 0.3 of every entry's bound (keeping at least a fifth)
+    screened = ~seeded
+    while True:
+        kept = ~screened
+        bound = np.maximum(camera_bounds(base[kept]), 1e-300)
+        share = sens / bound[None, :]
+        if share[kept].sum(axis=0).max() <= 0.3 or kept.sum() <= max(1, seeded.sum() // 5):
             break
-        screened = new
-    return screened, sens
+        worst = np.where(kept, share.max(axis=1), -1.0)
+        screened[int(np.argmax(worst))] = True
+    screened &= seeded
+    return screened, base
 
 
-def oracle_spread(p: Problem, pix, g, rel=1e-7, trials=3, seed=1):
+def oracle_spread(p: Problem, pix, g, rel=1e-7, trials=3, seed=1, per_ray=None):
     """Relative spread of the oracle's camera (norm-wise) and step gradients
     when the camera frame and the step are perturbed by `rel` relative (float32
     rounding of the inputs).  Returns (cam_spread, step_spread, elem): elem is
     the largest movement of any of the 13 entries (frame, step) as a fraction
-    of its element-wise bound (1e-3 max(|o_k|, 1e-2 max|o_cam|); 1e-3 |o_step|)."""
+    of its element-wise bound (camera_bounds of the per-ray gradients
+    `per_ray`, [n][13], if given)."""
     V = dequantized(p)
     cam = oracle_camera(p)
     rng = np.random.default_rng(seed)
     base = oracle.adjoint(V, p.tf, cam, p.W, p.H, p.step, p.model, g, pix=pix, want_dV=False)
     o = np.r_[base["dcam"], base["dstep"]]
-    bound = np.empty(13)
-    bound[:12] = 1e-3 * np.maximum(np.abs(o[:12]), 1e-2 * np.abs(o[:12]).max())
-    bound[12] = 1e-3 * abs(o[12])
+    bound = camera_bounds(o[None, :]) if per_ray is None else camera_bounds(per_ray)
     cs = ss = el = 0.0
     for _ in range(trials):
         a = oracle.adjoint(V, p.tf, cam * (1.0 + rel * rng.normal(size=12)), p.W, p.H,

@@ -61,6 +61,10 @@ def test_c1_forward_matches_oracle(flags):
 
 
 def test_forward_is_bitwise_identical_with_and_without_lds_staging():
+    """Emission-absorption: the staged and the plain launch run the same
+    per-sample arithmetic, bit for bit.  Absorption-only: the staged launch
+    sums each cell's run of samples in closed form, the plain one sample by
+    sample -- the same sum up to float32 rounding."""
     p = ea_problem()
     _say("EA forward staged vs plain")
     a, ta = gpu_forward(p, 0)
@@ -69,7 +73,7 @@ def test_forward_is_bitwise_identical_with_and_without_lds_staging():
     p, _ = c1_problem()
     a, ta = gpu_forward(p, 0)
     b, tb = gpu_forward(p, PLAIN)
-    assert np.array_equal(a, b) and np.array_equal(ta, tb)
+    assert np.abs(a - b).max() <= 1e-6 and np.abs(ta - tb).max() <= 1e-6
 
 
 @pytest.mark.parametrize("flags", [0, PLAIN, 1, 2, 3])

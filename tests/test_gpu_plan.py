@@ -60,7 +60,8 @@ def test_entropy_plan_replays_equal_the_eager_step():
     oe = torch.zeros(n, dtype=torch.float64, device="cuda")
     for k in range(n):
         gs[k].zero_()
-        d.opacity_entropy(imgs[k].view(-1, 4), work[k], oe[k:k + 1], gs[k], scale=-0.5)
+        d.opacity_entropy(imgs[k].view(probs[k].H, probs[k].W, 4), work[k], oe[k:k + 1],
+                          gs[k], scale=-0.5)
     b.run(d.PASS_ADJOINT, workspace=ws)
     torch.cuda.synchronize()
     ref = ([t.clone() for t in imgs], [t.clone() for t in gs], dcam.clone(), dstep.clone(),

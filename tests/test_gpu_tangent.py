@@ -101,7 +101,12 @@ def test_tangent_images_match_oracle_dual_numbers(which, flags):
     for chunk in (dirs[:4], dirs[4:]):          # 4 directions, then 1 (two instantiations)
         img, dot, _ = _gpu_tangent(p, chunk, flags)
         fwd, _ = gpu_forward(p, flags)
-        assert np.array_equal(img, fwd), "the tangent pass must render the forward's image"
+        if which == "ea":
+            assert np.array_equal(img, fwd), "the tangent pass must render the forward's image"
+        else:
+            # the absorption-only forward sums each cell's run of samples in
+            # closed form, the tangent pass sample by sample
+            assert np.abs(img - fwd).max() <= 1e-6
         for k, direction in enumerate(chunk):
             ref = _oracle_dot(p, direction)
             ok = keep & ~_unstable(p, direction, ref)

@@ -45,12 +45,15 @@ def _run(p, flags, noalloc):
 
 
 def _same(a, b, what):
+    """The same kernels on the same inputs: equal up to the order of float
+    atomics (density 1e-5 norm-wise; TF, camera and step entries 1e-4 of
+    max(|x|, 1e-2 of the array's scale), inside the 1e-3 parity bound)."""
     assert a[0] == b[0] and a[0] > 0, (what, a[0], b[0])      # the fallback ran
     assert_dv_close(a[1], b[1], f"{what} dV", 1e-5)
     if a[2] is not None:
-        assert_grad_close(a[2], b[2], f"{what} dTF", 1e-5)
-    assert_grad_close(a[3], b[3], f"{what} dcam", 1e-5)
-    assert_grad_close([a[4]], [b[4]], f"{what} dstep", 1e-5)
+        assert_grad_close(a[2], b[2], f"{what} dTF", 1e-4)
+    assert_grad_close(a[3], b[3], f"{what} dcam", 1e-4)
+    assert_grad_close([a[4]], [b[4]], f"{what} dstep", 1e-4)
 
 
 def test_noalloc_adjoint_equals_the_workspace_adjoint_twice():
