@@ -107,7 +107,10 @@ def tune(key: str, make_batch: Callable[[], "object"], run: Callable[["object"],
 
     make_batch() builds a fresh batch under the current tuning; run(batch)
     enqueues one pass on torch's current stream; images() returns a tensor of
-    the rendered images (compared bitwise across candidates)."""
+    the rendered images, compared across candidates: a launch shape may change
+    only the grouping of float32 sums (absorption-only cell runs end at slab
+    boundaries, which depend on the tile and brick size), so they must agree to
+    1e-5 of the largest value."""
     import torch
     old = _d.get_tuning()
     results = []
@@ -124,7 +127,7 @@ def tune(key: str, make_batch: Callable[[], "object"], run: Callable[["object"],
             img = images().clone()
             if ref is None:
                 ref = img
-            elif not torch.equal(img, ref):
+            elif not bool((img - ref).abs().max() <= 1e-5 * max(1.0, float(ref.abs().max()))):
                 raise RuntimeError(f"launch shape {cand} changed the rendered images")
             a = torch.cuda.Event(enable_timing=True)
             z = torch.cuda.Event(enable_timing=True)
