@@ -311,8 +311,18 @@ def secondary(args):
                     "config": {"workload": w.name + ", fused L2, density gradient",
                                "samples_per_step": S, "single_call_ms": ms_single,
                                "launch": "one fused launch, HIP graph replay"}})
-    elif args.workload in ("c2", "c5"):
-        w = synth.make_c2() if args.workload == "c2" else synth.make_c5()
+    elif args.workload == "c5":
+        res = inversion_c5(d, torch, args, stream)
+        out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
+                    "value": res["auto"]["value"], "ms_per_step": res["auto"]["ms_per_step"],
+                    "config": {"workload": res["workload"],
+                               "samples_per_step": res["auto"]["samples_per_step"],
+                               "tuning": res["tuning"], "tuning_source": res["tuning_source"]},
+                    "auto": res["auto"]})
+        if "checkpoint" in res:
+            out["checkpoint"] = res["checkpoint"]
+    elif args.workload == "c2":
+        w = synth.make_c2()
         vol = stored(w.volume, w.storage)
         tf = torch.from_numpy(w.tf).to(dev)
         cams = cams_of(w.views)
@@ -337,13 +347,10 @@ def secondary(args):
         loss = torch.zeros(1, dtype=torch.float64, device=dev)
         scale = 1.0 / images.numel()
         res = {}
-        for mode, flags in (("auto", 0), ("checkpoint", 3)):
-            if flags and (args.workload == "c2" or args.c5_checkpoint <= 0):
-                continue
+        for mode, flags in (("auto", 0),):
             views = [d.make_view(0, cams[i], w.step_world, images[i], transmittance=trans[i],
                                  target=targets[i], d_step=dstep[i:i + 1], tf_index=0,
-                                 d_camera=dcam[i] if args.workload == "c2" else None)
-                     for i in range(nv)]
+                                 d_camera=dcam[i]) for i in range(nv)]
             b = d.Batch([vol], [tf], views, d.EMISSION_ABSORPTION, flags=flags,
                         d_volumes=[dV], d_tfs=[dTF])
             ws = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32, device=dev)
@@ -355,13 +362,9 @@ def secondary(args):
             b.close()
         out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
                     "value": res["auto"]["value"], "ms_per_step": res["auto"]["ms_per_step"],
-                    "config": {"workload": w.name + (", gradients density+TF+camera+step"
-                                                     if args.workload == "c2" else
-                                                     ", gradients density+TF+step"),
+                    "config": {"workload": w.name + ", gradients density+TF+camera+step",
                                "samples_per_step": res["auto"]["samples_per_step"],
                                "tuning": d.get_tuning()}})
-        if "checkpoint" in res:
-            out["checkpoint"] = res["checkpoint"]
     elif args.workload == "color":
         w = synth.make_color()
         vol = stored(w.volume, w.storage)
@@ -415,26 +418,34 @@ def secondary(args):
         log(f"color batched (one launch, graph): {b_ms:.3f} ms, {S / (b_ms * 1e-3):.4g} "
             f"ray-samples/s")
         res["batched"] = {"ms_per_step": b_ms, "value": S / (b_ms * 1e-3)}
-        # HBM roofline of the batched launch on algorithmic bytes: per sample pair
-        # 8 corner gathers of 4 channels in the forward and again in the adjoint,
-        # and 8 x 4 float32 gradient scatters (the LDS bricks serve most of them)
+        # The batched launch against HBM on its measured DRAM bytes (rocprofv3
+        # FETCH_SIZE + WRITE_SIZE, committed with the kernel source's hash).
+        # Algorithmic bytes per sample pair (8 corner gathers of 4 bf16 channels
+        # in the forward and again in the adjoint, 8 x 4 float32 gradient
+        # scatters) over the launch are a gather/scatter rate that the LDS
+        # bricks serve, reported beside it, not against the HBM peak.
         alg = S * (2 * 8 * 4 * 2 + 8 * 4 * 4)
-        gbs = alg / (b_ms * 1e-3) / 1e9
+        c = counters_record("k_color_lds_bf16_fused_color", b_ms)
         tr = None
-        try:
-            with open(os.path.join(ROOT, "profiles", "traffic_color_batched.json")) as f:
-                t = json.load(f)
-            if t.get("kernel_source_sha") == kernel_source_hash():
-                tr = t.get("bytes_per_launch")
-        except (OSError, ValueError):
-            pass
-        out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr,
+        t = load_counters("k_color_lds_bf16_fused_color")
+        if t:
+            tr = t.get("dram_bytes_per_launch")
+        out["roofline"] = {"bound": "hbm", "achieved": c.get("dram_gbs"), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": c.get("dram_frac"), "traffic": tr,
                            "kernel": "k_color_lds<bf16, fused> (64 views, one launch)",
-                           "kernel_ms": round(b_ms, 4), "alg_bytes_per_launch": alg,
-                           "note": "algorithmic bytes (256 per sample pair, bf16): LDS bricks "
-                                   "serve the forward gathers and absorb the scatters; the "
-                                   "adjoint's global float atomics bound it"}
+                           "kernel_ms": round(b_ms, 4),
+                           "counters": c.get("counters"),
+                           "note": "DRAM bytes of the launch (rocprofv3, copy-calibrated) over "
+                                   "its event-timed duration; the adjoint's device-scope float "
+                                   "atomics, carried out past the per-XCD L2, are most of them"}
+        if t:
+            out["roofline"]["valu_frac"] = c.get("valu_frac")
+            out["roofline"]["atomic_requests_per_launch"] = t.get("counters", {}).get(
+                "TCC_EA0_ATOMIC_sum")
+        out["lds_gather_rate"] = {"achieved": round(alg / (b_ms * 1e-3) / 1e9, 1),
+                                  "unit": "GB/s", "alg_bytes_per_launch": alg,
+                                  "note": "algorithmic bytes (256 per sample pair) over the "
+                                          "launch, served by the LDS bricks: not HBM traffic"}
         if not getattr(args, "no_cpu_baseline", False):
             out["cpu_baseline"] = cpu_baseline_color(w, w.volume)
             log(f"cpu baseline: {out['cpu_baseline']}")
