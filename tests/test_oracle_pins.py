@@ -713,3 +713,38 @@ def test_resample_reproduces_affine_fields_and_matches_trilinear():
     for (k, j, i) in [(0, 0, 0), (7, 8, 6), (3, 4, 2), (5, 1, 6), (2, 7, 3)]:
         q = np.array([i * 5 / 6, j * 3 / 8, k * 4 / 7])       # input grid units (x, y, z)
         assert out[k, j, i] == pytest.approx(oracle.trilinear(W, bmin + q * h), abs=1e-12)
+
+
+def test_kink_distances_match_a_recomputation_on_an_affine_grid():
+    """oracle.kinks (the parity harness's mask of non-differentiable points)
+    against numpy: sample positions from trace_ray (pinned above), the density
+    of an affine grid in closed form, the distance of each sample to the
+    nearest interior cell face (faces 1..n-2 of each axis) and of d (R-1) to
+    the nearest TF knot 0..R-1; rays that miss report 1e30."""
+    n, R = 9, 6
+    h, bmin = 2.0 / (n - 1), -1.0
+    c0, c = 0.5, np.array([0.2, 0.1, -0.15])            # d = c0 + c . x, inside [0, 1]
+    ax = bmin + h * np.arange(n)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    V = c0 + c[0] * X + c[1] * Y + c[2] * Z
+    tf = synth.random_tf(R, np.random.default_rng(2), 5.0)
+    W, H, step = 16, 12, 0.37 * h
+    cam = oracle.camera_from_sphere(20.0, 15.0, 2.5, 50.0, W, H)
+    face, knot = oracle.kinks(V, tf, cam, W, H, step, oracle.EA)
+    hits = 0
+    for p in range(W * H):
+        tr = oracle.trace_ray(V, tf, cam, W, H, p % W, p // W, step, oracle.EA)
+        if tr["N"] <= 0:
+            assert face[p] == 1e30 and knot[p] == 1e30
+            continue
+        hits += 1
+        x = tr["x"]
+        q = (x - bmin) / h
+        k = np.round(q)
+        inner = (k >= 1) & (k <= n - 2)
+        fmin = np.where(inner, np.abs(q - k), 1e30).min()
+        u = (c0 + x @ c) * (R - 1)
+        kmin = np.abs(u - np.round(u)).min()
+        assert abs(face[p] - fmin) <= 1e-9, (p, face[p], fmin)
+        assert abs(knot[p] - kmin) <= 1e-9, (p, knot[p], kmin)
+    assert hits > W * H // 4
