@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define DDVR_ABI_VERSION 4
+#define DDVR_ABI_VERSION 5
 
 typedef enum {
   DDVR_OK = 0,
@@ -190,6 +190,12 @@ typedef struct {
  *              per XCD, 2 persistent workgroups popping tiles from a queue
  *              ordered by estimated samples, longest first.  Batches whose
  *              grids mix storage types always use 2.
+ *   slab_axis  density and absorption-only grids: 1 (default) slabs between
+ *              planes of the grid axis closest to the tile's centre ray, whose
+ *              bricks stay tight at any view angle; 0 shells of constant
+ *              sample distance from the tile's earliest entry point.  A tile
+ *              where some ray does not advance along that axis, and every
+ *              launch without bricks, use shells.
  * Results do not depend on the tuning beyond float32 summation order. */
 typedef struct {
   int32_t waves;
@@ -199,6 +205,7 @@ typedef struct {
   int32_t cell_acc;
   int32_t lane_map;
   int32_t schedule;
+  int32_t slab_axis;
 } ddvr_tuning;
 
 int ddvr_set_tuning(const ddvr_tuning* t);

@@ -86,6 +86,7 @@ struct Tuning {
   int cell_acc = 1;     // per-cell register accumulation of the density gradient
   int lane_map = 2;     // lane -> pixel maps: compact forward, interleaved adjoint
   int schedule = 0;     // batches: 0 auto, 1 one workgroup per tile, 2 persistent queue
+  int slab_axis = 1;    // slabs between planes of a grid axis (0: distance shells)
 };
 Tuning g_tuning;
 
@@ -396,6 +397,7 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.slab_kmax = g_tuning.slab_kmax;
   p.cell_acc = g_tuning.cell_acc;
   p.lane_map = g_tuning.lane_map;
+  p.slab_axis = g_tuning.slab_axis;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   if (fb) attach_fallback(p, L, ws, flags);
@@ -677,7 +679,9 @@ int ddvr_set_tuning(const ddvr_tuning* t) {
   if (t->cell_acc != 0 && t->cell_acc != 1) return fail(DDVR_ERR_VALUE, "cell_acc is 0 or 1");
   if (t->lane_map < 0 || t->lane_map > 3) return fail(DDVR_ERR_VALUE, "lane_map is 0..3");
   if (t->schedule < 0 || t->schedule > 2) return fail(DDVR_ERR_VALUE, "schedule is 0, 1 or 2");
+  if (t->slab_axis != 0 && t->slab_axis != 1) return fail(DDVR_ERR_VALUE, "slab_axis is 0 or 1");
   g_tuning.schedule = t->schedule;
+  g_tuning.slab_axis = t->slab_axis;
   g_tuning.waves = t->waves;
   g_tuning.lds_cap = t->lds_cap;
   g_tuning.slab_k = t->slab_k;
@@ -696,6 +700,7 @@ int ddvr_get_tuning(ddvr_tuning* t) {
   t->cell_acc = g_tuning.cell_acc;
   t->lane_map = g_tuning.lane_map;
   t->schedule = g_tuning.schedule;
+  t->slab_axis = g_tuning.slab_axis;
   return DDVR_OK;
 }
 
@@ -1090,6 +1095,7 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.slab_kmax = b->tuning.slab_kmax;
   p.cell_acc = b->tuning.cell_acc;
   p.lane_map = b->tuning.lane_map;
+  p.slab_axis = b->tuning.slab_axis;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
   p.work = b->d_work;

@@ -50,6 +50,7 @@ struct LaunchParams {
   int32_t slab_kmax;      // longest slab (samples per ray) the adaptive march tries
   int32_t cell_acc;       // 1: density gradient kept in registers per cell
   int32_t lane_map;       // 1: lanes of a wave on every other pixel
+  int32_t slab_axis;      // 1: slabs between planes of a grid axis; 0: distance shells
   int32_t xcd_remap;      // 1: contiguous tile ranges per XCD (one tile per workgroup)
   int32_t* queue;         // persistent launch: tile counter (zeroed before the launch)
   float loss_scale;       // fused L2

@@ -376,18 +376,31 @@ template <int NT>
 __device__ __forceinline__ void wg_max_n(int* v, int n, int* scratch) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // (n is a compile-time constant at every call: unrolled, v stays in registers)
+#pragma unroll
   for (int k = 0; k < n; ++k) v[k] = wave_max_i32(v[k]);
   if (NW == 1) return;
   __syncthreads();
-  if (lane == 0)
+  if (lane == 0) {
+#pragma unroll
     for (int k = 0; k < n; ++k) scratch[wid * 8 + k] = v[k];
+  }
   __syncthreads();
+#pragma unroll
   for (int k = 0; k < n; ++k) {
     int x = scratch[k];
 #pragma unroll
     for (int w = 1; w < NW; ++w) x = max(x, scratch[w * 8 + k]);
     v[k] = x;
   }
+}
+
+// A value every lane of the wave holds alike (a workgroup reduction's
+// result), moved to a scalar register so that it takes no vector register
+// while it stays live across the march loops.
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float wave_uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 template <int NT>
@@ -411,6 +424,7 @@ template <int NT>
 __device__ __forceinline__ void wg_sum_n(float* v, int n, float* scratch) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
   for (int k = 0; k < n; ++k) {
     float x = v[k];
 #pragma unroll
@@ -419,10 +433,13 @@ __device__ __forceinline__ void wg_sum_n(float* v, int n, float* scratch) {
   }
   if (NW == 1) return;
   __syncthreads();
-  if (lane == 0)
+  if (lane == 0) {
+#pragma unroll
     for (int k = 0; k < n; ++k) scratch[wid * 16 + k] = v[k];
+  }
   __syncthreads();
   if (threadIdx.x == 0)
+#pragma unroll
     for (int k = 0; k < n; ++k) {
       float x = scratch[k];
       for (int w = 1; w < NW; ++w) x += scratch[w * 16 + k];
@@ -477,6 +494,8 @@ __device__ __forceinline__ bool range_brick(const ViewDesc& vd, const RayG& r, i
     for (int k = 0; k < 6; ++k) v[k] = -0x3fffffff;
   }
   wg_max_n<NT>(v, 6, iscratch);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_uniform(v[k]);
   if (v[3] < 0) return false;
   br.x0 = -v[0]; br.y0 = -v[1]; br.z0 = -v[2];
   const int bx = v[3] - br.x0 + 1, by = v[4] - br.y0 + 1, bz = v[5] - br.z0 + 1;
@@ -486,8 +505,8 @@ __device__ __forceinline__ bool range_brick(const ViewDesc& vd, const RayG& r, i
   br.bx4 = 4 * bx;
   br.bxy4 = 4 * br.bxy;
   br.off4 = -4 * (br.x0 + br.y0 * bx + br.z0 * br.bxy);
-  br.inv_bx = 1.0f / (float)bx;
-  br.inv_bxy = 1.0f / (float)br.bxy;
+  br.inv_bx = wave_uniform(1.0f / (float)bx);
+  br.inv_bxy = wave_uniform(1.0f / (float)br.bxy);
   return true;
 }
 
@@ -523,6 +542,148 @@ __device__ __forceinline__ int pick_slab(const ViewDesc& vd, const RayG& r, int 
     }
     if (cap <= 0 || K <= kmin) return 2;
     K = max(K >> 1, kmin);
+  }
+}
+
+// Axis slabs of a tile.  Slabs lie between planes q_ax = const of the grid
+// axis ax closest to the tile's centre ray, in march order (t = sgn * q_ax
+// grows along every ray): an axis-aligned slab has a tight bounding box at
+// any view angle, where a shell of constant distance from the eye cut
+// obliquely through the grid spans a box many times its volume (the
+// 4-channel brick holds a quarter of the scalar brick's vertices).  Each
+// ray's samples between two planes form one index range; consecutive slabs
+// share their boundary plane, so the ranges partition the ray.
+__device__ __forceinline__ void tile_axis(const ViewDesc& vd, int tx, int ty, int tw, int th,
+                                          const RayG& r, float& t0, float& dta) {
+  const float uc = 2.0f * ((float)(tx * tw) + 0.5f * tw) / (float)vd.W - 1.0f;
+  const float vc = 1.0f - 2.0f * ((float)(ty * th) + 0.5f * th) / (float)vd.H;
+  float wc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) wc[k] = vd.fwd[k] + uc * vd.right[k] + vc * vd.up[k];
+  const int ax = fabsf(wc[0]) >= fabsf(wc[1]) ? (fabsf(wc[0]) >= fabsf(wc[2]) ? 0 : 2)
+                                               : (fabsf(wc[1]) >= fabsf(wc[2]) ? 1 : 2);
+  // The axis picks by 0/1 weights, not by a run-time array index or a select
+  // of the ray's fields (the compiler turns either into an indexed load and
+  // keeps the ray in scratch memory).  Exact for the finite values of rays
+  // with samples, the only ones the slab walk reads.
+  const float e0 = ax == 0 ? 1.0f : 0.0f, e1 = ax == 1 ? 1.0f : 0.0f, e2 = ax == 2 ? 1.0f : 0.0f;
+  const float w = e0 * wc[0] + e1 * wc[1] + e2 * wc[2];
+  const float sgn = w >= 0.0f ? 1.0f : -1.0f;
+  t0 = sgn * (e0 * r.qo[0] + e1 * r.qo[1] + e2 * r.qo[2]);
+  dta = sgn * (e0 * r.dq[0] + e1 * r.dq[1] + e2 * r.dq[2]);
+}
+
+// first sample index at or past plane t (clamped to [0, n])
+__device__ __forceinline__ int axis_index(float t, float t0, float dta, int n) {
+  return (int)fminf(fmaxf(ceilf((t - t0) / dta), 0.0f), (float)n);
+}
+
+// The tile's plane range [tlo, thi] covering every ray's samples [0, n);
+// returns false if some ray with samples does not advance along the axis.
+template <int NT>
+__device__ __forceinline__ bool axis_range(float t0, float dta, int n, int* iscratch, int& tlo,
+                                           int& thi) {
+  const bool bad = n > 0 && !(dta > 0.0f);
+  int v[3] = {n > 0 ? -(int)floorf(t0) : -0x3fffffff,
+              n > 0 ? (int)ceilf(fmaf((float)(n - 1), dta, t0)) + 1 : -0x3fffffff, bad ? 1 : 0};
+  wg_max_n<NT>(v, 3, iscratch);
+  tlo = -v[0];
+  thi = v[1];
+  return v[2] == 0;
+}
+
+// A tile's walk through its slabs, shared by the forward (front to back) and
+// the adjoint (back to front).  Axis slabs (tile_axis) bound a ray's samples
+// by planes of one grid axis: their bricks stay tight at any view angle, and
+// a brick row along x holds a long run of touched voxels (one global atomic
+// request per 64 bytes of it when the gradient brick is flushed).  Distance
+// shells group samples by their index offset `off` from the tile's earliest
+// entry point; they serve launches without bricks and tiles where some ray
+// does not advance along the axis.  Widths are in planes (axis) or samples
+// (shells) and adapt per slab as in pick_slab.
+struct SlabWalk {
+  bool axis;
+  // this ray's coordinate of sample 0 and its advance per sample: the plane
+  // coordinate of its axis (axis slabs) or its sample offset and 1 (shells);
+  // its samples between slab bounds [l, h) are [axis_index(l), axis_index(h))
+  float t0, dta;
+  float lo, hi;         // the tile's range: planes (axis) or offsets [0, end) (shells)
+  float w, wmin, wmax;  // current slab width and its limits
+};
+
+// Set up the walk over samples [0, N) of every ray of the tile (N = 0: none).
+// `tmin` is the tile's earliest entry distance (shells: a ray's offset is its
+// entry distance past it in steps).
+template <int NT>
+__device__ __forceinline__ void walk_init(const ViewDesc& vd, const RayG& r, int N, int tx,
+                                          int ty, int tw, int th, int cap, int kmax,
+                                          bool want_axis, float tmin, int* iscratch,
+                                          SlabWalk& w) {
+  const int off = (cap > 0 && r.N > 0) ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
+  float t0, dta;
+  tile_axis(vd, tx, ty, tw, th, r, t0, dta);
+  want_axis = want_axis && cap > 0;
+  const bool has = N > 0;
+  int v[4] = {has ? off + N : 0,
+              (want_axis && has) ? -(int)floorf(t0) : -0x3fffffff,
+              (want_axis && has) ? (int)ceilf(fmaf((float)(N - 1), dta, t0)) + 1 : -0x3fffffff,
+              (want_axis && has && !(dta > 0.0f)) ? 1 : 0};
+  wg_max_n<NT>(v, 4, iscratch);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_uniform(v[k]);
+  w.axis = want_axis && v[3] == 0 && v[1] > -0x3fffffff;
+  w.t0 = w.axis ? t0 : (float)off;
+  w.dta = w.axis ? dta : 1.0f;
+  const float K = (float)min(vd.slab_k, kmax);
+  if (w.axis) {
+    // a slab of K samples spans at most K step/h planes of its axis
+    const float pps = vd.step * vd.inv_h;
+    w.lo = (float)(-v[1]);
+    w.hi = (float)v[2];
+    w.w = wave_uniform(K * pps);
+    w.wmin = wave_uniform(fmaxf(4.0f * pps, 0.25f));
+    w.wmax = wave_uniform(fmaxf((float)kmax * pps, w.w));
+  } else {
+    w.lo = 0.0f;
+    w.hi = (float)v[0];
+    w.w = K;
+    w.wmin = 4.0f;
+    w.wmax = (float)kmax;
+  }
+}
+
+// This ray's samples [a, b) between the slab bounds [l, h) (N samples; for
+// shells the bounds and offsets are integers, so this is their index range).
+__device__ __forceinline__ void walk_range(const SlabWalk& w, float l, float h, int N, int& a,
+                                           int& b) {
+  a = axis_index(l, w.t0, w.dta, N);
+  b = axis_index(h, w.t0, w.dta, N);
+  if (N <= 0) a = b = 0;
+}
+
+// The next slab from `pos` (dir +1: [pos, pos + w), -1: [pos - w, pos)),
+// narrowed until its brick fits `cap` voxels and widened again after a slab
+// that used less than a quarter of it.  Returns 0 = empty, 1 = fits (stage in
+// LDS), 2 = does not fit at the minimum width (direct global access); [l, h)
+// is the slab and [a, b) this ray's samples in it.
+template <int NT>
+__device__ __forceinline__ int walk_next(const ViewDesc& vd, const RayG& r, int N, SlabWalk& w,
+                                         float pos, int dir, int cap, float& l, float& h,
+                                         int& a, int& b, int* iscratch, Brick& br) {
+  for (;;) {
+    if (dir > 0) { l = pos; h = wave_uniform(fminf(pos + w.w, w.hi)); }
+    else { h = pos; l = wave_uniform(fmaxf(pos - w.w, w.lo)); }
+    walk_range(w, l, h, N, a, b);
+    if (!range_brick<NT>(vd, r, a, b, iscratch, br)) {
+      w.w = wave_uniform(fminf(2.0f * w.w, w.wmax));
+      return 0;
+    }
+    if (cap > 0 && br.size <= cap) {
+      if (4 * br.size < cap) w.w = wave_uniform(fminf(2.0f * w.w, w.wmax));
+      return 1;
+    }
+    if (cap <= 0 || w.w <= w.wmin) return 2;
+    w.w = wave_uniform(fmaxf(w.axis ? 0.5f * w.w : floorf(0.5f * w.w), w.wmin));
   }
 }
 
@@ -1156,20 +1317,12 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   RunGeo rg;
   if (MODEL == DDVR_ABSORPTION) run_geo(vd, r, rg);
 
-  // slab bookkeeping (shared by both passes): sample offsets relative to the
-  // earliest entry point of the tile
-  int off = 0, tile_end;
+  // slab bookkeeping (shared by both passes): the tile's earliest entry
+  // distance (shells), the longest slab tried
   const int kmax = cap > 0 ? max(p.slab_kmax, 4) : kMaxSamples + 1;
+  const bool want_axis = p.slab_axis != 0;
   float tmin = 0.0f;
-  if (cap > 0) {
-    tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
-    off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
-  }
-  {
-    int e = hit ? off + r.N : 0;
-    wg_max_n<NT>(&e, 1, iscratch);
-    tile_end = e;
-  }
+  if (cap > 0) tmin = wg_min_f<NT>(hit ? r.t0 : INFINITY, fscratch);
   __syncthreads();   // TF table visible
 
   const int C = EA ? 4 : 1;
@@ -1181,14 +1334,13 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     fs.C[0] = fs.C[1] = fs.C[2] = 0.0f;
     fs.T = 1.0f;
     fs.sigma = 0.0f;
-    int K = min(vd.slab_k, kmax);
-    for (int pos = 0; pos < tile_end;) {
-      int lo, hi;
-      Brick br;
-      const int st = pick_slab<NT>(vd, r, off, r.N, pos, +1, tile_end, cap, K, kmax, lo, hi,
-                                   iscratch, br);
+    SlabWalk sw;
+    walk_init<NT>(vd, r, r.N, tx, ty, TW, TH, cap, kmax, want_axis, tmin, iscratch, sw);
+    for (float pos = sw.lo; pos < sw.hi;) {
+      float lo, hi;
       int a, b;
-      slab_range(lo, hi, off, r.N, a, b);
+      Brick br;
+      const int st = walk_next<NT>(vd, r, r.N, sw, pos, +1, cap, lo, hi, a, b, iscratch, br);
       if (st == 1) {
         stage_brick<NT, DT>(vd, br, stage, nullptr);
         __syncthreads();
@@ -1269,7 +1421,6 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     pix = (int64_t)py * vd.W + px;
     if (MODEL == DDVR_ABSORPTION) run_geo(vd, r, rg);
     hit = r.N > 0;
-    off = hit ? (int)rintf((r.t0 - tmin) / vd.step) : 0;
     // the staging region is next written after the adjoint's first brick
     // reduction, whose barriers order it after these reads
   }
@@ -1366,7 +1517,7 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
     // per-lane maxima, reduced in one pass: tile end, then the bound's factors
     constexpr int NV = EA ? 4 : 2;
     int v[NV];
-    v[0] = Nadj > 0 ? off + Nadj : 0;
+    v[0] = 0;
     if (!EA) {
       v[1] = __float_as_int((ao_bound && lane_dv) ? fabsf(vd.step * s.P) : 0.0f);
     } else {
@@ -1385,7 +1536,6 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
       v[3] = __float_as_int(rgbmax);
     }
     wg_max_n<NT>(v, NV, iscratch);
-    tile_end = v[0];
     float B;
     if (!EA) {
       B = __int_as_float(v[1]) * (float)NT * lmax;
@@ -1421,16 +1571,15 @@ __device__ __forceinline__ void render_tile(const LaunchParams& p, const int ite
   s.dhq = s.dh * s.qs;
   const bool need_v = EA || (gmask & (GRAD_CAM | GRAD_STEP)) || !use_fix;
   const int acap = fix_ok ? cap : 0;
-  int K = min(vd.slab_k, kmax);
-  for (int pos = tile_end; pos > 0;) {
-    int lo, hi;
+  SlabWalk sw;
+  walk_init<NT>(vd, r, Nadj, tx, ty, TW, TH, cap, kmax, want_axis, tmin, iscratch, sw);
+  for (float pos = sw.hi; pos > sw.lo;) {
+    float lo, hi;
+    int a, b;
     Brick br;
-    const int st = pick_slab<NT>(vd, r, off, Nadj, pos, -1, 0, acap, K, kmax, lo, hi, iscratch,
-                                 br);
+    const int st = walk_next<NT>(vd, r, Nadj, sw, pos, -1, acap, lo, hi, a, b, iscratch, br);
     pos = lo;
     if (st == 0) continue;
-    int a, b;
-    slab_range(lo, hi, off, Nadj, a, b);
     if (st == 1) {
       stage_brick<NT, DT, EA>(vd, br, need_v ? stage : nullptr, want_dv ? acc : nullptr);
       __syncthreads();
@@ -2332,47 +2481,6 @@ __device__ __forceinline__ void color_brick_flush(const ViewDesc& vd, const Bric
     gadd(org + 4 * (narrow ? brick_goff<true>(br, idx, sy, sz)
                            : brick_goff<false>(br, idx, sy, sz)) + ch, g);
   }
-}
-
-// Axis slabs of a tile.  Slabs lie between planes q_ax = const of the grid
-// axis ax closest to the tile's centre ray, in march order (t = sgn * q_ax
-// grows along every ray): an axis-aligned slab has a tight bounding box at
-// any view angle, where a shell of constant distance from the eye cut
-// obliquely through the grid spans a box many times its volume (the
-// 4-channel brick holds a quarter of the scalar brick's vertices).  Each
-// ray's samples between two planes form one index range; consecutive slabs
-// share their boundary plane, so the ranges partition the ray.
-__device__ __forceinline__ void tile_axis(const ViewDesc& vd, int tx, int ty, int tw, int th,
-                                          const RayG& r, float& t0, float& dta) {
-  const float uc = 2.0f * ((float)(tx * tw) + 0.5f * tw) / (float)vd.W - 1.0f;
-  const float vc = 1.0f - 2.0f * ((float)(ty * th) + 0.5f * th) / (float)vd.H;
-  float wc[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) wc[k] = vd.fwd[k] + uc * vd.right[k] + vc * vd.up[k];
-  const int ax = fabsf(wc[0]) >= fabsf(wc[1]) ? (fabsf(wc[0]) >= fabsf(wc[2]) ? 0 : 2)
-                                               : (fabsf(wc[1]) >= fabsf(wc[2]) ? 1 : 2);
-  const float sgn = wc[ax] >= 0.0f ? 1.0f : -1.0f;
-  t0 = sgn * r.qo[ax];
-  dta = sgn * r.dq[ax];
-}
-
-// first sample index at or past plane t (clamped to [0, n])
-__device__ __forceinline__ int axis_index(float t, float t0, float dta, int n) {
-  return (int)fminf(fmaxf(ceilf((t - t0) / dta), 0.0f), (float)n);
-}
-
-// The tile's plane range [tlo, thi] covering every ray's samples [0, n);
-// returns false if some ray with samples does not advance along the axis.
-template <int NT>
-__device__ __forceinline__ bool axis_range(float t0, float dta, int n, int* iscratch, int& tlo,
-                                           int& thi) {
-  const bool bad = n > 0 && !(dta > 0.0f);
-  int v[3] = {n > 0 ? -(int)floorf(t0) : -0x3fffffff,
-              n > 0 ? (int)ceilf(fmaf((float)(n - 1), dta, t0)) + 1 : -0x3fffffff, bad ? 1 : 0};
-  wg_max_n<NT>(v, 3, iscratch);
-  tlo = -v[0];
-  thi = v[1];
-  return v[2] == 0;
 }
 
 // Stage the brick's (r, g, b, tau) as float4 per vertex, 4 loads in flight

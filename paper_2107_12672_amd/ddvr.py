@@ -69,7 +69,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
                 ("slab_k", ctypes.c_int32), ("slab_kmax", ctypes.c_int32),
                 ("cell_acc", ctypes.c_int32), ("lane_map", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("slab_axis", ctypes.c_int32)]
 
 
 class Grads(ctypes.Structure):
@@ -242,7 +242,7 @@ def camera_grad_to_sphere(yaw, pitch, dist, fovy, width, height, d_frame: Sequen
 
 
 TUNING_DEFAULT = {"waves": 4, "lds_cap": 7168, "slab_k": 64, "slab_kmax": 256, "cell_acc": 1,
-                  "lane_map": 2, "schedule": 0}
+                  "lane_map": 2, "schedule": 0, "slab_axis": 1}
 
 
 def set_tuning(**kw):

@@ -326,10 +326,13 @@ def assert_grad_close(g, o, what, rtol=GRAD_RTOL, floor_frac=1e-2):
     o = np.asarray(o, np.float64)
     scale = float(np.abs(o).max())
     floor = floor_frac * scale
-    bound = rtol * np.maximum(np.abs(o), floor)
-    bad = np.abs(g - o) > bound
+    rel = np.abs(g - o) / np.maximum(np.maximum(np.abs(o), floor), 1e-300)
+    print(f"[grad] {what}: worst relative error {float(rel.max()):.3g} (rtol {rtol:g}, "
+          f"floor {floor_frac:g} of the scale)", flush=True)
+    bad = rel > rtol
     assert not bad.any(), f"{what}: {int(bad.sum())} entries off; worst {float(np.abs(g - o).max()):.3g} " \
                           f"at scale {scale:.3g}"
+    return float(rel.max())
 
 
 def assert_dv_close(g, o, what, rtol=GRAD_RTOL):

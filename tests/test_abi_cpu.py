@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_string():
     d = _ddvr()
-    assert d.abi_version() == 4
+    assert d.abi_version() == 5
     assert isinstance(d.last_error(), str)
 
 
@@ -174,13 +174,13 @@ def test_tuning_roundtrip_and_validation():
     old = d.get_tuning()
     try:
         d.set_tuning(waves=2, lds_cap=4096, slab_k=16, slab_kmax=64, cell_acc=0, lane_map=0,
-                     schedule=2)
+                     schedule=2, slab_axis=0)
         assert d.get_tuning() == {"waves": 2, "lds_cap": 4096, "slab_k": 16, "slab_kmax": 64,
-                                  "cell_acc": 0, "lane_map": 0, "schedule": 2}
+                                  "cell_acc": 0, "lane_map": 0, "schedule": 2, "slab_axis": 0}
         for bad in ({"waves": 3}, {"lds_cap": 10}, {"lds_cap": 1 << 20}, {"slab_k": 2},
                     {"slab_k": 128, "slab_kmax": 64}, {"cell_acc": 2}, {"lane_map": -1},
                     {"lane_map": 4},
-                    {"schedule": 3}):
+                    {"schedule": 3}, {"slab_axis": 2}):
             with pytest.raises(d.DDVRError) as ei:
                 d.set_tuning(**bad)
             assert ei.value.status == d.ERR_VALUE

@@ -413,10 +413,13 @@ def _fused_vs_separate(d):
     {"waves": 4, "lds_cap": 8192, "slab_k": 128, "cell_acc": 0, "lane_map": 1},
     {"waves": 4, "lds_cap": 7168, "slab_k": 64, "cell_acc": 1, "lane_map": 2},
     {"waves": 2, "lds_cap": 3072, "slab_k": 32, "cell_acc": 1, "lane_map": 3},
+    {"waves": 4, "lds_cap": 7168, "slab_k": 64, "cell_acc": 1, "lane_map": 2, "slab_axis": 0},
+    {"waves": 1, "lds_cap": 1024, "slab_k": 8, "cell_acc": 1, "lane_map": 0, "slab_axis": 0},
 ])
 def test_results_do_not_depend_on_the_launch_shape(tuning):
-    """Forward bitwise identical across tile shapes, brick sizes and slab
-    lengths (per-ray arithmetic does not depend on the tiling: this also
+    """Forward bitwise identical across tile shapes, brick sizes, slab
+    lengths and slab shapes (axis slabs or distance shells: the per-sample
+    emission-absorption arithmetic does not depend on the tiling, which also
     catches LDS staging / barrier races); gradients equal up to summation
     order and matching the oracle."""
     from paper_2107_12672_amd import ddvr as d
