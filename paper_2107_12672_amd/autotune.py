@@ -93,10 +93,10 @@ def apply(key: str, path: Optional[str] = None) -> bool:
 
 def default_candidates() -> List[dict]:
     out = []
-    for waves, cap, k, lm in itertools.product((2, 4), (5120, 6144, 7168, 8192, 12288),
-                                               (32, 64), (0, 1, 2)):
+    for waves, cap, k, lm, ax in itertools.product((2, 4), (5120, 6144, 7168, 8192, 12288),
+                                                   (32, 64), (1, 2), (0, 1)):
         out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
-                    "cell_acc": 1, "lane_map": lm, "schedule": 0})
+                    "cell_acc": 1, "lane_map": lm, "schedule": 0, "slab_axis": ax})
     return out
 
 
@@ -159,10 +159,10 @@ def uneven_candidates() -> List[dict]:
     """Launch shapes of the persistent uneven-batch launch (its schedule is
     always the queue)."""
     out = []
-    for waves, cap, k, lm in itertools.product((2, 4), (4096, 7168, 10240), (32, 64),
-                                               (0, 2)):
+    for waves, cap, k, lm, ax in itertools.product((2, 4), (4096, 7168, 10240), (32, 64),
+                                                   (0, 2), (0, 1)):
         out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
-                    "cell_acc": 1, "lane_map": lm, "schedule": 2})
+                    "cell_acc": 1, "lane_map": lm, "schedule": 2, "slab_axis": ax})
     return out
 
 
@@ -280,10 +280,10 @@ def main(argv=None) -> None:
         key = workload_key(_device_arch(), _d.EMISSION_ABSORPTION, "f16", w.tf.shape[0], W,
                            w.volume.shape[0], "V+TF+step", _d.PASS_FUSED)
         cands = []
-        for waves, cap, k, lm in itertools.product((2, 4), (4096, 5120, 6144, 7168), (32, 64),
-                                                   (0, 2)):
+        for waves, cap, k, lm, ax in itertools.product((2, 4), (4096, 5120, 6144, 7168),
+                                                       (32, 64), (0, 2), (0, 1)):
             cands.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
-                          "cell_acc": 1, "lane_map": lm, "schedule": 0})
+                          "cell_acc": 1, "lane_map": lm, "schedule": 0, "slab_axis": ax})
         res = tune(key, make5, lambda b: b.run(_d.PASS_FUSED, scale, loss, workspace=ws_["ws"]),
                    lambda: images, candidates=cands, reps=args.reps, verbose=True)
         print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
