@@ -12,26 +12,38 @@ namespace {
 
 constexpr int kChains = ddvr::kProbeChains;
 
+// Chain j of a lane runs per round: MODE 0 a float32 FMA, 1 a 32-bit integer
+// add, 2 the two alternating over the chains (float and integer work that the
+// SIMD may overlap), 3 FMAs alternating with the hardware exp2 (the
+// transcendental unit), 4 a float32 multiply then a max (two two-operand
+// instructions), 5 a shift then an xor (two integer ones).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_valu_probe(float* out, int iters, float a, float b) {
   float x[kChains];
   uint32_t y[kChains];
 #pragma unroll
   for (int j = 0; j < kChains; ++j) {
-    x[j] = (float)threadIdx.x * 1e-3f + (float)j;
+    x[j] = (float)threadIdx.x * 1e-3f + (float)j * 1e-2f;
     y[j] = threadIdx.x * 2654435761u + (uint32_t)j;
   }
   const uint32_t k = __float_as_uint(b);
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
     for (int j = 0; j < kChains; ++j) {
-      if (MODE == 0) x[j] = fmaf(x[j], a, b);
-      else y[j] += k;
+      const bool odd = (j & 1) != 0;
+      if (MODE == 0 || ((MODE == 2 || MODE == 3) && !odd)) x[j] = fmaf(x[j], a, b);
+      else if (MODE == 1 || MODE == 2) y[j] += k;
+      else if (MODE == 3) x[j] = __builtin_amdgcn_exp2f(-x[j]);   // stays in (0, 1]
+      else if (MODE == 4) x[j] = fmaxf(x[j] * a, b);
+      else y[j] ^= y[j] >> 3;
     }
   }
   float s = 0.0f;
 #pragma unroll
-  for (int j = 0; j < kChains; ++j) s += MODE == 0 ? x[j] : (float)y[j];
+  for (int j = 0; j < kChains; ++j) {
+    const bool odd = (j & 1) != 0;
+    s += (MODE == 1 || MODE == 5 || (MODE == 2 && odd)) ? (float)y[j] : x[j];
+  }
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
@@ -43,8 +55,16 @@ int launch_valu_probe(int mode, int blocks, int iters, float* out, void* stream)
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (mode == 0)
     hipLaunchKernelGGL(k_valu_probe<0>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
-  else
+  else if (mode == 1)
     hipLaunchKernelGGL(k_valu_probe<1>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
+  else if (mode == 2)
+    hipLaunchKernelGGL(k_valu_probe<2>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
+  else if (mode == 3)
+    hipLaunchKernelGGL(k_valu_probe<3>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
+  else if (mode == 4)
+    hipLaunchKernelGGL(k_valu_probe<4>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
+  else
+    hipLaunchKernelGGL(k_valu_probe<5>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
   return (int)hipGetLastError();
 }
 
