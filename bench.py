@@ -510,11 +510,16 @@ def secondary(args):
         if vc and vc.get("kernel_source_sha") == h.hexdigest()[:16]:
             ops = nvox * ncand * vc["valu_per_candidate"]
             a = ops / (ms * 1e-3) / 1e12
-            out["roofline"] = {"bound": "alu", "achieved": round(a, 3), "peak": VALU_PEAK_TOPS,
-                               "unit": "TOP/s", "frac": round(a / VALU_PEAK_TOPS, 4),
+            peak = valu_ceiling() or VALU_PUBLISHED_TOPS
+            single = valu_ceiling("single_issue_tops")
+            out["roofline"] = {"bound": "alu", "achieved": round(a, 3), "peak": peak,
+                               "unit": "TOP/s", "frac": round(a / peak, 4),
+                               "frac_of_single_issue": round(a / single, 4) if single else None,
+                               "peak_source": "measured VALU issue ceiling (dual issue), "
+                                              "profiles/valu_ceiling.json",
                                "traffic": tr, "kernel": "k_density_from_color<bf16>",
                                "kernel_ms": round(ms, 4), "ops_per_launch": ops,
-                               "ops": "VALU lane-operations: %d per candidate" %
+                               "ops": "VALU lane-instructions: %d per candidate" %
                                       vc["valu_per_candidate"]}
         else:
             out["roofline"] = None

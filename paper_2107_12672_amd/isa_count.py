@@ -11,8 +11,8 @@ adjoint's cell-run loops (one run = the samples of a ray inside one cell).
 It also counts, in ``csrc/ddvr_dfc.hip``, the VALU instructions of the
 density-from-colour candidate loop (bf16 colour volume): one candidate.
 ``--write`` stores the counts with the source hashes in
-``profiles/valu_per_sample_c3.json`` and ``profiles/valu_per_candidate_dfc.json``,
-which the benchmark reads.
+``profiles/valu_per_run_c3.json`` and ``profiles/valu_per_candidate_dfc.json``,
+the second of which the benchmark reads (the first documents the cell-run loops).
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ from . import build as _build
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-OUT = os.path.join(ROOT, "profiles", "valu_per_sample_c3.json")
+OUT = os.path.join(ROOT, "profiles", "valu_per_run_c3.json")
 OUT_DFC = os.path.join(ROOT, "profiles", "valu_per_candidate_dfc.json")
 DFC_SOURCES = ["paper_2107_12672_amd/csrc/ddvr_dfc.hip", "paper_2107_12672_amd/csrc/ddvr_internal.h"]
 DFC = "_ZN4ddvr12_GLOBAL__N_120k_density_from_colorILi2EEEvNS_9DfcParamsE"
