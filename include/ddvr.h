@@ -208,14 +208,16 @@ typedef struct {
   int32_t slab_axis;
 } ddvr_tuning;
 
+/* Set / read the process-wide launch shape (no paper counterpart).  set:
+ * DDVR_ERR_NULL for NULL, DDVR_ERR_VALUE outside the ranges above. */
 int ddvr_set_tuning(const ddvr_tuning* t);
 int ddvr_get_tuning(ddvr_tuning* t);
 
-/* Version of this ABI (DDVR_ABI_VERSION). */
+/* Version of this ABI (DDVR_ABI_VERSION; no paper counterpart). */
 int ddvr_abi_version(void);
 
 /* Description of the last error of the calling thread (static storage, valid
- * until the next call on this thread).  Never NULL. */
+ * until the next call on this thread; no paper counterpart).  Never NULL. */
 const char* ddvr_last_error(void);
 
 /* Camera on a sphere around the grid centre, facing it (Sec. 5.1: longitude /
@@ -226,11 +228,13 @@ int ddvr_camera_from_sphere(float yaw, float pitch, float dist, float fovy, int3
                             int32_t height, ddvr_camera* out);
 
 /* Chain rule from a frame gradient d_frame[12] (host, layout of
- * ddvr_grads.d_camera) to d_sphere[4] (host) = d/d(yaw, pitch, dist, fovy). */
+ * ddvr_grads.d_camera) to d_sphere[4] (host) = d/d(yaw, pitch, dist, fovy)
+ * (Sec. 5.1: gradients w.r.t. the viewpoint's longitude, latitude, distance). */
 int ddvr_camera_grad_to_sphere(float yaw, float pitch, float dist, float fovy, int32_t width,
                                int32_t height, const float* d_frame, float* d_sphere);
 
-/* Storage copy of a float32 master grid (form of the grid the kernels read):
+/* Storage copy of a float32 master grid (form of the grid the kernels read; no
+ * paper counterpart: reduced-precision storage is this implementation's):
  * dst[i] = round_to_nearest_even(src[i]) in `dtype` (f32: plain copy), for
  * i < n.  src, dst device; may not overlap. */
 int ddvr_cast_volume(const float* src, void* dst, int32_t dtype, int64_t n, void* hip_stream);
@@ -346,7 +350,8 @@ int ddvr_render_tangent(const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_ca
 /* Directions of the sphere camera's parameters: d_frame[k*12 + j] (host,
  * [4][12]) = d frame_j / d (yaw, pitch, dist, fovy)_k, angles in radians --
  * the tangent inputs that make render_tangent differentiate w.r.t. the
- * viewpoint (the transpose of ddvr_camera_grad_to_sphere). */
+ * viewpoint (the transpose of ddvr_camera_grad_to_sphere; Sec. 5.1, forward
+ * mode). */
 int ddvr_camera_sphere_tangents(float yaw, float pitch, float dist, float fovy, int32_t width,
                                 int32_t height, float* d_frame);
 
@@ -380,8 +385,9 @@ int ddvr_density_from_color(const ddvr_volume* color, const ddvr_tf* tf, const f
                             int32_t ncand, float* d_out, float* cost_out, uint32_t* n_changed,
                             void* hip_stream);
 
-/* Largest extinction (channel 3) of a colour volume: *out (device, one float)
- * is written (-inf for an empty volume). */
+/* Largest extinction (channel 3) of a colour volume (Sec. 5.4 colour volume;
+ * no paper counterpart for the reduction): *out (device, one float) is written
+ * (-inf for an empty volume). */
 int ddvr_color_tau_max(const ddvr_volume* color, float* out, void* hip_stream);
 
 /* ------------------------------------------------------------------------
@@ -416,7 +422,8 @@ int ddvr_volume_prior(const float* volume, int32_t nx, int32_t ny, int32_t nz, f
 int ddvr_opacity_entropy(const float* image, int64_t npix, int32_t channels, double* work,
                          double* value_out, float* d_image, float scale, void* hip_stream);
 
-/* One Adam step (Kingma and Ba 2014) on n float32 parameters, step t >= 1:
+/* One Adam step (Kingma and Ba 2014; the optimiser of the Sec. 5.2-5.3
+ * reconstructions) on n float32 parameters, step t >= 1:
  *   m = beta1 m + (1-beta1) g;  v = beta2 v + (1-beta2) g^2;
  *   param -= lr (m/(1-beta1^t)) / (sqrt(v/(1-beta2^t)) + eps), then clamped to
  *   [lo, hi] (pass -inf / +inf for none).
@@ -462,8 +469,9 @@ typedef struct {
 
 typedef struct ddvr_batch ddvr_batch;
 
-/* Build a batch (host-side planning + a small device buffer of view
- * descriptors and a cost-ordered tile queue, owned by the batch).
+/* Build a batch (no paper counterpart; host-side planning + a small device
+ * buffer of view descriptors and a cost-ordered tile queue, owned by the
+ * batch).
  *   d_volumes[nvol], d_tfs[ntf]: per-volume / per-TF gradient outputs (device,
  *   entries or the arrays themselves may be NULL).
  *   The pointers inside are captured; rebuild the batch if they change. */
@@ -471,23 +479,29 @@ int ddvr_batch_create(const ddvr_volume* vols, int32_t nvol, const ddvr_tf* tfs,
                       const ddvr_view* views, int32_t nview, int32_t model, int32_t flags,
                       float* const* d_volumes, float* const* d_tfs, void* hip_stream,
                       ddvr_batch** out);
+/* Free a batch and its device buffers (NULL is ignored; no paper counterpart). */
 void ddvr_batch_destroy(ddvr_batch* b);
-/* pass: 0 = forward, 1 = adjoint (views need d_image), 2 = fused forward+L2+adjoint
+/* Workspace bytes of the batch's adjoint (checkpoint queue and slots; no paper
+ * counterpart), and one pass of the batch (per view Alg. 1 / Alg. 2): pass 0 =
+ * forward, 1 = adjoint (views need d_image), 2 = fused forward+L2+adjoint
  * (views need target). loss_out as in render_fused_l2.  Workspace as for a
  * single view, sized by ddvr_batch_workspace_size. */
 int ddvr_batch_workspace_size(const ddvr_batch* b, size_t* bytes);
 int ddvr_batch_run(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
                    void* workspace, size_t workspace_bytes, void* hip_stream);
-/* Record pass `pass` of the batch into a HIP graph and replay it.  The batch
+/* Record pass `pass` of the batch into a HIP graph and replay it (no paper
+ * counterpart).  The batch
  * keeps one recorded graph per pass, keyed on (loss_scale, loss_out,
  * workspace, workspace_bytes): a call with the same arguments as the pass's
  * last recording replays it, other arguments re-record that pass only (after
  * waiting for the stream).  Alternating passes therefore replay. */
 int ddvr_batch_run_graph(ddvr_batch* b, int32_t pass, float loss_scale, double* loss_out,
                          void* workspace, size_t workspace_bytes, void* hip_stream);
-/* Graphs recorded and instantiated by ddvr_batch_run_graph so far (host). */
+/* Graphs recorded and instantiated by ddvr_batch_run_graph so far (host; no
+ * paper counterpart). */
 int ddvr_batch_graph_builds(const ddvr_batch* b, int64_t* builds);
-/* Samples (sum over rays of N) the batch's views take; host output. */
+/* Samples (sum over rays of N, Alg. 1's sample count) the batch's views take;
+ * host output. */
 int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples);
 
 /* ------------------------------------------------------------------------
@@ -511,7 +525,8 @@ int ddvr_batch_sample_count(const ddvr_batch* b, int64_t* samples);
  * colour channels 0) between the forward and the adjoint. */
 #define DDVR_PLAN_LOSS_NEG_ENTROPY 2
 typedef struct ddvr_plan ddvr_plan;
-/*   loss        one of DDVR_PLAN_LOSS_*.
+/* Record a batch's whole step into one HIP graph (no paper counterpart):
+ *   loss        one of DDVR_PLAN_LOSS_*.
  *   loss_scale  weight of the loss (fused: as render_fused_l2).
  *   loss_out    (device, one double, may be NULL) += the step's loss on every
  *               replay.
@@ -520,11 +535,13 @@ typedef struct ddvr_plan ddvr_plan;
  * The plan owns its graph and, for the entropy, 3 doubles per view. */
 int ddvr_plan_create(ddvr_batch* b, int32_t loss, float loss_scale, double* loss_out,
                      void* workspace, size_t workspace_bytes, void* hip_stream, ddvr_plan** out);
-/* Replay the recorded step on hip_stream. */
+/* Replay the recorded step on hip_stream (no paper counterpart). */
 int ddvr_plan_execute(ddvr_plan* p, void* hip_stream);
-/* Entropy plans: OE of every view at the last replay, out (host) [n], n the
- * number of views; synchronises hip_stream. */
+/* Entropy plans: OE of every view at the last replay (Sec. 5.1's opacity
+ * entropy), out (host) [n], n the number of views; synchronises hip_stream. */
+
 int ddvr_plan_loss_terms(const ddvr_plan* p, double* out, int32_t n, void* hip_stream);
+/* Free a plan and its graph (NULL is ignored; no paper counterpart). */
 void ddvr_plan_destroy(ddvr_plan* p);
 
 /* ------------------------------------------------------------------------

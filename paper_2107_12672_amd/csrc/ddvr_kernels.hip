@@ -822,7 +822,8 @@ __device__ __forceinline__ void march_fwd(const ViewDesc& vd, const RayG& r, int
 // ---------------------------------------------------------------------------
 struct RunGeo {
   float inv_dq[3];       // 1/dq per axis (1e30 where dq = 0: no boundary)
-  float up[3];           // 1 if the ray moves up the axis (or not at all), else 0
+  float upq[3];          // up - q_o: up = 1 if the ray moves up the axis (or not at
+                         // all), else 0
   float dxy, dxz, dyz;   // products of the per-sample steps of two axes
 };
 
@@ -831,7 +832,7 @@ __device__ __forceinline__ void run_geo(const ViewDesc& vd, const RayG& r, RunGe
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     g.inv_dq[a] = r.dq[a] != 0.0f ? 1.0f / r.dq[a] : 1e30f;
-    g.up[a] = r.dq[a] >= 0.0f ? 1.0f : 0.0f;
+    g.upq[a] = (r.dq[a] >= 0.0f ? 1.0f : 0.0f) - r.qo[a];
   }
   g.dxy = r.dq[0] * r.dq[1];
   g.dxz = r.dq[0] * r.dq[2];
@@ -852,7 +853,7 @@ __device__ __forceinline__ void locate_cell(const RayG& r, float fi, const ViewD
 
 // One past the last sample of [fi, fb) in the cell kf of sample fi, at least
 // fi + 1: the first index at or past the next cell face along each axis,
-// ceil((k + up - q_o)/dq).  Float rounding can move a boundary by one sample
+// ceil((k + (up - q_o))/dq).  Float rounding can move a boundary by one sample
 // (that sample is then evaluated with the neighbouring cell's polynomial a
 // hair outside [0, 1], where the trilinear interpolant is continuous, or
 // starts a run of its own); the box faces end the ray anyway.
@@ -860,7 +861,7 @@ __device__ __forceinline__ float run_end(const RayG& r, const RunGeo& g, const f
                                          float fi, float fb) {
   float e = fb;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) e = fminf(e, ceilf((kf[a] + g.up[a] - r.qo[a]) * g.inv_dq[a]));
+  for (int a = 0; a < 3; ++a) e = fminf(e, ceilf((kf[a] + g.upq[a]) * g.inv_dq[a]));
   return fmaxf(e, fi + 1.0f);
 }
 
@@ -899,24 +900,27 @@ __device__ __forceinline__ float run_density_sum(const float* v, const float* f,
 // Sums over an absorption-only run of the 8 corner weights, w (index cx + 2cy
 // + 4cz) = m (w_c(mu) + s2 (sx sy dxy z_c + sx sz dxz y_c + sy sz dyz x_c)),
 // with x_c, y_c, z_c the corner's linear factors at mu and s = +1 for the
-// upper corner of an axis, -1 for the lower; times `scale`.
+// lower corner of an axis, -1 for the upper (the sign of the factor's slope;
+// only products of two signs appear); times `scale`.
 __device__ __forceinline__ void run_weight_sums(const float* f, float m, const RunGeo& g,
                                                 float scale, float* w) {
+  // Corner (cx, cy, cz) sums to
+  //   X (Y Z + s_y s_z e_yz) + s_x (s_y e_xy Z + s_z e_xz Y),
+  // factored over (cy, cz); the run length and the scale ride on X, e_xy and
+  // e_xz.
   const float s2 = (m * m - 1.0f) * (1.0f / 12.0f);
-  const float exy = s2 * g.dxy, exz = s2 * g.dxz, eyz = s2 * g.dyz;
-  const float X[2] = {1.0f - f[0], f[0]}, Y[2] = {1.0f - f[1], f[1]}, Z[2] = {1.0f - f[2], f[2]};
   const float sc = m * scale;
+  const float exy = (s2 * sc) * g.dxy, exz = (s2 * sc) * g.dxz, eyz = s2 * g.dyz;
+  const float X[2] = {(1.0f - f[0]) * sc, f[0] * sc};
+  const float Y[2] = {1.0f - f[1], f[1]}, Z[2] = {1.0f - f[2], f[2]};
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int cx = k & 1, cy = (k >> 1) & 1, cz = k >> 2;
-    const float sxy = (cx == cy) ? 1.0f : -1.0f, sxz = (cx == cz) ? 1.0f : -1.0f,
-                syz = (cy == cz) ? 1.0f : -1.0f;
-    const float yz = Y[cy] * Z[cz];
-    float t = X[cx] * yz;
-    t = fmaf(sxy * exy, Z[cz], t);
-    t = fmaf(sxz * exz, Y[cy], t);
-    t = fmaf(syz * eyz, X[cx], t);
-    w[k] = t * sc;
+  for (int q = 0; q < 4; ++q) {
+    const int cy = q & 1, cz = q >> 1;
+    const float sy = cy ? -1.0f : 1.0f, sz = cz ? -1.0f : 1.0f;
+    const float P = fmaf(Y[cy], Z[cz], (sy * sz) * eyz);
+    const float Q = fmaf(sy * exy, Z[cz], (sz * exz) * Y[cy]);
+    w[2 * q] = fmaf(X[0], P, Q);
+    w[2 * q + 1] = fmaf(X[1], P, -Q);
   }
 }
 
