@@ -861,7 +861,8 @@ def main():
         props = torch.cuda.get_device_properties(0)
         res = {"device": props.name, "compute_units": props.multi_processor_count}
         for mode, name in ((0, "fma"), (1, "int_add"), (2, "fma_int_add"), (3, "fma_exp2"),
-                           (4, "mul_max"), (5, "shift_xor")):
+                           (4, "mul_max"), (5, "shift_xor"), (6, "fma_max"),
+                           (7, "mul_max_independent")):
             for blocks in (2048, 8192):
                 tops, ms = valu_probe(mode, blocks, 16000)
                 key = f"{name}_{blocks}wg"

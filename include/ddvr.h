@@ -552,11 +552,12 @@ void ddvr_plan_destroy(ddvr_plan* p);
  * rounds of 16 independent chains of one VALU operation each -- non-packed
  * float32 FMA (mode 0), 32-bit integer add (mode 1), the two alternating over
  * the chains (mode 2), FMA alternating with the hardware exp2 (mode 3), or
- * two instructions per chain: a float32 multiply then a max (mode 4), a shift
- * then an xor (mode 5) -- built with the library's own compiler flags.  out
- * [blocks*256] float32 (device) receives a checksum per lane; *lane_ops (host)
- * = blocks*256*iters*16 instructions (times 2 for modes 4 and 5).  Modes
- * outside 0..5: DDVR_ERR_VALUE. */
+ * two dependent instructions per chain: a float32 multiply then a max (mode
+ * 4), a shift then an xor (mode 5), an FMA then a max (mode 6); or multiplies
+ * and maxes on alternating chains (mode 7) -- built with the library's own
+ * compiler flags.  out [blocks*256] float32 (device) receives a checksum per
+ * lane; *lane_ops (host) = blocks*256*iters*16 instructions (times 2 for modes
+ * 4 to 6).  Modes outside 0..7: DDVR_ERR_VALUE. */
 int ddvr_valu_probe(int32_t mode, int32_t blocks, int32_t iters, float* out, int64_t* lane_ops,
                     void* hip_stream);
 

@@ -1313,15 +1313,15 @@ int ddvr_plan_loss_terms(const ddvr_plan* p, double* out, int32_t n, void* hip_s
 int ddvr_valu_probe(int32_t mode, int32_t blocks, int32_t iters, float* out, int64_t* lane_ops,
                     void* hip_stream) {
   if (!out || !lane_ops) return fail(DDVR_ERR_NULL, "out or lane_ops is NULL");
-  if (mode < 0 || mode > 5) return fail(DDVR_ERR_VALUE, "probe mode %d not in 0..5", mode);
+  if (mode < 0 || mode > 7) return fail(DDVR_ERR_VALUE, "probe mode %d not in 0..7", mode);
   if (blocks <= 0 || blocks > (1 << 20) || iters <= 0)
     return fail(DDVR_ERR_SHAPE, "probe of %d workgroups x %d rounds", blocks, iters);
   int rc;
   if ((rc = check_pending())) return rc;
   const hipError_t e = (hipError_t)launch_valu_probe(mode, blocks, iters, out, hip_stream);
   if (e != hipSuccess) return hip_fail(e, "probe launch");
-  // modes 4 and 5 run two instructions per chain and round
-  *lane_ops = (int64_t)blocks * 256 * iters * kProbeChains * (mode >= 4 ? 2 : 1);
+  // modes 4 to 6 run two instructions per chain and round
+  *lane_ops = (int64_t)blocks * 256 * iters * kProbeChains * (mode >= 4 && mode <= 6 ? 2 : 1);
   return DDVR_OK;
 }
 

@@ -353,7 +353,7 @@ def test_plan_probe_and_noalloc_reject_bad_arguments_before_launch():
     n = ctypes.c_int64(0)
     assert L.ddvr_batch_graph_builds(None, ctypes.byref(n)) == d.ERR_NULL
     buf = ctypes.c_void_p(16)                      # never dereferenced: rejected first
-    assert L.ddvr_valu_probe(6, 1, 1, buf, ctypes.byref(n), None) == d.ERR_VALUE
+    assert L.ddvr_valu_probe(8, 1, 1, buf, ctypes.byref(n), None) == d.ERR_VALUE
     assert L.ddvr_valu_probe(-1, 1, 1, buf, ctypes.byref(n), None) == d.ERR_VALUE
     assert L.ddvr_valu_probe(0, 0, 1, buf, ctypes.byref(n), None) == d.ERR_SHAPE
     assert L.ddvr_valu_probe(0, 1, 1, None, ctypes.byref(n), None) == d.ERR_NULL
