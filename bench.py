@@ -282,6 +282,11 @@ def secondary(args):
     out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "unit": "ray-samples/s"}
+    from paper_2107_12672_amd import autotune
+    old_tuning = d.get_tuning()
+    if args.workload in ("c1", "c2"):
+        key = (autotune.c1_key if args.workload == "c1" else autotune.c2_key)(_arch(torch))
+        out["tuning_source"] = "autotuned" if autotune.apply(key) else "default"
     if args.workload == "c1":
         # one small view: the launch and its synchronisation dominate
         w = synth.make_c1()
@@ -313,7 +318,8 @@ def secondary(args):
                     "value": S / (ms_graph * 1e-3), "ms_per_step": ms_graph,
                     "config": {"workload": w.name + ", fused L2, density gradient",
                                "samples_per_step": S, "single_call_ms": ms_single,
-                               "launch": "one fused launch, HIP graph replay"}})
+                               "launch": "one fused launch, HIP graph replay",
+                               "tuning": d.get_tuning()}})
     elif args.workload == "c5":
         res = inversion_c5(d, torch, args, stream)
         out.update({"metric": "fwd+adjoint ray-samples/s (fused forward + L2 + adjoint)",
@@ -685,6 +691,7 @@ def secondary(args):
                                          "of all views, adjoint, fallback in one HIP graph",
                                "samples_per_step": S, "tuning": d.get_tuning(),
                                "tuning_source": "autotuned" if tuned else "default"}})
+    d.set_tuning(**old_tuning)
     print(json.dumps(out), flush=True)
 
 

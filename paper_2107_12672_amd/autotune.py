@@ -166,6 +166,29 @@ def uneven_candidates() -> List[dict]:
     return out
 
 
+def small_candidates() -> List[dict]:
+    """Launch shapes of single small views (a few hundred tiles or fewer), where
+    smaller tiles spread the work over more CUs."""
+    out = []
+    for waves, cap, k, lm, ax in itertools.product((1, 2, 4), (2048, 4096, 7168), (16, 64),
+                                                   (0, 2), (0, 1)):
+        out.append({"waves": waves, "lds_cap": cap, "slab_k": k, "slab_kmax": 256,
+                    "cell_acc": 1, "lane_map": lm, "schedule": 0, "slab_axis": ax})
+    return out
+
+
+def c1_key(arch: str) -> str:
+    """Absorption-only 32^3 f32, one 64^2 view, fused pass (density gradient)."""
+    return workload_key(arch, _d.ABSORPTION, "f32", 0, 64, 32, "V", _d.PASS_FUSED)
+
+
+def c2_key(arch: str) -> str:
+    """Emission-absorption 128^3 f32, R=16, one 256^2 view, fused pass with
+    density, TF, camera and step gradients."""
+    return workload_key(arch, _d.EMISSION_ABSORPTION, "f32", 16, 256, 128, "V+TF+cam+step",
+                        _d.PASS_FUSED)
+
+
 def color_candidates() -> List[dict]:
     """The colour kernel takes 16x16 tiles and one item per workgroup; only its
     brick capacity (lds_cap / 4 vertices of 4 channels) is free."""
@@ -181,6 +204,9 @@ def _device_arch() -> str:
 
 def main(argv=None) -> None:
     """Tune a workload class and store the result in the cache:
+      c1     absorption-only 32^3 f32, one 64x64 view, fused pass;
+      c2     emission-absorption 128^3 f32, R=16, one 256x256 view, fused pass with
+             density, TF, camera and step gradients;
       c3     absorption-only tomography (256^3 bf16, 64 views at 512x512, fused pass);
       c4     the uneven batch (16 grids of mixed size and storage, one view each,
              minus the opacity entropy, camera + step gradients, one step plan);
@@ -191,7 +217,7 @@ def main(argv=None) -> None:
     import sys
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5", "color"))
+    ap.add_argument("--workload", default="c3", choices=("c1", "c2", "c3", "c4", "c5", "color"))
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--image", type=int, default=512)
@@ -204,6 +230,44 @@ def main(argv=None) -> None:
     import numpy as np
     import synth
     dev = torch.device("cuda:0")
+    if args.workload in ("c1", "c2"):
+        w = synth.make_c1() if args.workload == "c1" else synth.make_c2()
+        v = w.views[0]
+        vol = torch.from_numpy(np.ascontiguousarray(w.volume)).to(dev)
+        cam = _d.camera_from_sphere(math.radians(v.yaw), math.radians(v.pitch), v.dist,
+                                    math.radians(v.fovy), v.width, v.height)
+        ea = args.workload == "c2"
+        C = 4 if ea else 1
+        tf = torch.from_numpy(w.tf).to(dev) if ea else None
+        targets = torch.rand((v.height, v.width, C) if ea else (v.height, v.width), device=dev,
+                             generator=torch.Generator("cuda").manual_seed(1))
+        image = torch.empty_like(targets)
+        trans = torch.empty((v.height, v.width), device=dev)
+        dV = torch.zeros(w.volume.shape, device=dev)
+        dTF = torch.zeros_like(tf) if ea else None
+        dcam = torch.zeros(12, device=dev)
+        dstep = torch.zeros(1, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        scale = 1.0 / image.numel()
+        ws_ = {}
+
+        def make_s():
+            view = _d.make_view(0, cam, w.step_world, image, transmittance=trans, target=targets,
+                                d_camera=dcam if ea else None, d_step=dstep if ea else None,
+                                tf_index=0 if ea else -1)
+            b = _d.Batch([vol], [tf] if ea else None, [view],
+                         _d.EMISSION_ABSORPTION if ea else _d.ABSORPTION, d_volumes=[dV],
+                         d_tfs=[dTF] if ea else None)
+            ws_["ws"] = torch.zeros(max(b.workspace_size(), 4) // 4, dtype=torch.int32,
+                                    device=dev)
+            return b
+
+        key = c2_key(_device_arch()) if ea else c1_key(_device_arch())
+        res = tune(key, make_s, lambda b: b.run(_d.PASS_FUSED, scale, loss, workspace=ws_["ws"]),
+                   lambda: image, candidates=small_candidates(), reps=max(args.reps, 20),
+                   verbose=True)
+        print(json.dumps({"key": key, "best": res["tuning"], "ms": res["ms"]}))
+        return
     if args.workload == "c4":
         ws_ = synth.make_c4()
         vols, tfs, imgs, views = [], [], [], []
