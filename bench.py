@@ -21,7 +21,7 @@ atomics).
 from __future__ import annotations
 
 import argparse
-import hashlib
+
 import json
 import math
 import os
@@ -55,12 +55,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def kernel_source_hash(sources=None) -> str:
+    """Hash of the kernels' code, comments ignored: the key of committed
+    counters (they go stale with any change to the code)."""
+    from paper_2107_12672_amd import isa_count
+    return isa_count.source_hash(sources or KERNEL_SOURCES)
 
 
 def measured_traffic():
@@ -500,20 +499,17 @@ def secondary(args):
                 vc = json.load(f)
         except (OSError, ValueError):
             vc = None
-        h = hashlib.sha256()
-        for rel in ("paper_2107_12672_amd/csrc/ddvr_dfc.hip",
-                    "paper_2107_12672_amd/csrc/ddvr_internal.h"):
-            with open(os.path.join(ROOT, rel), "rb") as f:
-                h.update(f.read())
+        dfc_sha = kernel_source_hash(["paper_2107_12672_amd/csrc/ddvr_dfc.hip",
+                                      "paper_2107_12672_amd/csrc/ddvr_internal.h"])
         tr = None
         try:
             with open(os.path.join(ROOT, "profiles", "traffic_dfc.json")) as f:
                 t = json.load(f)
-            if t.get("kernel_source_sha") == h.hexdigest()[:16]:
+            if t.get("kernel_source_sha") == dfc_sha:
                 tr = t.get("bytes_per_launch")
         except (OSError, ValueError):
             pass
-        if vc and vc.get("kernel_source_sha") == h.hexdigest()[:16]:
+        if vc and vc.get("kernel_source_sha") == dfc_sha:
             ops = nvox * ncand * vc["valu_per_candidate"]
             a = ops / (ms * 1e-3) / 1e12
             peak = valu_ceiling() or VALU_PUBLISHED_TOPS

@@ -7,8 +7,10 @@
 //   * one ray per lane; a wave owns an 8x8 pixel block, a workgroup owns a
 //     tile of WAVES such blocks (16x16 pixels for 4 waves);
 //   * the tile marches slab-synchronously: its rays' samples are grouped into
-//     slabs of K samples at the same distance from the eye; for every slab the
-//     workgroup computes the bounding box of the grid cells its samples touch,
+//     slabs between planes of the grid axis closest to the tile's centre ray
+//     (shells of constant distance from the eye where that cannot be used);
+//     for every slab the workgroup computes the bounding box of the grid
+//     cells its samples touch,
 //     stages that brick of the density grid into LDS (converted to float32)
 //     and, in the adjoint, accumulates the density gradient of the slab in an
 //     LDS brick of fixed-point integers (ds_add_u32; ds_add_u64 for
@@ -21,6 +23,8 @@
 //     in registers while the ray stays on one TF segment and flushed to an
 //     LDS table on segment change (Sec. 5.2 "adjoint-delayed"), then to global
 //     memory once per workgroup;
+//   * absorption-only marches sum the samples of a ray inside one cell in
+//     closed form (cell runs), forward and closed-form adjoint alike;
 //   * camera and step-size gradients stay in registers per ray and are reduced
 //     over the workgroup before one atomic per value;
 //   * blockIdx is remapped so that each XCD (own L2) gets a contiguous range

@@ -38,11 +38,40 @@ FWD = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi0ELb0EEEvNS_12LaunchParamsE"
 FUSED = "_ZN4ddvr8k_renderILi0ELi2ELi4ELi2ELb0EEEvNS_12LaunchParamsE"
 
 
+def strip_comments(text: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed to one space
+    (string and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(sources=None) -> str:
+    """Hash of the code of the kernel sources (comments and layout ignored):
+    the key under which measured counters and counts of these kernels are
+    stored, so that they stay valid across comment edits and go stale with
+    any change to the code."""
     h = hashlib.sha256()
     for rel in (sources or KERNEL_SOURCES):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(strip_comments(f.read()).encode())
     return h.hexdigest()[:16]
 
 
