@@ -322,6 +322,30 @@ void attach_fallback(LaunchParams& p, const FbLayout& L, void* ws, int flags) {
   p.fb_slot_floats = L.slot_floats;
 }
 
+// The fallback's LDS table for the TF gradient: used when every view that
+// wants a TF gradient writes the same dTF, of one size of at most
+// kFallbackTabR entries (16 KB of LDS per workgroup).
+constexpr int kFallbackTabR = 1024;
+void fallback_tf_table(LaunchParams& p, const ViewDesc* views, size_t n, int model) {
+  p.fb_dtf = nullptr;
+  p.fb_tf_R = 0;
+  if (model != DDVR_EMISSION_ABSORPTION || !(p.grad_mask & GRAD_TF)) return;
+  float* dtf = nullptr;
+  int R = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (!views[i].dTF) continue;
+    if (!dtf) {
+      dtf = views[i].dTF;
+      R = views[i].R;
+    } else if (views[i].dTF != dtf || views[i].R != R) {
+      return;
+    }
+  }
+  if (!dtf || R > kFallbackTabR) return;
+  p.fb_dtf = dtf;
+  p.fb_tf_R = R;
+}
+
 int read_fallback_count(const LaunchParams& p, hipStream_t s, int32_t* out) {
   if (!out) return DDVR_OK;
   if (!p.fb_count) { *out = 0; return DDVR_OK; }
@@ -400,7 +424,10 @@ int run_single(int pass, const ddvr_volume* vol, const ddvr_tf* tf, const ddvr_c
   p.slab_axis = g_tuning.slab_axis;
   p.loss_scale = loss_scale;
   p.loss_out = pass == PASS_FUSED ? loss_out : nullptr;
-  if (fb) attach_fallback(p, L, ws, flags);
+  if (fb) {
+    attach_fallback(p, L, ws, flags);
+    fallback_tf_table(p, &p.one, 1, model);
+  }
 
   hipError_t e;
   if (model == DDVR_COLOR) {
@@ -1102,7 +1129,10 @@ static int batch_enqueue(ddvr_batch* b, int pass, float loss_scale, double* loss
   p.n_items = b->n_items;
   p.xcd_remap = b->persistent ? 0 : 1;
   p.queue = b->persistent ? b->d_queue : nullptr;
-  if (fb) attach_fallback(p, L, ws, b->flags);
+  if (fb) {
+    attach_fallback(p, L, ws, b->flags);
+    fallback_tf_table(p, b->views.data(), b->views.size(), b->model);
+  }
   const size_t lds = lds_bytes(p.lds_cap, p.lds_two, b->model, b->max_R);
   {
     const int rc = check_lds(lds);

@@ -64,6 +64,9 @@ struct LaunchParams {
   float* fb_scratch;      // per-slot scratch for checkpointing
   int32_t fb_slots;       // number of concurrent checkpoint slots
   int32_t fb_slot_floats; // floats per slot
+  float* fb_dtf;          // TF gradient every fallback ray that wants one writes (null: none
+                          // or several; then each ray adds to its view's dTF directly)
+  int32_t fb_tf_R;        // entries of that TF
 };
 
 // Forward-mode (tangent) launch: derivatives of the image along up to

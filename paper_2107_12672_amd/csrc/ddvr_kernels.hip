@@ -1896,103 +1896,133 @@ __global__ __launch_bounds__(256) void k_tangent(const TangentParams p) {
 // ---------------------------------------------------------------------------
 // segment-checkpoint fallback (one ray per thread, queued by the main kernel)
 // ---------------------------------------------------------------------------
+// One queued ray.  TAB: the ray's TF gradient goes to the workgroup's LDS
+// table `tab` (its view's dTF is the launch's fb_dtf), which the kernel adds
+// to global memory once per workgroup; without it every TF-segment change of
+// every ray would be a global atomic on the same few hundred floats.
+template <int MODEL, int DT, int FUSED, bool TAB>
+__device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code, float* ws,
+                                             float* tab) {
+  constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
+  const int view = (int)(code >> 32);
+  const int64_t pix = code & 0xFFFFFFFFll;
+  const ViewDesc vd = p.views ? p.views[view] : p.one;
+  int gmask = p.grad_mask;
+  if (!vd.dV) gmask &= ~GRAD_V;
+  if (!vd.dTF) gmask &= ~GRAD_TF;
+  if (!vd.dcam) gmask &= ~GRAD_CAM;
+  if (!vd.dstep) gmask &= ~GRAD_STEP;
+  float* const dtf = TAB ? tab : vd.dTF;
+  const int px = (int)(pix % vd.W), py = (int)(pix / vd.W);
+  RayG r;
+  setup_ray(vd, px, py, true, r);
+  if (r.N <= 0) return;
+  const int C = EA ? 4 : 1;
+  float gimg[4];
+  for (int ch = 0; ch < C; ++ch) {
+    float unused = 0.0f;
+    if (FUSED)
+      gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale,
+                           vd.image[pix * C + ch] - vd.target[pix * C + ch], unused);
+    else gimg[ch] = vd.d_image[pix * C + ch];
+  }
+  const float4* tfl = reinterpret_cast<const float4*>(vd.tf);
+  const int N = r.N;
+  int K = (int)ceilf(sqrtf((float)N));
+  while (K * K < N) ++K;
+  const int nseg = (N + K - 1) / K;
+  float* ck = ws;             // T at the start of every segment
+  float* tseg = ws + nseg;    // T^(i) inside the current segment
+  // forward: keep T at segment starts
+  {
+    float T = 1.0f;
+    for (int i = 0; i < N; ++i) {
+      if (i % K == 0) ck[i / K] = T;
+      Cell c;
+      locate(r, (float)i, vd, c);
+      float v[8];
+      fetch_global<DT>(vd, c, v);
+      const float d = trilerp(v, c.f);
+      float tau = d;
+      if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
+      T *= __expf(-vd.step * tau);
+    }
+  }
+  AdjState s;
+  s.Chat[0] = EA ? gimg[0] : 0.0f;
+  s.Chat[1] = EA ? gimg[1] : 0.0f;
+  s.Chat[2] = EA ? gimg[2] : 0.0f;
+  s.ahat = EA ? gimg[3] : gimg[0];
+  s.Tn = 0.0f; s.an = 0.0f; s.P = 0.0f;
+  s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0;
+  s.si[0] = s.si[1] = s.si[2] = 0.0;
+  s.dstep = 0.0;
+  s.tj = -1;
+  for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
+  s.ckey = -1;
+  s.gkey = -1;
+  s.qs = 1.0f;
+  s.dh = 0.0f; s.dhq = 0.0f;
+  for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
+  Brick br{};
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int i0 = sg * K, i1 = min(N, i0 + K);
+    tseg[0] = ck[sg];
+    for (int i = i0; i < i1; ++i) {
+      Cell c;
+      locate(r, (float)i, vd, c);
+      float v[8];
+      fetch_global<DT>(vd, c, v);
+      const float d = trilerp(v, c.f);
+      float tau = d;
+      if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
+      tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
+    }
+    // density gradient kept per cell in registers, one global atomic per
+    // corner when the ray leaves the cell
+    for (int i = i1 - 1; i >= i0; --i)
+      adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, dtf,
+                                            gmask, true, true, s, tseg[i - i0]);
+  }
+  cell_flush<false, false>(vd, br, nullptr, s);
+  if (EA && (gmask & GRAD_TF)) tf_flush(s, dtf);
+  if (gmask & (GRAD_CAM | GRAD_STEP)) {
+    float cg[13];
+    camera_adjoint(vd, r, s, true, cg);
+    if (gmask & GRAD_CAM)
+      for (int k = 0; k < 12; ++k) gadd(vd.dcam + k, cg[k]);
+    if (gmask & GRAD_STEP) gadd(vd.dstep, cg[12]);
+  }
+}
+
 template <int MODEL, int DT, int FUSED>
 __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
-  constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
+  extern __shared__ __align__(16) float fb_tab[];
+  // the LDS TF table (emission-absorption, set by the host when every view
+  // that wants a TF gradient writes the same dTF of fb_tf_R entries)
+  const bool tab = MODEL == DDVR_EMISSION_ABSORPTION && p.fb_dtf != nullptr;
+  const int nt = 4 * p.fb_tf_R;
+  if (tab) {
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) fb_tab[i] = 0.0f;
+    __syncthreads();
+  }
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= p.fb_slots) return;
-  float* ws = p.fb_scratch + (int64_t)slot * p.fb_slot_floats;
-  const int64_t count = min((int64_t)*p.fb_count, p.fb_cap);
-  const int64_t stride = (int64_t)p.fb_slots;
-  for (int64_t q = slot; q < count; q += stride) {
-    const int64_t code = p.fb_list[q];
-    const int view = (int)(code >> 32);
-    const int64_t pix = code & 0xFFFFFFFFll;
-    const ViewDesc vd = p.views ? p.views[view] : p.one;
-    int gmask = p.grad_mask;
-    if (!vd.dV) gmask &= ~GRAD_V;
-    if (!vd.dTF) gmask &= ~GRAD_TF;
-    if (!vd.dcam) gmask &= ~GRAD_CAM;
-    if (!vd.dstep) gmask &= ~GRAD_STEP;
-    const int px = (int)(pix % vd.W), py = (int)(pix / vd.W);
-    RayG r;
-    setup_ray(vd, px, py, true, r);
-    if (r.N <= 0) continue;
-    const int C = EA ? 4 : 1;
-    float gimg[4];
-    for (int ch = 0; ch < C; ++ch) {
-      float unused = 0.0f;
-      if (FUSED)
-        gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale,
-                             vd.image[pix * C + ch] - vd.target[pix * C + ch], unused);
-      else gimg[ch] = vd.d_image[pix * C + ch];
-    }
-    const float4* tfl = reinterpret_cast<const float4*>(vd.tf);
-    const int N = r.N;
-    int K = (int)ceilf(sqrtf((float)N));
-    while (K * K < N) ++K;
-    const int nseg = (N + K - 1) / K;
-    float* ck = ws;             // T at the start of every segment
-    float* tseg = ws + nseg;    // T^(i) inside the current segment
-    // forward: keep T at segment starts
-    {
-      float T = 1.0f;
-      for (int i = 0; i < N; ++i) {
-        if (i % K == 0) ck[i / K] = T;
-        Cell c;
-        locate(r, (float)i, vd, c);
-        float v[8];
-        fetch_global<DT>(vd, c, v);
-        const float d = trilerp(v, c.f);
-        float tau = d;
-        if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
-        T *= __expf(-vd.step * tau);
-      }
-    }
-    AdjState s;
-    s.Chat[0] = EA ? gimg[0] : 0.0f;
-    s.Chat[1] = EA ? gimg[1] : 0.0f;
-    s.Chat[2] = EA ? gimg[2] : 0.0f;
-    s.ahat = EA ? gimg[3] : gimg[0];
-    s.Tn = 0.0f; s.an = 0.0f; s.P = 0.0f;
-    s.xo_hat[0] = s.xo_hat[1] = s.xo_hat[2] = 0.0;
-    s.si[0] = s.si[1] = s.si[2] = 0.0;
-    s.dstep = 0.0;
-    s.tj = -1;
-    for (int ch = 0; ch < 4; ++ch) { s.tg0[ch] = 0.0f; s.tg1[ch] = 0.0f; }
-    s.ckey = -1;
-    s.gkey = -1;
-    s.qs = 1.0f;
-    s.dh = 0.0f; s.dhq = 0.0f;
-    for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
-    Brick br{};
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      const int i0 = sg * K, i1 = min(N, i0 + K);
-      tseg[0] = ck[sg];
-      for (int i = i0; i < i1; ++i) {
-        Cell c;
-        locate(r, (float)i, vd, c);
-        float v[8];
-        fetch_global<DT>(vd, c, v);
-        const float d = trilerp(v, c.f);
-        float tau = d;
-        if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
-        tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
-      }
-      // density gradient kept per cell in registers, one global atomic per
-      // corner when the ray leaves the cell
-      for (int i = i1 - 1; i >= i0; --i)
-        adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, vd.dTF,
-                                              gmask, true, true, s, tseg[i - i0]);
-    }
-    cell_flush<false, false>(vd, br, nullptr, s);
-    if (EA && (gmask & GRAD_TF)) tf_flush(s, vd.dTF);
-    if (gmask & (GRAD_CAM | GRAD_STEP)) {
-      float cg[13];
-      camera_adjoint(vd, r, s, true, cg);
-      if (gmask & GRAD_CAM)
-        for (int k = 0; k < 12; ++k) gadd(vd.dcam + k, cg[k]);
-      if (gmask & GRAD_STEP) gadd(vd.dstep, cg[12]);
+  if (slot < p.fb_slots) {
+    float* ws = p.fb_scratch + (int64_t)slot * p.fb_slot_floats;
+    const int64_t count = min((int64_t)*p.fb_count, p.fb_cap);
+    const int64_t stride = (int64_t)p.fb_slots;
+    if (tab)
+      for (int64_t q = slot; q < count; q += stride)
+        fallback_ray<MODEL, DT, FUSED, true>(p, p.fb_list[q], ws, fb_tab);
+    else
+      for (int64_t q = slot; q < count; q += stride)
+        fallback_ray<MODEL, DT, FUSED, false>(p, p.fb_list[q], ws, nullptr);
+  }
+  if (tab) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+      const float g = fb_tab[i];
+      if (g != 0.0f) gadd(p.fb_dtf + i, g);
     }
   }
 }
@@ -3033,8 +3063,9 @@ int launch_render(const LaunchParams& p, int pass, int model, int dtype, int wav
 
 template <int MODEL, int DT>
 static hipError_t launch_fb2(const LaunchParams& p, int fused, int blocks, hipStream_t s) {
-  if (fused) hipLaunchKernelGGL((k_fallback<MODEL, DT, 1>), dim3(blocks), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL((k_fallback<MODEL, DT, 0>), dim3(blocks), dim3(256), 0, s, p);
+  const size_t lds = p.fb_dtf ? (size_t)p.fb_tf_R * 4 * sizeof(float) : 0;
+  if (fused) hipLaunchKernelGGL((k_fallback<MODEL, DT, 1>), dim3(blocks), dim3(256), lds, s, p);
+  else hipLaunchKernelGGL((k_fallback<MODEL, DT, 0>), dim3(blocks), dim3(256), lds, s, p);
   return hipGetLastError();
 }
 
