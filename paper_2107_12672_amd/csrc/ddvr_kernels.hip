@@ -1022,7 +1022,8 @@ __device__ __forceinline__ void tf_flush(AdjState& s, float* dtf) {
 
 // Adjoint of one sample i given T^(i) source.  `mode` selects how T^(i) is
 // recovered: 0 closed form (AO), 1 T-form inversion, 2 alpha-form inversion,
-// 3 caller supplies Ti (checkpoint).
+// 3 caller supplies Ti (checkpoint), 4 the same with the density gradient in
+// a float32 LDS brick.
 template <int MODEL, int DT, bool LDS, int MODE, bool XH>
 __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, float fi,
                                            const float* stage, float* acc, const Brick& br,
@@ -1030,9 +1031,11 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
                                            bool need_v, bool cell_acc, AdjState& s,
                                            float Ti_given) {
   // the closed form and the inversions accumulate the LDS brick in fixed
-  // point, 64-bit for emission-absorption (its scale bound is looser)
+  // point, 64-bit for emission-absorption (its scale bound is looser); the
+  // checkpoint fallback's wave bricks (MODE 4) in float32, with the grid
+  // gathered from global memory
   constexpr bool FIX = LDS && MODE <= 2;
-  constexpr bool WIDE = MODEL == DDVR_EMISSION_ABSORPTION;
+  constexpr bool WIDE = MODEL == DDVR_EMISSION_ABSORPTION && MODE <= 2;
   Cell c;
   locate(r, fi, vd, c);
   // XH: camera or step gradients are compiled in (their float64 ray sums cost
@@ -1043,7 +1046,7 @@ __device__ __forceinline__ void adj_sample(const ViewDesc& vd, const RayG& r, fl
   int base = 0;
   if (LDS) base = brick_base(br, c);
   if (need_v) {
-    if (LDS) fetch_lds(stage, br, base, v);
+    if (LDS && MODE != 4) fetch_lds(stage, br, base, v);
     else fetch_global<DT>(vd, c, v);
     d = trilerp(v, c.f);
   }
@@ -1896,16 +1899,30 @@ __global__ __launch_bounds__(256) void k_tangent(const TangentParams p) {
 // ---------------------------------------------------------------------------
 // segment-checkpoint fallback (one ray per thread, queued by the main kernel)
 // ---------------------------------------------------------------------------
-// One queued ray.  TAB: the ray's TF gradient goes to the workgroup's LDS
-// table `tab` (its view's dTF is the launch's fb_dtf), which the kernel adds
-// to global memory once per workgroup; without it every TF-segment change of
-// every ray would be a global atomic on the same few hundred floats.
+// One queued ray per lane; all lanes of the wave call it together (`live`:
+// the lane holds a ray).  TAB: the ray's TF gradient goes to the workgroup's
+// LDS table `tab` (its view's dTF is the launch's fb_dtf), which the kernel
+// adds to global memory once per workgroup; without it every TF-segment
+// change of every ray would be a global atomic on the same few hundred
+// floats.
+//
+// Segments: the wave splits sample indices into segments of K =
+// ceil(sqrt(N_max)) samples (N_max: the wave's longest ray), so that its
+// lanes march the same segment at a time.  The forward keeps T at every
+// segment start; the adjoint re-marches a segment forward for its T^(i) (the
+// same float32 products in the same order as the first pass) and then runs it
+// back to front, in windows of sample indices.  When the wave's rays write
+// one gradient grid and the cells a window touches fit the wave's LDS region
+// `wacc`, the window's density gradient is accumulated there (float32 LDS
+// atomics at each cell exit) and added to global memory once per touched
+// voxel; otherwise every cell exit adds its 8 corners to global memory.
 template <int MODEL, int DT, int FUSED, bool TAB>
-__device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code, float* ws,
-                                             float* tab) {
+__device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code, bool live,
+                                             float* ws, float* tab, float* wacc) {
   constexpr bool EA = MODEL == DDVR_EMISSION_ABSORPTION;
-  const int view = (int)(code >> 32);
-  const int64_t pix = code & 0xFFFFFFFFll;
+  const int lane = threadIdx.x & 63;
+  const int view = live ? (int)(code >> 32) : 0;
+  const int64_t pix = live ? (code & 0xFFFFFFFFll) : 0;
   const ViewDesc vd = p.views ? p.views[view] : p.one;
   int gmask = p.grad_mask;
   if (!vd.dV) gmask &= ~GRAD_V;
@@ -1915,22 +1932,25 @@ __device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code
   float* const dtf = TAB ? tab : vd.dTF;
   const int px = (int)(pix % vd.W), py = (int)(pix / vd.W);
   RayG r;
-  setup_ray(vd, px, py, true, r);
-  if (r.N <= 0) return;
+  setup_ray(vd, px, py, live, r);
+  const int N = live ? max(r.N, 0) : 0;
+  const int Nw = wave_max_i32(N);
+  if (Nw <= 0) return;
   const int C = EA ? 4 : 1;
-  float gimg[4];
-  for (int ch = 0; ch < C; ++ch) {
-    float unused = 0.0f;
-    if (FUSED)
-      gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale,
-                           vd.image[pix * C + ch] - vd.target[pix * C + ch], unused);
-    else gimg[ch] = vd.d_image[pix * C + ch];
+  float gimg[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (N > 0) {
+    for (int ch = 0; ch < C; ++ch) {
+      float unused = 0.0f;
+      if (FUSED)
+        gimg[ch] = loss_seed((p.flags & DDVR_LOSS_L1) != 0, p.loss_scale,
+                             vd.image[pix * C + ch] - vd.target[pix * C + ch], unused);
+      else gimg[ch] = vd.d_image[pix * C + ch];
+    }
   }
   const float4* tfl = reinterpret_cast<const float4*>(vd.tf);
-  const int N = r.N;
-  int K = (int)ceilf(sqrtf((float)N));
-  while (K * K < N) ++K;
-  const int nseg = (N + K - 1) / K;
+  int K = (int)ceilf(sqrtf((float)Nw));
+  while (K * K < Nw) ++K;
+  const int nseg = (Nw + K - 1) / K;
   float* ck = ws;             // T at the start of every segment
   float* tseg = ws + nseg;    // T^(i) inside the current segment
   // forward: keep T at segment starts
@@ -1964,27 +1984,83 @@ __device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code
   s.qs = 1.0f;
   s.dh = 0.0f; s.dhq = 0.0f;
   for (int k = 0; k < 8; ++k) s.cg[k] = 0.0f;
-  Brick br{};
+  // the wave's bricks need one gradient grid: that of its first lane with
+  // samples, written by every lane with samples
+  const uint64_t has = __builtin_amdgcn_ballot_w64(N > 0);
+  const int first = __builtin_ctzll(has);
+  const uint64_t dvp = reinterpret_cast<uint64_t>(vd.dV);
+  const uint64_t dv0 =
+      ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(dvp >> 32), first) << 32) |
+      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)dvp, first);
+  const int nx0 = __builtin_amdgcn_readlane(vd.nx, first);
+  const int ny0 = __builtin_amdgcn_readlane(vd.ny, first);
+  float* const g0 = reinterpret_cast<float*>(dv0);
+  const bool bricks =
+      wacc != nullptr && g0 != nullptr &&
+      __builtin_amdgcn_ballot_w64(N > 0 && (dvp != dv0 || vd.nx != nx0 || vd.ny != ny0)) == 0;
   for (int sg = nseg - 1; sg >= 0; --sg) {
-    const int i0 = sg * K, i1 = min(N, i0 + K);
-    tseg[0] = ck[sg];
-    for (int i = i0; i < i1; ++i) {
-      Cell c;
-      locate(r, (float)i, vd, c);
-      float v[8];
-      fetch_global<DT>(vd, c, v);
-      const float d = trilerp(v, c.f);
-      float tau = d;
-      if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
-      tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
+    const int i0 = sg * K, i1 = min(N, i0 + K);   // i1 <= i0: no samples here
+    if (i0 < i1) {
+      tseg[0] = ck[sg];
+      for (int i = i0; i < i1; ++i) {
+        Cell c;
+        locate(r, (float)i, vd, c);
+        float v[8];
+        fetch_global<DT>(vd, c, v);
+        const float d = trilerp(v, c.f);
+        float tau = d;
+        if (EA) { TFv t; tf_eval(tfl, vd.R, d, t); tau = t.tau; }
+        tseg[i - i0 + 1] = tseg[i - i0] * __expf(-vd.step * tau);
+      }
     }
-    // density gradient kept per cell in registers, one global atomic per
-    // corner when the ray leaves the cell
-    for (int i = i1 - 1; i >= i0; --i)
-      adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, dtf,
-                                            gmask, true, true, s, tseg[i - i0]);
+    // the segment back to front in windows of m sample indices (the same
+    // indices in every lane), m halved until the window's brick fits and
+    // doubled again after a window that used under a quarter of it
+    int m = K;
+    for (int e = min(Nw, i0 + K); e > i0;) {
+      int lo, a, b, st;
+      Brick br{};
+      for (;;) {
+        lo = max(i0, e - m);
+        a = lo;
+        b = min(e, i1);
+        if (!bricks) { st = 2; break; }
+        if (!range_brick<64>(vd, r, a, b, nullptr, br)) { st = 0; break; }
+        if (br.size <= kFallbackBrick) { st = 1; break; }
+        if (m <= 4) { st = 2; break; }
+        m >>= 1;
+      }
+      if (st == 1) {
+        for (int x = lane; x < br.size; x += 64) wacc[x] = 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int i = b - 1; i >= a; --i)
+          adj_sample<MODEL, DT, true, 4, true>(vd, r, (float)i, nullptr, wacc, br, tfl, dtf,
+                                               gmask, true, true, s, tseg[i - i0]);
+        cell_flush<true, false>(vd, br, wacc, s);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int64_t sy = nx0, sz = (int64_t)nx0 * ny0;
+        float* const org = g0 + (br.z0 * sz + br.y0 * sy + br.x0);
+        const bool narrow = brick_narrow(br, sz);
+        for (int x = lane; x < br.size; x += 64) {
+          const float g = wacc[x];
+          if (g != 0.0f)
+            gadd(org + (narrow ? brick_goff<true>(br, x, sy, sz) : brick_goff<false>(br, x, sy, sz)),
+                 g);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (4 * br.size < kFallbackBrick) m = min(2 * m, K);
+      } else if (st == 2) {
+        // density gradient kept per cell in registers, one global atomic per
+        // corner when the ray leaves the cell (or the window)
+        for (int i = b - 1; i >= a; --i)
+          adj_sample<MODEL, DT, false, 3, true>(vd, r, (float)i, nullptr, nullptr, br, tfl, dtf,
+                                                gmask, true, true, s, tseg[i - i0]);
+        cell_flush<false, false>(vd, br, nullptr, s);
+      }
+      e = lo;
+    }
   }
-  cell_flush<false, false>(vd, br, nullptr, s);
+  if (N <= 0) return;
   if (EA && (gmask & GRAD_TF)) tf_flush(s, dtf);
   if (gmask & (GRAD_CAM | GRAD_STEP)) {
     float cg[13];
@@ -1997,31 +2073,35 @@ __device__ __forceinline__ void fallback_ray(const LaunchParams& p, int64_t code
 
 template <int MODEL, int DT, int FUSED>
 __global__ __launch_bounds__(256) void k_fallback(const LaunchParams p) {
-  extern __shared__ __align__(16) float fb_tab[];
-  // the LDS TF table (emission-absorption, set by the host when every view
-  // that wants a TF gradient writes the same dTF of fb_tf_R entries)
+  extern __shared__ __align__(16) float fb_smem[];
+  // LDS: the TF table (emission-absorption, set by the host when every view
+  // that wants a TF gradient writes the same dTF of fb_tf_R entries), then
+  // one density brick region of kFallbackBrick floats per wave
   const bool tab = MODEL == DDVR_EMISSION_ABSORPTION && p.fb_dtf != nullptr;
-  const int nt = 4 * p.fb_tf_R;
+  const int nt = tab ? 4 * p.fb_tf_R : 0;
+  float* const wacc = fb_smem + nt + (threadIdx.x >> 6) * kFallbackBrick;
   if (tab) {
-    for (int i = threadIdx.x; i < nt; i += blockDim.x) fb_tab[i] = 0.0f;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) fb_smem[i] = 0.0f;
     __syncthreads();
   }
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot < p.fb_slots) {
-    float* ws = p.fb_scratch + (int64_t)slot * p.fb_slot_floats;
-    const int64_t count = min((int64_t)*p.fb_count, p.fb_cap);
-    const int64_t stride = (int64_t)p.fb_slots;
-    if (tab)
-      for (int64_t q = slot; q < count; q += stride)
-        fallback_ray<MODEL, DT, FUSED, true>(p, p.fb_list[q], ws, fb_tab);
-    else
-      for (int64_t q = slot; q < count; q += stride)
-        fallback_ray<MODEL, DT, FUSED, false>(p, p.fb_list[q], ws, nullptr);
+  const int lane = threadIdx.x & 63;
+  float* ws = p.fb_scratch + (int64_t)slot * p.fb_slot_floats;   // (used by live lanes only)
+  const int64_t count = min((int64_t)*p.fb_count, p.fb_cap);
+  const int64_t stride = (int64_t)p.fb_slots;
+  // the lanes of a wave take consecutive queue entries, round after round
+  // (the wave's loop is uniform: lanes without a ray ride along)
+  for (int64_t q0 = (int64_t)(slot - lane); q0 < count; q0 += stride) {
+    const int64_t q = q0 + lane;
+    const bool live = slot < p.fb_slots && q < count;
+    const int64_t code = live ? p.fb_list[q] : 0;
+    if (tab) fallback_ray<MODEL, DT, FUSED, true>(p, code, live, ws, fb_smem, wacc);
+    else fallback_ray<MODEL, DT, FUSED, false>(p, code, live, ws, nullptr, wacc);
   }
   if (tab) {
     __syncthreads();
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-      const float g = fb_tab[i];
+      const float g = fb_smem[i];
       if (g != 0.0f) gadd(p.fb_dtf + i, g);
     }
   }
@@ -3063,7 +3143,8 @@ int launch_render(const LaunchParams& p, int pass, int model, int dtype, int wav
 
 template <int MODEL, int DT>
 static hipError_t launch_fb2(const LaunchParams& p, int fused, int blocks, hipStream_t s) {
-  const size_t lds = p.fb_dtf ? (size_t)p.fb_tf_R * 4 * sizeof(float) : 0;
+  const size_t lds = ((p.fb_dtf ? (size_t)p.fb_tf_R * 4 : 0) + 4 * (size_t)kFallbackBrick) *
+                     sizeof(float);
   if (fused) hipLaunchKernelGGL((k_fallback<MODEL, DT, 1>), dim3(blocks), dim3(256), lds, s, p);
   else hipLaunchKernelGGL((k_fallback<MODEL, DT, 0>), dim3(blocks), dim3(256), lds, s, p);
   return hipGetLastError();
