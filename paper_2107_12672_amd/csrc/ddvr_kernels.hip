@@ -27,6 +27,10 @@
 //     closed form (cell runs), forward and closed-form adjoint alike;
 //   * camera and step-size gradients stay in registers per ray and are reduced
 //     over the workgroup before one atomic per value;
+//   * rays too opaque for the inversion go to a segment-checkpoint kernel that
+//     marches one ray per lane in wave-uniform segments, with the density
+//     gradient in per-wave LDS bricks and the TF gradient in a per-workgroup
+//     LDS table;
 //   * blockIdx is remapped so that each XCD (own L2) gets a contiguous range
 //     of tiles.
 #include <hip/hip_runtime.h>
