@@ -323,6 +323,59 @@ def test_checkpoint_for_every_ray_in_lds_bricks_and_global_windows(W, H, n):
     assert_grad_close([got["dstep"]], [ref["dstep"]], "checkpoint dstep")
 
 
+def test_checkpoint_batch_of_two_grids_and_three_tfs():
+    # CHECKPOINT on an uneven batch (two grids, f16 and f32, three views with
+    # their own TFs and ragged image sizes): the checkpoint kernel's waves take
+    # queued rays of different views, so where a wave's rays write different
+    # gradient grids the density gradient goes out by per-cell global atomics,
+    # and with three TF gradients there is no shared LDS table.  Every
+    # gradient matches the sum of the oracle's per-view stored-tape adjoints.
+    import torch
+    from paper_2107_12672_amd import ddvr as d
+    from harness import device_volume, gpu_camera
+    probs = [ea_problem(W=40, H=24, seed=71, storage="f16"),
+             ea_problem(W=72, H=56, seed=72, yaw=200.0),
+             ea_problem(W=33, H=47, seed=71, yaw=-40.0, pitch=30.0, storage="f16")]
+    probs[2].volume = probs[0].volume
+    vidx = [0, 1, 0]
+    _say("checkpoint batch, two grids, three TFs")
+    rng = np.random.default_rng(17)
+    seeds, refs = [], []
+    for p in probs:
+        ora = oracle_forward(p)
+        g = rng.normal(size=ora["image"].shape) / ora["image"].size
+        g[tie_mask(ora["ratio"]) | kink_mask(p)] = 0.0
+        seeds.append(g)
+        refs.append(oracle_adjoint(p, g))
+    vols = [device_volume(probs[0]), device_volume(probs[1])]
+    tfs = [torch.from_numpy(p.tf).cuda() for p in probs]
+    n = len(probs)
+    imgs = [torch.zeros(p.H * p.W * 4, device="cuda") for p in probs]
+    trs = [torch.zeros(p.H * p.W, device="cuda") for p in probs]
+    gs = [torch.from_numpy(np.ascontiguousarray(g, dtype=np.float32).ravel()).cuda() for g in seeds]
+    dcam = torch.zeros((n, 12), device="cuda")
+    dstep = torch.zeros(n, device="cuda")
+    dvs = [torch.zeros(v.shape, device="cuda") for v in vols]
+    dtfs = [torch.zeros_like(t) for t in tfs]
+    views = [d.make_view(vidx[k], gpu_camera(p), p.step, imgs[k], transmittance=trs[k],
+                         d_image=gs[k], d_camera=dcam[k], d_step=dstep[k:k + 1], tf_index=k)
+             for k, p in enumerate(probs)]
+    b = d.Batch(vols, tfs, views, d.EMISSION_ABSORPTION, flags=d.ADJ_CHECKPOINT, d_volumes=dvs,
+                d_tfs=dtfs)
+    ws = torch.zeros(b.workspace_size() // 4 + 1, dtype=torch.int32, device="cuda")
+    b.run(d.PASS_FORWARD)
+    b.run(d.PASS_ADJOINT, workspace=ws)
+    torch.cuda.synchronize()
+    b.close()
+    assert_dv_close(dvs[0].cpu().numpy(), refs[0]["dV"] + refs[2]["dV"], "batch grid 0 dV")
+    assert_dv_close(dvs[1].cpu().numpy(), refs[1]["dV"], "batch grid 1 dV")
+    for k in range(n):
+        assert_grad_close(dtfs[k].cpu().numpy(), refs[k]["dTF"], f"batch view {k} dTF")
+        assert_grad_close(dcam[k].cpu().numpy(), refs[k]["dcam"], f"batch view {k} dcam",
+                          floor_frac=5e-2)
+        assert_grad_close([dstep[k].item()], [refs[k]["dstep"]], f"batch view {k} dstep")
+
+
 def test_rays_that_miss_give_exact_zeros():
     p = ea_problem(W=32, H=24)
     p.yaw, p.pitch, p.fovy = 10.0, 10.0, 120.0
