@@ -143,6 +143,6 @@ constexpr int kDtypeDynamic = 3;        // storage type chosen per view; persist
 constexpr int kMaxSamples = 1 << 22;    // per-ray sample cap (validated on the host)
 constexpr float kFallbackTmin = 7.888609052210118e-31f;   // 2^-100 (T-form inversion)
 constexpr float kFallbackTminAlpha = 9.765625e-4f;         // 2^-10 (alpha-form inversion)
-constexpr int kFallbackBrick = 3072;   // floats of LDS per wave for the fallback's segment bricks
+constexpr int kFallbackBrick = 4096;   // floats of LDS per wave for the fallback's segment bricks
 
 }  // namespace ddvr
